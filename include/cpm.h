@@ -1,0 +1,176 @@
+/*
+ * cpm.h - C ABI of the MI355X (gfx950) Schwarz-preconditioned closest point
+ * method solver.
+ *
+ * Problem (May, Haynes, Ruuth, "Schwarz solvers and preconditioners for the
+ * closest point method", arXiv:1909.08734, Section 1): the surface positive
+ * Helmholtz equation (c - Delta_S) u = f, c > 0, discretised by the closest
+ * point method with the stabilised operator of Section 2.1
+ *     A = c I - Delta_S^h,  Delta_S^h = -(6/h^2) I + (Delta^h + (6/h^2) [I 0]) E,
+ * and solved by GMRES preconditioned with restricted additive Schwarz (RAS,
+ * Dirichlet transmission rows, Section 5.1) or optimized RAS (ORAS, Robin
+ * rows of eq. robfo, Section 5.2, with the cross-point weight of Section 5.2.2):
+ *     M^{-1} = sum_j R~_j^T A_j^{-1} R_j        (eq. algRAS).
+ *
+ * Call order (state machine): cpm_create -> cpm_build_band -> cpm_build_operator
+ * -> cpm_partition -> cpm_factor -> cpm_solve*. A new operator or partition
+ * invalidates the factors (cpm_factor must run again). Calls out of order
+ * return CPM_ESTATE; a failed call leaves the previous state intact unless
+ * stated otherwise.
+ *
+ * Vectors: length N_A (number of active band nodes), float64, in band order
+ * (active nodes sorted by linear grid index L = (i n1 + j) n2 + k).
+ * Pointers named *_dev are device pointers on the context's device, used on
+ * the context's stream; all other pointers are host pointers. Every call is
+ * synchronous (returns after the device work it issued has finished) unless
+ * stated otherwise. Ownership: the context owns all device memory it
+ * allocates; caller buffers are only borrowed for the duration of a call.
+ *
+ * Errors: 0 on success, negative CPM_E* on failure, CPM_ENOTCONV (> 0) as a
+ * warning from the solve. cpm_last_error() describes the most recent failure.
+ * No C++ exception crosses this boundary.
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpm_ctx cpm_ctx;
+
+enum {
+  CPM_OK = 0,
+  CPM_ENOTCONV = 1,    /* solve hit max_iter; u holds the last iterate */
+  CPM_EINVAL = -1,     /* invalid argument (message says which) */
+  CPM_ESTATE = -2,     /* call out of order */
+  CPM_ENOMEM = -3,     /* host or device allocation failed */
+  CPM_ESINGULAR = -4,  /* exactly zero pivot in a local LU */
+  CPM_EDEVICE = -5,    /* HIP runtime error, or no device (host-only context) */
+  CPM_ECALLBACK = -6   /* the closest-point callback returned non-zero */
+};
+
+enum { CPM_RAS = 0, CPM_ORAS = 1 };                 /* transmission condition */
+enum { CPM_FP64 = 0, CPM_FP32 = 1 };                /* local factor precision */
+enum { CPM_PART_OCTANT = 0, CPM_PART_RCB = 1 };     /* disjoint partition */
+
+/*
+ * Closest-point callback (the surface representation CP_S of Section 2.1).
+ * x: n query points, row-major n x 3. Writes cp (n x 3) = closest points and
+ * nrm (n x 3) = unit surface normals at those points. A non-finite cp marks a
+ * point whose closest point is undefined (treated as outside every band).
+ * Returns 0 on success. Must give the same value for a point however the
+ * queries are batched. Called from the thread that called cpm_build_band.
+ */
+typedef int (*cpm_cp_fn)(void* user, int64_t n, const double* x, double* cp, double* nrm);
+
+typedef struct {
+  int32_t iters;        /* total GMRES iterations (preconditioner applications) */
+  int32_t cycles;       /* restart cycles */
+  int32_t status;       /* CPM_OK or CPM_ENOTCONV */
+  int32_t reserved;
+  double relres_true;   /* ||f - A u||_2 / ||f||_2 at exit, computed on the device */
+  double relres_est;    /* GMRES residual estimate / ||f||_2 at exit */
+  double ms;            /* wall time of the solve on the device stream */
+} cpm_solve_info;
+
+/* Create a context on HIP device `device` (>= 0). device < 0 gives a
+ * host-only context: set-up and queries work, factor/solve return
+ * CPM_EDEVICE. The context creates and owns one HIP stream. */
+int cpm_create(cpm_ctx** out, int device);
+void cpm_destroy(cpm_ctx* ctx);
+const char* cpm_last_error(const cpm_ctx* ctx);
+
+/*
+ * Band (Section 2.1): grid lo + (i,j,k) h covering the box [lo, hi]
+ * (n_a = floor((hi_a - lo_a)/h + 1/2) + 1 nodes per axis), active nodes
+ * = nodes within rho h of their closest point (tube-radius construction,
+ * rho = band_factor, or sqrt(3)(degree+1)/2 when band_factor <= 0), closed
+ * so that every interpolation stencil is active; ghost nodes complete the
+ * 7-point stencils. Extension rows interpolate with tensor-product Lagrange
+ * polynomials of `degree` (2 or 3) at CP(x) (Figure 1). EINVAL if h <= 0,
+ * the degree is unsupported, or a ghost or stencil node leaves the box.
+ */
+int cpm_build_band(cpm_ctx* ctx, cpm_cp_fn fn, void* user, const double lo[3],
+                   const double hi[3], double h, int degree, double band_factor);
+
+/* Operator A = c I - Delta_S^h (Section 2.1). EINVAL if c <= 0 or not finite. */
+int cpm_build_operator(cpm_ctx* ctx, double c);
+
+/*
+ * Overlapping decomposition (Sections 3, 4, 5).
+ * method: CPM_PART_OCTANT (n_sub must be 8) or CPM_PART_RCB (recursive
+ *   coordinate bisection into n_sub parts; weights = n_sub target weights for
+ *   weighted bisection, or NULL).
+ * overlap: N_O >= 0 layers (>= 1 for ORAS).
+ * kind: CPM_RAS or CPM_ORAS; alpha: Robin weight (ORAS, > 0);
+ * alpha_cross: weight for boundary nodes within 2 N_O h of a cross point
+ *   (Section 5.2.2); 0 disables the modification.
+ */
+int cpm_partition(cpm_ctx* ctx, int method, int n_sub, const double* weights, int overlap,
+                  int kind, double alpha, double alpha_cross);
+
+/*
+ * Local operators A_j (eq. localOP) assembled on the device and factored by
+ * batched dense LU with partial pivoting (Section 5) in `prec`; the factors
+ * are reduced to the restricted local solution operators
+ * W_j = R~_j A_j^{-1} R_j^T (rows Sigma~_j, columns Sigma_j) kept resident.
+ * ESINGULAR if a pivot is exactly zero; ENOMEM if the device memory is short.
+ */
+int cpm_factor(cpm_ctx* ctx, int prec);
+
+/*
+ * Solve A u = f for nrhs right-hand sides (column-major N_A x nrhs, host
+ * pointers) with restarted right-preconditioned FGMRES(restart), x0 = 0,
+ * until ||f - A u|| <= tol ||f|| (true residual). info may be NULL (else
+ * nrhs entries). EINVAL for tol <= 0, max_iter < 1, restart < 1 or > 64,
+ * or a non-finite f. Returns CPM_ENOTCONV if some RHS hit max_iter.
+ */
+int cpm_solve(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, int max_iter,
+              int restart, cpm_solve_info* info);
+/* Same with device pointers (inputs resident in HBM). */
+int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs, double tol,
+                     int max_iter, int restart, cpm_solve_info* info);
+
+/* Single applications on device vectors, for checking and profiling.
+ * y = A x (Section 2.1);  z = M^{-1} v (eq. algRAS) after cpm_factor. */
+int cpm_apply_operator(cpm_ctx* ctx, const double* x_dev, double* y_dev);
+int cpm_apply_precond(cpm_ctx* ctx, const double* v_dev, double* z_dev);
+
+/* ---- queries (host copies of the set-up; any pointer may be NULL) ---- */
+int cpm_band_sizes(const cpm_ctx* ctx, int64_t* n_act, int64_t* n_ghost, int64_t shape[3]);
+/* lin: N_T linear indices (actives then ghosts); cp, nrm: N_T x 3; nbr: N_A x 6
+ * band indices (x-,x+,y-,y+,z-,z+); base: N_T x 3 first stencil node per axis;
+ * wts: N_T x 3 x (degree+1) one-dimensional weights. */
+int cpm_band_arrays(const cpm_ctx* ctx, int64_t* lin, double* cp, double* nrm, int32_t* nbr,
+                    int32_t* base, double* wts);
+int cpm_partition_info(const cpm_ctx* ctx, int* n_sub, int32_t* part, uint8_t* cross);
+/* sizes[5] = |Sigma~_j|, |Sigma_j|, |F_j|, |Sigma_j^G|, |B_j| */
+int cpm_subdomain_sizes(const cpm_ctx* ctx, int j, int64_t sizes[5]);
+/* sorted band indices of each set; xstar, s, alpha are per B node (ORAS). */
+int cpm_subdomain_sets(const cpm_ctx* ctx, int j, int32_t* tilde, int32_t* sigma, int32_t* fin,
+                       int32_t* ghost, int32_t* bnd, int32_t* xstar, double* s, double* alpha);
+/* W_j (|Sigma~_j| x |Sigma_j|, row-major) copied to host as float64. */
+int cpm_factor_export(cpm_ctx* ctx, int j, double* w);
+/* Device bytes held for the band, operator, factors and Krylov workspace. */
+size_t cpm_footprint_bytes(const cpm_ctx* ctx);
+
+/* Per-kernel timing with HIP events on the context stream (off by default).
+ * which: 0 = preconditioner apply, 1 = extension apply, 2 = stencil apply,
+ * 3 = LU trailing update. total_ms and launches since the last reset. */
+int cpm_set_timing(cpm_ctx* ctx, int on);
+int cpm_kernel_time(cpm_ctx* ctx, int which, double* total_ms, int64_t* launches);
+
+/* Diagnostic: run the matrix-core tile of the LU trailing update once on
+ * device `device`: c (64x64, row-major, in/out) -= a (64 x kb, row stride 32)
+ * * b (kb x 64, row-major), kb <= 32, in `prec` (CPM_FP64 or CPM_FP32; values
+ * are rounded to float for CPM_FP32). Host pointers. */
+int cpm_selftest_tile(int device, int prec, const double* a, const double* b, double* c, int kb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPM_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) Schwarz-preconditioned GMRES for the closest point method.
+
+The solver lives in the HIP/C++ shared library ``libcpm.so`` (C ABI in
+``include/cpm.h``); this package is its thin Python binding.
+"""
+
+from .binding import (  # noqa: F401
+    Context, CpmError, SolveInfo, lib, selftest_tile, EXPORTED,
+    OK, ENOTCONV, EINVAL, ESTATE, ENOMEM, ESINGULAR, EDEVICE, ECALLBACK,
+    RAS, ORAS, FP64, FP32, PART_OCTANT, PART_RCB,
+    TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM,
+)

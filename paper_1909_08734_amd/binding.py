@@ -1,0 +1,280 @@
+"""ctypes binding of the C ABI in include/cpm.h (argument marshalling only).
+
+Every computation runs in the shared library ``libcpm.so`` built for gfx950;
+importing this module fails loudly when the library has not been built.
+PyTorch is used only to hand device buffers (``torch.Tensor`` on a HIP
+device) to the library.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpm.so")
+
+OK, ENOTCONV, EINVAL, ESTATE, ENOMEM, ESINGULAR, EDEVICE, ECALLBACK = 0, 1, -1, -2, -3, -4, -5, -6
+RAS, ORAS = 0, 1
+FP64, FP32 = 0, 1
+PART_OCTANT, PART_RCB = 0, 1
+TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM = 0, 1, 2, 3
+
+_NAMES = {OK: "OK", ENOTCONV: "ENOTCONV", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM",
+          ESINGULAR: "ESINGULAR", EDEVICE: "EDEVICE", ECALLBACK: "ECALLBACK"}
+
+CP_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                    C.POINTER(C.c_double))
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("relres_true", C.c_double), ("relres_est", C.c_double),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class CpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_SIGS = {
+    "cpm_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "cpm_destroy": (None, [C.c_void_p]),
+    "cpm_last_error": (C.c_char_p, [C.c_void_p]),
+    "cpm_build_band": (C.c_int, [C.c_void_p, CP_FN, C.c_void_p, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_double, C.c_int, C.c_double]),
+    "cpm_build_operator": (C.c_int, [C.c_void_p, C.c_double]),
+    "cpm_partition": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int,
+                                C.c_double, C.c_double]),
+    "cpm_factor": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int,
+                            C.POINTER(SolveInfo)]),
+    "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
+                                   C.c_int, C.POINTER(SolveInfo)]),
+    "cpm_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cpm_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cpm_band_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64)]),
+    "cpm_band_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
+    "cpm_partition_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p]),
+    "cpm_subdomain_sizes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
+    "cpm_subdomain_sets": (C.c_int, [C.c_void_p, C.c_int] + [C.c_void_p] * 8),
+    "cpm_factor_export": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "cpm_footprint_bytes": (C.c_size_t, [C.c_void_p]),
+    "cpm_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_kernel_time": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "cpm_selftest_tile": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libcpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1909_08734_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t, dtype="float64"):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a torch tensor on a HIP device")
+    if str(t.dtype) != f"torch.{dtype}" or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _sync_torch():
+    import torch
+    torch.cuda.synchronize()
+
+
+def selftest_tile(a, b, c, prec=FP64, device=0):
+    """c - a @ b on one 64x64 matrix-core tile of the LU trailing update (returns new c)."""
+    kb = a.shape[1]
+    A = np.zeros((64, 32))
+    A[:, :kb] = a
+    B = np.zeros((32, 64))
+    B[:kb] = b
+    Cm = np.ascontiguousarray(c, dtype=np.float64).copy()
+    rc = lib().cpm_selftest_tile(device, prec, _ptr(A), _ptr(B), _ptr(Cm), kb)
+    if rc != 0:
+        raise CpmError(rc, "selftest_tile failed")
+    return Cm
+
+
+class Context:
+    """One solver context (owns device memory and a HIP stream)."""
+
+    def __init__(self, device: int = 0):
+        self._L = lib()
+        h = C.c_void_p()
+        rc = self._L.cpm_create(C.byref(h), int(device))
+        if rc != 0:
+            raise CpmError(rc, f"cpm_create(device={device}) failed")
+        self._h = h
+        self._cb = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.cpm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = self._L.cpm_last_error(self._h)
+            raise CpmError(rc, f"{what}: {msg.decode() if msg else ''}")
+        return rc
+
+    # ---- the five calls of the method -------------------------------------------
+    def build_band(self, surface, h, degree=3, lo=(-2.0, -2.0, -2.0), hi=(2.0, 2.0, 2.0),
+                   band_factor=0.0):
+        def cb(user, n, x, cp, nrm):
+            try:
+                X = np.ctypeslib.as_array(x, shape=(n, 3))
+                c, nr = surface.cp(X)
+                np.ctypeslib.as_array(cp, shape=(n, 3))[:] = c
+                np.ctypeslib.as_array(nrm, shape=(n, 3))[:] = nr
+                return 0
+            except Exception:  # reported as ECALLBACK
+                return 1
+        self._cb = CP_FN(cb)
+        lo_a = (C.c_double * 3)(*lo)
+        hi_a = (C.c_double * 3)(*hi)
+        self._check(self._L.cpm_build_band(self._h, self._cb, None, lo_a, hi_a, float(h), int(degree),
+                                           float(band_factor)), "build_band")
+
+    def build_operator(self, c):
+        self._check(self._L.cpm_build_operator(self._h, float(c)), "build_operator")
+
+    def partition(self, method=PART_RCB, n_sub=8, weights=None, overlap=2, kind=RAS, alpha=0.0,
+                  alpha_cross=0.0):
+        w = None
+        if weights is not None:
+            w = np.ascontiguousarray(weights, dtype=np.float64)
+            wp = w.ctypes.data_as(C.POINTER(C.c_double))
+        else:
+            wp = None
+        self._check(self._L.cpm_partition(self._h, int(method), int(n_sub), wp, int(overlap), int(kind),
+                                          float(alpha), float(alpha_cross)), "partition")
+
+    def factor(self, prec=FP64):
+        self._check(self._L.cpm_factor(self._h, int(prec)), "factor")
+
+    def solve(self, f, tol=1e-8, max_iter=1000, restart=30):
+        """Host arrays: f (N_A,) or (nrhs, N_A). Returns (u, [info dicts])."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        nrhs = 1 if f.ndim == 1 else f.shape[0]
+        u = np.zeros_like(f)
+        info = (SolveInfo * max(nrhs, 1))()
+        rc = self._check(self._L.cpm_solve(self._h, _ptr(f), _ptr(u), nrhs, float(tol), int(max_iter),
+                                           int(restart), info), "solve")
+        return u, [info[q].as_dict() for q in range(nrhs)], rc
+
+    def solve_device(self, f, u, tol=1e-8, max_iter=1000, restart=30):
+        """torch float64 HIP tensors f, u of N_A x nrhs (column-major = (nrhs, N_A) row-major)."""
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+        info = (SolveInfo * max(nrhs, 1))()
+        _sync_torch()
+        rc = self._check(self._L.cpm_solve_device(self._h, _dev_ptr(f), _dev_ptr(u), nrhs, float(tol),
+                                                  int(max_iter), int(restart), info), "solve_device")
+        return [info[q].as_dict() for q in range(nrhs)], rc
+
+    def apply_operator(self, x, y):
+        _sync_torch()
+        self._check(self._L.cpm_apply_operator(self._h, _dev_ptr(x), _dev_ptr(y)), "apply_operator")
+
+    def apply_precond(self, v, z):
+        _sync_torch()
+        self._check(self._L.cpm_apply_precond(self._h, _dev_ptr(v), _dev_ptr(z)), "apply_precond")
+
+    # ---- queries --------------------------------------------------------------------
+    def band_sizes(self):
+        na, ng = C.c_int64(), C.c_int64()
+        shape = (C.c_int64 * 3)()
+        self._check(self._L.cpm_band_sizes(self._h, C.byref(na), C.byref(ng), shape), "band_sizes")
+        return na.value, ng.value, tuple(shape)
+
+    def band_arrays(self, degree=3):
+        na, ng, _ = self.band_sizes()
+        nt = na + ng
+        lin = np.empty(nt, dtype=np.int64)
+        cp = np.empty((nt, 3))
+        nrm = np.empty((nt, 3))
+        nbr = np.empty((na, 6), dtype=np.int32)
+        base = np.empty((nt, 3), dtype=np.int32)
+        wts = np.empty((nt, 3, degree + 1))
+        self._check(self._L.cpm_band_arrays(self._h, _ptr(lin), _ptr(cp), _ptr(nrm), _ptr(nbr), _ptr(base),
+                                            _ptr(wts)), "band_arrays")
+        return {"lin": lin, "cp": cp, "nrm": nrm, "nbr": nbr, "base": base, "wts": wts}
+
+    def partition_info(self):
+        na, _, _ = self.band_sizes()
+        n = C.c_int()
+        part = np.empty(na, dtype=np.int32)
+        cross = np.empty(na, dtype=np.uint8)
+        self._check(self._L.cpm_partition_info(self._h, C.byref(n), _ptr(part), _ptr(cross)), "partition_info")
+        return n.value, part, cross.astype(bool)
+
+    def subdomain(self, j):
+        sz = (C.c_int64 * 5)()
+        self._check(self._L.cpm_subdomain_sizes(self._h, int(j), sz), "subdomain_sizes")
+        nt, ns, nf, ng, nb = list(sz)
+        out = {"tilde": np.empty(nt, np.int32), "sigma": np.empty(ns, np.int32), "final": np.empty(nf, np.int32),
+               "ghost": np.empty(ng, np.int32), "bnd": np.empty(nb, np.int32), "xstar": np.empty(nb, np.int32),
+               "s": np.empty(nb), "alpha": np.empty(nb)}
+        self._check(self._L.cpm_subdomain_sets(self._h, int(j), *[_ptr(out[k]) for k in
+                                                                   ("tilde", "sigma", "final", "ghost", "bnd",
+                                                                    "xstar", "s", "alpha")]), "subdomain_sets")
+        return out
+
+    def factor_export(self, j):
+        s = self.subdomain(j)
+        w = np.empty((len(s["tilde"]), len(s["sigma"])))
+        self._check(self._L.cpm_factor_export(self._h, int(j), _ptr(w)), "factor_export")
+        return w
+
+    def footprint_bytes(self):
+        return int(self._L.cpm_footprint_bytes(self._h))
+
+    def set_timing(self, on=True):
+        self._check(self._L.cpm_set_timing(self._h, 1 if on else 0), "set_timing")
+
+    def kernel_time(self, which):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self._L.cpm_kernel_time(self._h, int(which), C.byref(ms), C.byref(n)), "kernel_time")
+        return ms.value, n.value

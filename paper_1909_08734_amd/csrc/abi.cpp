@@ -1,0 +1,312 @@
+// C ABI of the CPM Schwarz solver: argument checks, call-order state machine,
+// error reporting and host queries. Device work lives in device.hip.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "cpm_internal.h"
+
+namespace {
+
+const char* kNull = "null context";
+
+int fail(cpm_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+template <class F>
+int guarded(cpm_ctx* ctx, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, CPM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(ctx, CPM_EINVAL, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(ctx, CPM_EINVAL, "internal error");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int cpm_create(cpm_ctx** out, int device) {
+  if (!out) return CPM_EINVAL;
+  *out = nullptr;
+  cpm_ctx* ctx = new (std::nothrow) cpm_ctx();
+  if (!ctx) return CPM_ENOMEM;
+  if (device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+      delete ctx;
+      return CPM_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return CPM_EDEVICE;
+    }
+    ctx->device = device;
+    ctx->host_only = false;
+  }
+  *out = ctx;
+  return CPM_OK;
+}
+
+void cpm_destroy(cpm_ctx* ctx) {
+  if (!ctx) return;
+  if (!ctx->host_only) {
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    cpm::dev_free_all(ctx);
+    for (hipEvent_t e : ctx->timer.pool) hipEventDestroy(e);
+    hipStreamDestroy(ctx->stream);
+  }
+  delete ctx;
+}
+
+const char* cpm_last_error(const cpm_ctx* ctx) { return ctx ? ctx->err.c_str() : kNull; }
+
+int cpm_build_band(cpm_ctx* ctx, cpm_cp_fn fn, void* user, const double lo[3], const double hi[3],
+                   double h, int degree, double band_factor) {
+  if (!ctx) return CPM_EINVAL;
+  if (!lo || !hi) return fail(ctx, CPM_EINVAL, "build_band: null box");
+  return guarded(ctx, [&]() -> int {
+    cpm::Band b;
+    int rc = cpm::build_band(b, fn, user, lo, hi, h, degree, band_factor, ctx->err);
+    if (rc != CPM_OK) return rc;
+    if (!ctx->host_only) cpm::dev_free_all(ctx);
+    ctx->band = std::move(b);
+    ctx->dec = cpm::Decomp();
+    ctx->state = 1;
+    if (!ctx->host_only) {
+      rc = cpm::dev_upload_operator(ctx);
+      if (rc != CPM_OK) {
+        ctx->state = 0;
+        return rc;
+      }
+    }
+    return CPM_OK;
+  });
+}
+
+int cpm_build_operator(cpm_ctx* ctx, double c) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 1) return fail(ctx, CPM_ESTATE, "build_operator: build the band first");
+  if (!(c > 0) || !std::isfinite(c)) return fail(ctx, CPM_EINVAL, "build_operator: c must be positive and finite");
+  if (!ctx->host_only) cpm::dev_free_factor(ctx);
+  ctx->c = c;
+  ctx->state = ctx->dec.n_sub > 0 ? 3 : 2;
+  return CPM_OK;
+}
+
+int cpm_partition(cpm_ctx* ctx, int method, int n_sub, const double* weights, int overlap, int kind,
+                  double alpha, double alpha_cross) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 2) return fail(ctx, CPM_ESTATE, "partition: build the operator first");
+  return guarded(ctx, [&]() -> int {
+    cpm::Decomp d;
+    int rc = cpm::build_decomposition(ctx->band, d, method, n_sub, weights, overlap, kind, alpha,
+                                      alpha_cross, ctx->err);
+    if (rc != CPM_OK) return rc;
+    if (!ctx->host_only) cpm::dev_free_factor(ctx);
+    ctx->dec = std::move(d);
+    ctx->state = 3;
+    return CPM_OK;
+  });
+}
+
+int cpm_factor(cpm_ctx* ctx, int prec) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 3) return fail(ctx, CPM_ESTATE, "factor: partition first");
+  if (prec != CPM_FP64 && prec != CPM_FP32) return fail(ctx, CPM_EINVAL, "factor: precision must be FP64 or FP32");
+  if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "factor: host-only context");
+  return guarded(ctx, [&]() -> int {
+    int rc = cpm::dev_factor(ctx, prec);
+    ctx->state = rc == CPM_OK ? 4 : 3;
+    return rc;
+  });
+}
+
+// f and u are device pointers (N_A x nrhs, column-major).
+static int solve_common(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, int max_iter,
+                        int restart, cpm_solve_info* info) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "solve: factor first");
+  if (!f || !u) return fail(ctx, CPM_EINVAL, "solve: null vector");
+  if (nrhs < 0) return fail(ctx, CPM_EINVAL, "solve: nrhs < 0");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, CPM_EINVAL, "solve: tol must be positive");
+  if (max_iter < 1) return fail(ctx, CPM_EINVAL, "solve: max_iter must be >= 1");
+  if (restart < 1 || restart > 64) return fail(ctx, CPM_EINVAL, "solve: restart must be in [1, 64]");
+  return guarded(ctx, [&]() -> int {
+    const int64_t na = ctx->band.n_act;
+    int worst = CPM_OK;
+    for (int q = 0; q < nrhs; ++q) {
+      cpm_solve_info tmp{};
+      int rc = cpm::dev_solve(ctx, f + (size_t)q * na, u + (size_t)q * na, tol, max_iter, restart, &tmp);
+      if (info) info[q] = tmp;
+      if (rc < 0) return rc;
+      if (rc > worst) worst = rc;
+    }
+    return worst;
+  });
+}
+
+int cpm_solve(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, int max_iter, int restart,
+              cpm_solve_info* info) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "solve: factor first");
+  if (!f || !u) return fail(ctx, CPM_EINVAL, "solve: null vector");
+  // Host vectors: stage through device buffers, one RHS at a time.
+  const int64_t na = ctx->band.n_act;
+  return guarded(ctx, [&]() -> int {
+    double *df = nullptr, *du = nullptr;
+    if (hipMalloc(&df, na * sizeof(double)) != hipSuccess) return fail(ctx, CPM_ENOMEM, "solve: device allocation failed");
+    if (hipMalloc(&du, na * sizeof(double)) != hipSuccess) {
+      hipFree(df);
+      return fail(ctx, CPM_ENOMEM, "solve: device allocation failed");
+    }
+    int worst = CPM_OK;
+    for (int q = 0; q < nrhs; ++q) {
+      hipMemcpyAsync(df, f + (size_t)q * na, na * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+      cpm_solve_info tmp{};
+      int rc = solve_common(ctx, df, du, 1, tol, max_iter, restart, &tmp);
+      if (rc >= 0) {
+        hipMemcpyAsync(u + (size_t)q * na, du, na * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        hipStreamSynchronize(ctx->stream);
+      }
+      if (info) info[q] = tmp;
+      if (rc < 0) {
+        hipFree(df);
+        hipFree(du);
+        return rc;
+      }
+      if (rc > worst) worst = rc;
+    }
+    hipFree(df);
+    hipFree(du);
+    return worst;
+  });
+}
+
+int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs, double tol, int max_iter,
+                     int restart, cpm_solve_info* info) {
+  return solve_common(ctx, f_dev, u_dev, nrhs, tol, max_iter, restart, info);
+}
+
+int cpm_apply_operator(cpm_ctx* ctx, const double* x_dev, double* y_dev) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 2) return fail(ctx, CPM_ESTATE, "apply_operator: build the operator first");
+  if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "apply_operator: host-only context");
+  if (!x_dev || !y_dev) return fail(ctx, CPM_EINVAL, "apply_operator: null vector");
+  return cpm::dev_apply_operator(ctx, x_dev, y_dev);
+}
+
+int cpm_apply_precond(cpm_ctx* ctx, const double* v_dev, double* z_dev) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "apply_precond: factor first");
+  if (!v_dev || !z_dev) return fail(ctx, CPM_EINVAL, "apply_precond: null vector");
+  return cpm::dev_apply_precond(ctx, v_dev, z_dev);
+}
+
+int cpm_band_sizes(const cpm_ctx* ctx, int64_t* n_act, int64_t* n_ghost, int64_t shape[3]) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 1) return CPM_ESTATE;
+  if (n_act) *n_act = ctx->band.n_act;
+  if (n_ghost) *n_ghost = ctx->band.n_ghost;
+  if (shape)
+    for (int a = 0; a < 3; ++a) shape[a] = ctx->band.n[a];
+  return CPM_OK;
+}
+
+int cpm_band_arrays(const cpm_ctx* ctx, int64_t* lin, double* cp, double* nrm, int32_t* nbr, int32_t* base,
+                    double* wts) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 1) return CPM_ESTATE;
+  const cpm::Band& b = ctx->band;
+  if (lin) std::memcpy(lin, b.lin.data(), b.lin.size() * sizeof(int64_t));
+  if (cp) std::memcpy(cp, b.cp.data(), b.cp.size() * sizeof(double));
+  if (nrm) std::memcpy(nrm, b.nrm.data(), b.nrm.size() * sizeof(double));
+  if (nbr) std::memcpy(nbr, b.nbr.data(), b.nbr.size() * sizeof(int32_t));
+  if (base) std::memcpy(base, b.base.data(), b.base.size() * sizeof(int32_t));
+  if (wts) std::memcpy(wts, b.wts.data(), b.wts.size() * sizeof(double));
+  return CPM_OK;
+}
+
+int cpm_partition_info(const cpm_ctx* ctx, int* n_sub, int32_t* part, uint8_t* cross) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 3) return CPM_ESTATE;
+  if (n_sub) *n_sub = ctx->dec.n_sub;
+  if (part) std::memcpy(part, ctx->dec.part.data(), ctx->dec.part.size() * sizeof(int32_t));
+  if (cross) std::memcpy(cross, ctx->dec.cross.data(), ctx->dec.cross.size());
+  return CPM_OK;
+}
+
+int cpm_subdomain_sizes(const cpm_ctx* ctx, int j, int64_t sizes[5]) {
+  if (!ctx || !sizes) return CPM_EINVAL;
+  if (ctx->state < 3) return CPM_ESTATE;
+  if (j < 0 || j >= ctx->dec.n_sub) return CPM_EINVAL;
+  const cpm::Sub& s = ctx->dec.subs[j];
+  sizes[0] = (int64_t)s.tilde.size();
+  sizes[1] = (int64_t)s.sigma.size();
+  sizes[2] = (int64_t)s.fin.size();
+  sizes[3] = (int64_t)s.ghost.size();
+  sizes[4] = (int64_t)s.bnd.size();
+  return CPM_OK;
+}
+
+int cpm_subdomain_sets(const cpm_ctx* ctx, int j, int32_t* tilde, int32_t* sigma, int32_t* fin,
+                       int32_t* ghost, int32_t* bnd, int32_t* xstar, double* s, double* alpha) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 3) return CPM_ESTATE;
+  if (j < 0 || j >= ctx->dec.n_sub) return CPM_EINVAL;
+  const cpm::Sub& d = ctx->dec.subs[j];
+  auto cp32 = [](int32_t* dst, const std::vector<int32_t>& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(int32_t));
+  };
+  cp32(tilde, d.tilde);
+  cp32(sigma, d.sigma);
+  cp32(fin, d.fin);
+  cp32(ghost, d.ghost);
+  cp32(bnd, d.bnd);
+  cp32(xstar, d.xstar);
+  if (s && !d.s.empty()) std::memcpy(s, d.s.data(), d.s.size() * sizeof(double));
+  if (alpha && !d.alpha.empty()) std::memcpy(alpha, d.alpha.data(), d.alpha.size() * sizeof(double));
+  return CPM_OK;
+}
+
+int cpm_factor_export(cpm_ctx* ctx, int j, double* w) {
+  if (!ctx || !w) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "factor_export: factor first");
+  if (j < 0 || j >= ctx->dec.n_sub) return fail(ctx, CPM_EINVAL, "factor_export: bad subdomain");
+  return guarded(ctx, [&]() -> int { return cpm::dev_export_w(ctx, j, w); });
+}
+
+size_t cpm_footprint_bytes(const cpm_ctx* ctx) {
+  if (!ctx) return 0;
+  return ctx->dev.op_bytes + ctx->dev.w_bytes + ctx->dev.krylov_bytes;
+}
+
+int cpm_set_timing(cpm_ctx* ctx, int on) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "set_timing: host-only context");
+  cpm::timer_harvest(ctx);
+  ctx->timer.on = on != 0;
+  for (int q = 0; q < cpm::N_TIMERS; ++q) {
+    ctx->timer.ms[q] = 0;
+    ctx->timer.count[q] = 0;
+  }
+  return CPM_OK;
+}
+
+int cpm_kernel_time(cpm_ctx* ctx, int which, double* total_ms, int64_t* launches) {
+  if (!ctx) return CPM_EINVAL;
+  if (which < 0 || which >= cpm::N_TIMERS) return fail(ctx, CPM_EINVAL, "kernel_time: unknown kernel");
+  if (!ctx->host_only) cpm::timer_harvest(ctx);
+  if (total_ms) *total_ms = ctx->timer.ms[which];
+  if (launches) *launches = ctx->timer.count[which];
+  return CPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal declarations of the CPM Schwarz library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cpm.h"
+
+namespace cpm {
+
+// Band and extension data (Section 2.1). Band order: actives sorted by L, then ghosts.
+struct Band {
+  double lo[3] = {0, 0, 0};
+  double h = 0;
+  int p = 0;
+  int64_t n[3] = {0, 0, 0};
+  int64_t n_act = 0, n_ghost = 0;
+  std::vector<int64_t> lin;    // N_T linear indices
+  std::vector<int32_t> ijk;    // N_T x 3
+  std::vector<double> xyz;     // N_T x 3 node coordinates
+  std::vector<double> cp;      // N_T x 3 closest points
+  std::vector<double> nrm;     // N_T x 3 normals at the closest points
+  std::vector<int32_t> nbr;    // N_A x 6 band indices (x-,x+,y-,y+,z-,z+)
+  std::vector<int32_t> base;   // N_T x 3 first stencil node per axis
+  std::vector<double> wts;     // N_T x 3 x (p+1) one-dimensional weights
+  std::vector<int32_t> lines;  // N_T x (p+1)^2 band index of each stencil z-line's first node
+  int64_t total() const { return n_act + n_ghost; }
+};
+
+struct Sub {
+  std::vector<int32_t> tilde, sigma, fin, ghost, bnd, xstar;
+  std::vector<double> s, alpha;
+};
+
+struct Decomp {
+  int n_sub = 0, kind = CPM_RAS, overlap = 0;
+  double alpha = 0, alpha_cross = 0;
+  std::vector<int32_t> part;
+  std::vector<uint8_t> cross;
+  std::vector<Sub> subs;
+};
+
+// Host set-up (setup_band.cpp, setup_partition.cpp). Return CPM_* codes.
+int build_band(Band& b, cpm_cp_fn fn, void* user, const double lo[3], const double hi[3],
+               double h, int p, double band_factor, std::string& err);
+int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const double* weights,
+                        int overlap, int kind, double alpha, double alpha_cross,
+                        std::string& err);
+
+// Per-subdomain descriptor shared by the factor and apply kernels.
+struct SubDesc {
+  int32_t m;         // |Sigma_j|
+  int32_t n;         // local unknowns: m (+ |B_j| for ORAS)
+  int32_t t;         // |Sigma~_j|
+  int32_t u_off;     // offset of the unknown list / lookup tables
+  int32_t t_off;     // offset of Sigma~_j lists
+  int32_t ldw;       // row stride of W_j
+  int64_t w_off;     // element offset of W_j in the W arena
+  int64_t a_off;     // element offset of the augmented matrix in the factor arena
+  int32_t lda;       // row stride of the augmented matrix
+  int32_t rows;      // n + t
+  int32_t cols;      // n + m
+  int32_t blk_off;   // first apply block of this subdomain
+};
+
+enum { TIMER_PRECOND = 0, TIMER_EXTEND = 1, TIMER_STENCIL = 2, TIMER_LU_GEMM = 3, N_TIMERS = 4 };
+
+struct Timer {
+  bool on = false;
+  double ms[N_TIMERS] = {0, 0, 0, 0};
+  int64_t count[N_TIMERS] = {0, 0, 0, 0};
+  std::vector<hipEvent_t> pool;   // event pairs recorded since the last harvest
+  std::vector<int> which;
+  size_t used = 0;
+};
+
+// Device-resident state.
+struct Dev {
+  // operator
+  int32_t* lines = nullptr;   // N_T x (p+1)^2
+  double* wts = nullptr;      // N_T x 3(p+1)
+  int32_t* nbr = nullptr;     // 6 x N_A (structure of arrays)
+  double* e = nullptr;        // N_T extension scratch
+  // preconditioner
+  SubDesc* desc = nullptr;
+  int32_t* blk_sub = nullptr;   // apply block -> subdomain
+  int32_t* sig_idx = nullptr;   // concatenated Sigma_j (band indices)
+  int32_t* tilde_idx = nullptr; // concatenated Sigma~_j (band indices)
+  void* W = nullptr;            // W arena (float or double)
+  int prec = -1;
+  int n_blocks = 0;
+  int max_m = 0;
+  size_t w_bytes = 0;
+  // Krylov workspace
+  int restart = 0;
+  int64_t ld = 0;               // padded vector length
+  double* V = nullptr;          // (restart+1) x ld
+  double* Z = nullptr;          // restart x ld
+  double* x = nullptr;
+  double* r = nullptr;
+  double* f = nullptr;
+  double* part = nullptr;       // partial sums
+  double* small = nullptr;      // H, cs, sn, g, y, h1, h2, scalars
+  double* host_small = nullptr; // pinned mirror of the scalars
+  size_t krylov_bytes = 0;
+  size_t op_bytes = 0;
+};
+
+}  // namespace cpm
+
+struct cpm_ctx {
+  int device = -1;
+  bool host_only = true;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;  // 0 created, 1 band, 2 operator, 3 partition, 4 factored
+  double c = 0;
+  cpm::Band band;
+  cpm::Decomp dec;
+  cpm::Dev dev;
+  cpm::Timer timer;
+};
+
+namespace cpm {
+// Device orchestration (device.hip).
+int dev_upload_operator(cpm_ctx* ctx);
+int dev_factor(cpm_ctx* ctx, int prec);
+int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y);
+int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);
+int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
+              cpm_solve_info* info);
+int dev_export_w(cpm_ctx* ctx, int j, double* w);
+void dev_free_all(cpm_ctx* ctx);
+void dev_free_factor(cpm_ctx* ctx);
+void timer_harvest(cpm_ctx* ctx);
+}  // namespace cpm

@@ -1,0 +1,584 @@
+// Device orchestration: operator upload, local operator factorisation,
+// preconditioner and operator applies, and the FGMRES driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace cpm {
+namespace {
+
+#define HIPCHK(expr)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+      return e_ == hipErrorOutOfMemory ? CPM_ENOMEM : CPM_EDEVICE;              \
+    }                                                                           \
+  } while (0)
+
+inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+template <class P>
+void dfree(P*& p) {
+  if (p) hipFree((void*)p);
+  p = nullptr;
+}
+
+template <class T>
+int upload(cpm_ctx* ctx, T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return CPM_OK;
+  HIPCHK(hipMalloc((void**)dst, src.size() * sizeof(T)));
+  HIPCHK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  return CPM_OK;
+}
+
+// Event pair around a launch when per-kernel timing is on.
+struct Scope {
+  cpm_ctx* ctx;
+  int which;
+  hipEvent_t e1 = nullptr;
+  Scope(cpm_ctx* c, int w) : ctx(c), which(w) {
+    Timer& t = ctx->timer;
+    if (!t.on) return;
+    if (t.used + 2 > t.pool.size()) {
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      t.pool.push_back(a);
+      t.pool.push_back(b);
+    }
+    hipEvent_t e0 = t.pool[t.used];
+    e1 = t.pool[t.used + 1];
+    t.which.push_back(which);
+    t.used += 2;
+    hipEventRecord(e0, ctx->stream);
+  }
+  ~Scope() {
+    if (e1) hipEventRecord(e1, ctx->stream);
+  }
+};
+
+}  // namespace
+
+void timer_harvest(cpm_ctx* ctx) {
+  Timer& t = ctx->timer;
+  if (t.used == 0) return;
+  hipStreamSynchronize(ctx->stream);
+  for (size_t q = 0; q < t.which.size(); ++q) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.pool[2 * q], t.pool[2 * q + 1]) == hipSuccess) {
+      t.ms[t.which[q]] += ms;
+      t.count[t.which[q]] += 1;
+    }
+  }
+  t.which.clear();
+  t.used = 0;
+}
+
+void dev_free_factor(cpm_ctx* ctx) {
+  Dev& d = ctx->dev;
+  hipStreamSynchronize(ctx->stream);
+  dfree(d.desc);
+  dfree(d.blk_sub);
+  dfree(d.sig_idx);
+  dfree(d.tilde_idx);
+  dfree(d.W);
+  d.prec = -1;
+  d.n_blocks = 0;
+  d.w_bytes = 0;
+}
+
+static void free_krylov(cpm_ctx* ctx) {
+  Dev& d = ctx->dev;
+  dfree(d.V);
+  dfree(d.Z);
+  dfree(d.x);
+  dfree(d.r);
+  dfree(d.f);
+  dfree(d.part);
+  dfree(d.small);
+  if (d.host_small) hipHostFree(d.host_small);
+  d.host_small = nullptr;
+  d.restart = 0;
+  d.krylov_bytes = 0;
+}
+
+void dev_free_all(cpm_ctx* ctx) {
+  Dev& d = ctx->dev;
+  dev_free_factor(ctx);
+  free_krylov(ctx);
+  dfree(d.lines);
+  dfree(d.wts);
+  dfree(d.nbr);
+  dfree(d.e);
+  d.op_bytes = 0;
+}
+
+int dev_upload_operator(cpm_ctx* ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  const Band& b = ctx->band;
+  Dev& d = ctx->dev;
+  int rc;
+  if ((rc = upload(ctx, &d.lines, b.lines)) != CPM_OK) return rc;
+  if ((rc = upload(ctx, &d.wts, b.wts)) != CPM_OK) return rc;
+  std::vector<int32_t> soa(b.n_act * 6);
+  for (int64_t i = 0; i < b.n_act; ++i)
+    for (int e = 0; e < 6; ++e) soa[e * b.n_act + i] = b.nbr[i * 6 + e];
+  if ((rc = upload(ctx, &d.nbr, soa)) != CPM_OK) return rc;
+  HIPCHK(hipMalloc((void**)&d.e, b.total() * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  d.op_bytes = b.lines.size() * 4 + b.wts.size() * 8 + soa.size() * 4 + b.total() * 8;
+  return CPM_OK;
+}
+
+// e = E x, y = A x (or y = f - A x when f != nullptr)
+static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const double* f) {
+  const Band& b = ctx->band;
+  Dev& d = ctx->dev;
+  const double ih2 = 1.0 / (b.h * b.h);
+  const double diag = ctx->c + 6.0 * ih2;
+  {
+    Scope s(ctx, TIMER_EXTEND);
+    if (b.p == 3)
+      k_extend<3><<<nblk(b.total() * 16, 256), 256, 0, ctx->stream>>>(b.total(), d.lines, d.wts, x, d.e);
+    else
+      k_extend<2><<<nblk(b.total() * 16, 256), 256, 0, ctx->stream>>>(b.total(), d.lines, d.wts, x, d.e);
+  }
+  {
+    Scope s(ctx, TIMER_STENCIL);
+    k_stencil<<<nblk(b.n_act, 256), 256, 0, ctx->stream>>>(b.n_act, diag, ih2, d.nbr, x, d.e, f, y);
+  }
+}
+
+static void launch_precond(cpm_ctx* ctx, const double* v, double* z) {
+  Dev& d = ctx->dev;
+  const size_t lds = (size_t)d.max_m * sizeof(double);
+  Scope s(ctx, TIMER_PRECOND);
+  if (d.prec == CPM_FP64)
+    k_precond<double><<<d.n_blocks, 256, lds, ctx->stream>>>(d.desc, d.blk_sub, d.sig_idx, d.tilde_idx,
+                                                              (const double*)d.W, v, z);
+  else
+    k_precond<float><<<d.n_blocks, 256, lds, ctx->stream>>>(d.desc, d.blk_sub, d.sig_idx, d.tilde_idx,
+                                                             (const float*)d.W, v, z);
+}
+
+int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y) {
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_operator(ctx, x, y, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return CPM_OK;
+}
+
+int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z) {
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_precond(ctx, v, z);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return CPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Factorisation
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FactorPlan {
+  std::vector<SubDesc> desc;
+  std::vector<int32_t> U, usrt, upos, bx, tilde_pos, tilde_idx, blk_sub;
+  std::vector<double> bs, ba;
+  int64_t a_elems = 0, w_elems = 0, u_total = 0;
+  int max_m = 0, max_n = 0, max_rows = 0, n_blocks = 0;
+};
+
+void make_plan(const cpm_ctx* ctx, FactorPlan& P) {
+  const Decomp& D = ctx->dec;
+  const bool oras = D.kind == CPM_ORAS;
+  int32_t u_off = 0, t_off = 0, blk = 0;
+  int64_t a_off = 0, w_off = 0;
+  for (int j = 0; j < D.n_sub; ++j) {
+    const Sub& s = D.subs[j];
+    SubDesc d{};
+    d.m = (int32_t)s.sigma.size();
+    d.n = d.m + (oras ? (int32_t)s.bnd.size() : 0);
+    d.t = (int32_t)s.tilde.size();
+    d.u_off = u_off;
+    d.t_off = t_off;
+    d.ldw = (int32_t)round_up(d.m, 8);
+    d.w_off = w_off;
+    d.rows = d.n + d.t;
+    d.cols = d.n + d.m;
+    d.lda = (int32_t)round_up(d.cols, 16);
+    d.a_off = a_off;
+    d.blk_off = blk;
+    const int nb = (d.t + PRECOND_ROWS - 1) / PRECOND_ROWS;
+    for (int q = 0; q < nb; ++q) P.blk_sub.push_back(j);
+    blk += nb;
+    a_off += (int64_t)d.rows * d.lda;
+    w_off += (int64_t)d.t * d.ldw;
+    // unknowns [Sigma_j ; B_j] and their sorted lookup
+    std::vector<int32_t> u(s.sigma);
+    if (oras) u.insert(u.end(), s.bnd.begin(), s.bnd.end());
+    std::vector<int32_t> order(u.size());
+    for (size_t q = 0; q < u.size(); ++q) order[q] = (int32_t)q;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return u[x] < u[y]; });
+    for (size_t q = 0; q < u.size(); ++q) {
+      P.U.push_back(u[q]);
+      P.usrt.push_back(u[order[q]]);
+      P.upos.push_back(order[q]);
+      const bool isb = (int)q >= d.m;
+      P.bx.push_back(isb ? s.xstar[q - d.m] : 0);
+      P.bs.push_back(isb ? s.s[q - d.m] : 0.0);
+      P.ba.push_back(isb ? s.alpha[q - d.m] : 0.0);
+    }
+    // positions of Sigma~_j inside Sigma_j (both sorted)
+    size_t p = 0;
+    for (int32_t x : s.tilde) {
+      while (s.sigma[p] != x) ++p;
+      P.tilde_pos.push_back((int32_t)p);
+      P.tilde_idx.push_back(x);
+    }
+    u_off += d.n;
+    t_off += d.t;
+    P.max_m = std::max(P.max_m, (int)d.ldw);
+    P.max_n = std::max(P.max_n, (int)d.n);
+    P.max_rows = std::max(P.max_rows, (int)d.rows);
+    P.desc.push_back(d);
+  }
+  P.a_elems = a_off;
+  P.w_elems = w_off;
+  P.u_total = u_off;
+  P.n_blocks = blk;
+}
+
+template <typename T>
+int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
+  const Band& b = ctx->band;
+  const Decomp& D = ctx->dec;
+  Dev& dv = ctx->dev;
+  const int ns = D.n_sub;
+  const double ih2 = 1.0 / (b.h * b.h);
+  const double diag = ctx->c + 6.0 * ih2;
+
+  SubDesc* ddesc = nullptr;
+  int32_t *dU = nullptr, *dsrt = nullptr, *dpos = nullptr, *dbx = nullptr, *dtpos = nullptr, *dtidx = nullptr,
+          *dblk = nullptr, *dipiv = nullptr, *dinfo = nullptr, *dpre = nullptr;
+  double *dbs = nullptr, *dba = nullptr;
+  T* dA = nullptr;
+  T* dW = nullptr;
+  int rc = CPM_OK;
+  auto cleanup = [&]() {
+    hipStreamSynchronize(ctx->stream);
+    dfree(dsrt); dfree(dpos); dfree(dbx); dfree(dtpos); dfree(dipiv); dfree(dinfo);
+    dfree(dpre); dfree(dbs); dfree(dba); dfree(dA);
+  };
+  auto bail = [&](int code) {
+    cleanup();
+    dfree(ddesc); dfree(dU); dfree(dtidx); dfree(dblk); dfree(dW);
+    return code;
+  };
+#define FCHK(expr)                                                      \
+  do {                                                                  \
+    int r_ = (expr);                                                    \
+    if (r_ != CPM_OK) return bail(r_);                                  \
+  } while (0)
+#define FHIP(expr)                                                      \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess) {                                             \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);     \
+      return bail(e_ == hipErrorOutOfMemory ? CPM_ENOMEM : CPM_EDEVICE); \
+    }                                                                   \
+  } while (0)
+
+  FCHK(upload(ctx, &ddesc, P.desc));
+  FCHK(upload(ctx, &dU, P.U));
+  FCHK(upload(ctx, &dsrt, P.usrt));
+  FCHK(upload(ctx, &dpos, P.upos));
+  FCHK(upload(ctx, &dbx, P.bx));
+  FCHK(upload(ctx, &dbs, P.bs));
+  FCHK(upload(ctx, &dba, P.ba));
+  FCHK(upload(ctx, &dtpos, P.tilde_pos));
+  FCHK(upload(ctx, &dtidx, P.tilde_idx));
+  FCHK(upload(ctx, &dblk, P.blk_sub));
+  FHIP(hipMalloc((void**)&dipiv, P.u_total * sizeof(int32_t)));
+  FHIP(hipMalloc((void**)&dinfo, ns * sizeof(int32_t)));
+  FHIP(hipMemsetAsync(dinfo, 0, ns * sizeof(int32_t), ctx->stream));
+  FHIP(hipMalloc((void**)&dA, P.a_elems * sizeof(T)));
+  FHIP(hipMemsetAsync(dA, 0, P.a_elems * sizeof(T), ctx->stream));
+
+  // Assembly of the augmented local matrices.
+  {
+    dim3 grid(nblk(P.max_rows, 256), ns);
+    if (b.p == 3)
+      k_assemble<T, 3><<<grid, 256, 0, ctx->stream>>>(ddesc, b.n_act, dv.lines, dv.wts, dv.nbr, dU, dsrt, dpos,
+                                                      dbx, dbs, dba, dtpos, diag, ih2, D.kind == CPM_ORAS, dA);
+    else
+      k_assemble<T, 2><<<grid, 256, 0, ctx->stream>>>(ddesc, b.n_act, dv.lines, dv.wts, dv.nbr, dU, dsrt, dpos,
+                                                      dbx, dbs, dba, dtpos, diag, ih2, D.kind == CPM_ORAS, dA);
+    FHIP(hipGetLastError());
+  }
+
+  // Per-step work lists: blocks of 256 trailing columns (swap + TRSM) and
+  // 64x64 tiles (trailing update), as prefix sums over subdomains.
+  const int nsteps = (P.max_n + LU_NB - 1) / LU_NB;
+  std::vector<int32_t> pre((size_t)nsteps * 2 * (ns + 1));
+  std::vector<int> tot_c(nsteps), tot_t(nsteps);
+  for (int st = 0; st < nsteps; ++st) {
+    const int k = st * LU_NB;
+    int32_t* pc = &pre[(size_t)st * 2 * (ns + 1)];
+    int32_t* pt = pc + ns + 1;
+    int ac = 0, at = 0;
+    for (int j = 0; j < ns; ++j) {
+      const SubDesc& d = P.desc[j];
+      pc[j] = ac;
+      pt[j] = at;
+      if (k >= d.n) continue;
+      const int lo = k + std::min(LU_NB, d.n - k);
+      ac += (d.cols - lo + 255) / 256;
+      at += ((d.rows - lo + GEMM_TILE - 1) / GEMM_TILE) * ((d.cols - lo + GEMM_TILE - 1) / GEMM_TILE);
+    }
+    pc[ns] = ac;
+    pt[ns] = at;
+    tot_c[st] = ac;
+    tot_t[st] = at;
+  }
+  FCHK(upload(ctx, &dpre, pre));
+  for (int st = 0; st < nsteps; ++st) {
+    const int k = st * LU_NB;
+    const int32_t* pc = dpre + (size_t)st * 2 * (ns + 1);
+    const int32_t* pt = pc + ns + 1;
+    k_lu_panel<T><<<ns, PANEL_THREADS, 0, ctx->stream>>>(ddesc, dA, k, dipiv, dinfo);
+    if (tot_c[st] > 0) k_lu_swap_trsm<T><<<tot_c[st], 256, 0, ctx->stream>>>(ddesc, dA, k, dipiv, pc, ns);
+    if (tot_t[st] > 0) {
+      Scope s(ctx, TIMER_LU_GEMM);
+      k_lu_gemm<T><<<tot_t[st], 256, 0, ctx->stream>>>(ddesc, dA, k, pt, ns);
+    }
+  }
+  FHIP(hipGetLastError());
+  FHIP(hipMalloc((void**)&dW, P.w_elems * sizeof(T)));
+  {
+    int tmax = 0;
+    for (const SubDesc& d : P.desc) tmax = std::max(tmax, (int)d.t);
+    dim3 grid(tmax, ns);
+    k_extract_w<T><<<grid, 256, 0, ctx->stream>>>(ddesc, dA, dW);
+    FHIP(hipGetLastError());
+  }
+  std::vector<int32_t> info(ns);
+  FHIP(hipMemcpyAsync(info.data(), dinfo, ns * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  FHIP(hipStreamSynchronize(ctx->stream));
+  for (int j = 0; j < ns; ++j)
+    if (info[j] != 0) {
+      ctx->err = "factor: zero pivot in subdomain " + std::to_string(j) + " at column " + std::to_string(info[j] - 1);
+      return bail(CPM_ESINGULAR);
+    }
+  cleanup();
+  dv.desc = ddesc;
+  dv.sig_idx = dU;
+  dv.tilde_idx = dtidx;
+  dv.blk_sub = dblk;
+  dv.W = dW;
+  dv.prec = prec;
+  dv.n_blocks = P.n_blocks;
+  dv.max_m = P.max_m;
+  dv.w_bytes = P.w_elems * sizeof(T) + P.desc.size() * sizeof(SubDesc) + (P.U.size() + P.tilde_idx.size() +
+               P.blk_sub.size()) * sizeof(int32_t);
+  return rc;
+#undef FCHK
+#undef FHIP
+}
+
+}  // namespace
+
+int dev_factor(cpm_ctx* ctx, int prec) {
+  HIPCHK(hipSetDevice(ctx->device));
+  dev_free_factor(ctx);
+  FactorPlan P;
+  make_plan(ctx, P);
+  const size_t lds = (size_t)P.max_m * sizeof(double);
+  if (lds > 160 * 1024) {
+    ctx->err = "factor: a subdomain is too large for the preconditioner apply (|Sigma_j| > 20480)";
+    return CPM_EINVAL;
+  }
+  if (lds > 64 * 1024) {
+    hipFuncSetAttribute((const void*)k_precond<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute((const void*)k_precond<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec) : run_factor<float>(ctx, P, prec);
+}
+
+int dev_export_w(cpm_ctx* ctx, int j, double* w) {
+  HIPCHK(hipSetDevice(ctx->device));
+  Dev& dv = ctx->dev;
+  SubDesc d;
+  HIPCHK(hipMemcpy(&d, dv.desc + j, sizeof(SubDesc), hipMemcpyDeviceToHost));
+  const size_t esz = dv.prec == CPM_FP64 ? 8 : 4;
+  std::vector<char> buf((size_t)d.t * d.ldw * esz);
+  HIPCHK(hipMemcpy(buf.data(), (char*)dv.W + d.w_off * esz, buf.size(), hipMemcpyDeviceToHost));
+  for (int q = 0; q < d.t; ++q)
+    for (int c = 0; c < d.m; ++c) {
+      const size_t at = (size_t)q * d.ldw + c;
+      w[(size_t)q * d.m + c] = esz == 8 ? ((const double*)buf.data())[at] : (double)((const float*)buf.data())[at];
+    }
+  return CPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES(m), right preconditioned, CGS2 Arnoldi, x0 = 0.
+// ---------------------------------------------------------------------------
+static int ensure_krylov(cpm_ctx* ctx, int m) {
+  Dev& d = ctx->dev;
+  if (d.restart == m && d.V) return CPM_OK;
+  free_krylov(ctx);
+  const int64_t na = ctx->band.n_act;
+  d.ld = round_up(na, 64);
+  SmallLayout L{m};
+  HIPCHK(hipMalloc((void**)&d.V, (size_t)(m + 1) * d.ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.Z, (size_t)m * d.ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.x, d.ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.r, d.ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.f, d.ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.part, (size_t)RED_BLOCKS * PART_LD * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.small, (size_t)L.size() * sizeof(double)));
+  HIPCHK(hipHostMalloc((void**)&d.host_small, 8 * sizeof(double)));
+  d.restart = m;
+  d.krylov_bytes = ((size_t)(2 * m + 4) * d.ld + RED_BLOCKS * PART_LD + L.size()) * sizeof(double);
+  return CPM_OK;
+}
+
+int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int m, cpm_solve_info* info) {
+  HIPCHK(hipSetDevice(ctx->device));
+  int rc = ensure_krylov(ctx, m);
+  if (rc != CPM_OK) return rc;
+  Dev& d = ctx->dev;
+  const int64_t na = ctx->band.n_act;
+  const SmallLayout L{m};
+  double* sm = d.small;
+  double* scal = sm + L.scal();
+  double* hs = d.host_small;
+  hipStream_t st = ctx->stream;
+  const unsigned gv = nblk(na, 256);
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, st));
+
+  auto fetch_scal = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CPM_OK;
+  };
+  auto finish = [&](int code, int iters, int cycles, double rel_true, double rel_est) -> int {
+    hipEventRecord(t1, st);
+    hipEventSynchronize(t1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, t0, t1);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (info) {
+      info->iters = iters;
+      info->cycles = cycles;
+      info->status = code;
+      info->relres_true = rel_true;
+      info->relres_est = rel_est;
+      info->ms = ms;
+    }
+    return code;
+  };
+
+  // ||f||
+  k_dots<<<RED_BLOCKS, 256, 0, st>>>(na, f, 0, 1, f, d.part);
+  k_reduce_norm<<<1, 64, 0, st>>>(d.part, scal);
+  if ((rc = fetch_scal()) != CPM_OK) return rc;
+  const double bnorm = hs[S_BETA];
+  if (!std::isfinite(bnorm)) {
+    finish(CPM_EINVAL, 0, 0, NAN, NAN);
+    ctx->err = "solve: right-hand side is not finite";
+    return CPM_EINVAL;
+  }
+  k_fill<<<gv, 256, 0, st>>>(na, u, 0.0);
+  if (bnorm == 0.0) return finish(CPM_OK, 0, 0, 0.0, 0.0);
+  k_copy<<<gv, 256, 0, st>>>(na, f, d.r);
+
+  int iters = 0, cycles = 0;
+  double rel_true = 1.0, rel_est = 1.0;
+  int status = CPM_ENOTCONV;
+  for (;;) {
+    k_init_cycle<<<gv, 256, 0, st>>>(na, d.r, d.V, L, sm);
+    int kk = 0;
+    for (int k = 0; k < m; ++k) {
+      double* vk = d.V + (size_t)k * d.ld;
+      double* w = d.V + (size_t)(k + 1) * d.ld;
+      double* zk = d.Z + (size_t)k * d.ld;
+      launch_precond(ctx, vk, zk);
+      launch_operator(ctx, zk, w, nullptr);
+      k_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.V, d.ld, k + 1, w, d.part);
+      k_reduce_cols<<<1, 256, 0, st>>>(d.part, k + 1, sm + L.h1());
+      k_axpy_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.V, d.ld, k + 1, sm + L.h1(), w, d.part, 0);
+      k_reduce_cols<<<1, 256, 0, st>>>(d.part, k + 1, sm + L.h2());
+      k_axpy_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.V, d.ld, k + 1, sm + L.h2(), w, d.part, 1);
+      k_arnoldi<<<1, 64, 0, st>>>(k, L, sm, d.part);
+      k_scale<<<gv, 256, 0, st>>>(na, w, scal + S_INV);
+      if ((rc = fetch_scal()) != CPM_OK) return rc;
+      ++iters;
+      kk = k + 1;
+      rel_est = hs[S_EST] / bnorm;
+      if (!(hs[S_EST] > tol * bnorm) || iters >= max_iter || hs[S_HK1] == 0.0) break;
+    }
+    k_backsolve<<<1, 64, 0, st>>>(kk, L, sm);
+    k_update_x<<<gv, 256, 0, st>>>(na, d.Z, d.ld, kk, sm + L.y(), u);
+    launch_operator(ctx, u, d.r, f);
+    k_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.r, 0, 1, d.r, d.part);
+    k_reduce_norm<<<1, 64, 0, st>>>(d.part, scal);
+    if ((rc = fetch_scal()) != CPM_OK) return rc;
+    ++cycles;
+    rel_true = hs[S_BETA] / bnorm;
+    if (rel_true <= tol) { status = CPM_OK; break; }
+    if (iters >= max_iter || !std::isfinite(rel_true)) break;
+  }
+  HIPCHK(hipGetLastError());
+  return finish(status, iters, cycles, rel_true, rel_est);
+}
+
+template <typename T>
+static int selftest_tile(const double* a, const double* b, double* c, int kb) {
+  std::vector<T> ha(GEMM_TILE * LU_NB, (T)0), hb(LU_NB * GEMM_TILE, (T)0), hc(GEMM_TILE * GEMM_TILE);
+  for (int i = 0; i < GEMM_TILE; ++i)
+    for (int q = 0; q < kb; ++q) ha[i * LU_NB + q] = (T)a[i * LU_NB + q];
+  for (int q = 0; q < kb; ++q)
+    for (int jx = 0; jx < GEMM_TILE; ++jx) hb[q * GEMM_TILE + jx] = (T)b[q * GEMM_TILE + jx];
+  for (int q = 0; q < GEMM_TILE * GEMM_TILE; ++q) hc[q] = (T)c[q];
+  T *da = nullptr, *db = nullptr, *dc = nullptr;
+  if (hipMalloc((void**)&da, ha.size() * sizeof(T)) != hipSuccess) return CPM_ENOMEM;
+  if (hipMalloc((void**)&db, hb.size() * sizeof(T)) != hipSuccess) { hipFree(da); return CPM_ENOMEM; }
+  if (hipMalloc((void**)&dc, hc.size() * sizeof(T)) != hipSuccess) { hipFree(da); hipFree(db); return CPM_ENOMEM; }
+  hipMemcpy(da, ha.data(), ha.size() * sizeof(T), hipMemcpyHostToDevice);
+  hipMemcpy(db, hb.data(), hb.size() * sizeof(T), hipMemcpyHostToDevice);
+  hipMemcpy(dc, hc.data(), hc.size() * sizeof(T), hipMemcpyHostToDevice);
+  k_tile_selftest<T><<<1, 256>>>(dc, da, db, kb);
+  hipError_t e = hipDeviceSynchronize();
+  hipMemcpy(hc.data(), dc, hc.size() * sizeof(T), hipMemcpyDeviceToHost);
+  hipFree(da);
+  hipFree(db);
+  hipFree(dc);
+  if (e != hipSuccess) return CPM_EDEVICE;
+  for (int q = 0; q < GEMM_TILE * GEMM_TILE; ++q) c[q] = (double)hc[q];
+  return CPM_OK;
+}
+
+}  // namespace cpm
+
+extern "C" int cpm_selftest_tile(int device, int prec, const double* a, const double* b, double* c, int kb) {
+  if (!a || !b || !c || kb < 1 || kb > cpm::LU_NB) return CPM_EINVAL;
+  if (prec != CPM_FP64 && prec != CPM_FP32) return CPM_EINVAL;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CPM_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return CPM_EDEVICE;
+  return prec == CPM_FP64 ? cpm::selftest_tile<double>(a, b, c, kb) : cpm::selftest_tile<float>(a, b, c, kb);
+}

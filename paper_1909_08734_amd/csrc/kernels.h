@@ -1,0 +1,635 @@
+// HIP kernels for gfx950 (wave64). Included once, by device.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cpm_internal.h"
+
+namespace cpm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of one value per thread over a 256-thread block (fixed order).
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply (Section 2.1): e = E x over all band rows, then
+// y = (c + 6/h^2) x - (1/h^2) sum_{6 neighbours} e.
+// Extension: 16 lanes per row, one lane per stencil z-line (a, b); the lane
+// interpolates along z, weights by w_x[a] w_y[b], the 16 lanes reduce.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
+                                                const double* __restrict__ wts,
+                                                const double* __restrict__ x, double* __restrict__ e) {
+  constexpr int P1 = P + 1, NL = P1 * P1;
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int q = threadIdx.x & 15;
+  double acc = 0.0;
+  if (row < n_rows && q < NL) {
+    const int a = q / P1, b = q - (q / P1) * P1;
+    const double* w = wts + row * (3 * P1);
+    const int32_t s = lines[row * NL + q];
+    double lz = 0.0;
+#pragma unroll
+    for (int c = 0; c < P1; ++c) lz += w[2 * P1 + c] * x[s + c];
+    acc = (w[a] * w[P1 + b]) * lz;
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (row < n_rows && q == 0) e[row] = acc;
+}
+
+// y = diag x - ih2 * sum_nb e[nb]           (f == nullptr)
+// y = f - (diag x - ih2 * sum_nb e[nb])     (residual form)
+__global__ __launch_bounds__(256) void k_stencil(int64_t na, double diag, double ih2,
+                                                 const int32_t* __restrict__ nbr,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ e,
+                                                 const double* __restrict__ f, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= na) return;
+  const double s = (e[nbr[i]] + e[nbr[na + i]]) + (e[nbr[2 * na + i]] + e[nbr[3 * na + i]]) +
+                   (e[nbr[4 * na + i]] + e[nbr[5 * na + i]]);
+  const double v = diag * x[i] - ih2 * s;
+  y[i] = f ? f[i] - v : v;
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner apply (eq. algRAS): for every subdomain j and row q of
+// Sigma~_j, z[tilde_j(q)] = sum_c W_j[q, c] v[sigma_j(c)]. One block per
+// (subdomain, group of rows); v|Sigma_j is gathered into LDS once per block,
+// W rows stream from HBM with 16-byte loads; each row is written once.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct VecOf;
+template <>
+struct VecOf<double> {
+  typedef d2v type;
+  static constexpr int n = 2;
+};
+template <>
+struct VecOf<float> {
+  typedef f4 type;
+  static constexpr int n = 4;
+};
+
+constexpr int PRECOND_ROWS = 32;   // rows of W per block
+constexpr int PRECOND_RPW = 4;     // rows a wave streams at once
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_precond(const SubDesc* __restrict__ desc,
+                                                 const int32_t* __restrict__ blk_sub,
+                                                 const int32_t* __restrict__ sig_idx,
+                                                 const int32_t* __restrict__ tilde_idx,
+                                                 const T* __restrict__ W, const double* __restrict__ v,
+                                                 double* __restrict__ z) {
+  extern __shared__ double vs[];
+  typedef typename VecOf<T>::type VT;
+  constexpr int VN = VecOf<T>::n;
+  const int blk = blockIdx.x;
+  const int j = blk_sub[blk];
+  const SubDesc d = desc[j];
+  for (int c = threadIdx.x; c < d.ldw; c += blockDim.x) vs[c] = c < d.m ? v[sig_idx[d.u_off + c]] : 0.0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r_begin = (blk - d.blk_off) * PRECOND_ROWS;
+  const int r_end = min(r_begin + PRECOND_ROWS, d.t);
+  for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += 4 * PRECOND_RPW) {
+    const T* wr[PRECOND_RPW];
+    double acc[PRECOND_RPW];
+#pragma unroll
+    for (int i = 0; i < PRECOND_RPW; ++i) {
+      wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw;
+      acc[i] = 0.0;
+    }
+    for (int c = lane * VN; c < d.ldw; c += 64 * VN) {
+      VT wv[PRECOND_RPW];
+#pragma unroll
+      for (int i = 0; i < PRECOND_RPW; ++i) wv[i] = *reinterpret_cast<const VT*>(wr[i] + c);
+#pragma unroll
+      for (int u = 0; u < VN; ++u) {
+        const double xv = vs[c + u];
+#pragma unroll
+        for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[i][u] * xv;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PRECOND_RPW; ++i) {
+      const double s = wave_sum(acc[i]);
+      if (lane == 0 && r0 + i < r_end) z[tilde_idx[d.t_off + r0 + i]] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Local operator assembly (Section 5, eq. localOP) into the augmented matrix
+//   [ A_j        E_Sigma ]      E_Sigma: identity on the Sigma_j rows
+//   [ R~_j          0    ]      R~_j: selects Sigma~_j
+// stored row-major. Eliminating the first n_j columns leaves -W_j in the
+// lower-right block. Interior rows: (c + 6/h^2) u_x - (1/h^2) sum over the FD
+// neighbours of their extended value: E row for Sigma_j / ghost neighbours,
+// the unknown u_b itself for a neighbour in B_j (ORAS; equal to its Robin
+// extension by the B row) or 0 (RAS). B rows (ORAS):
+// sigma u_b - sigma/(1 + alpha_b s_b) E[x*(b)] u = 0, sigma = c + 6/h^2.
+// Column lookup: binary search of the band index in the sorted unknown list.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int local_pos(const int32_t* __restrict__ srt, const int32_t* __restrict__ pos,
+                                         int n, int32_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (srt[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && srt[lo] == key) ? pos[lo] : -1;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ desc, int64_t na,
+                                                  const int32_t* __restrict__ lines,
+                                                  const double* __restrict__ wts,
+                                                  const int32_t* __restrict__ nbr,
+                                                  const int32_t* __restrict__ U,
+                                                  const int32_t* __restrict__ usrt,
+                                                  const int32_t* __restrict__ upos,
+                                                  const int32_t* __restrict__ bx,
+                                                  const double* __restrict__ bs,
+                                                  const double* __restrict__ ba,
+                                                  const int32_t* __restrict__ tilde_pos,
+                                                  double diag, double ih2, int oras, T* __restrict__ A) {
+  constexpr int P1 = P + 1, NL = P1 * P1;
+  const int j = blockIdx.y;
+  const SubDesc d = desc[j];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.rows) return;
+  T* row = A + d.a_off + (int64_t)r * d.lda;
+  const int32_t* srt = usrt + d.u_off;
+  const int32_t* ps = upos + d.u_off;
+  auto add_ext = [&](int32_t node, double scale) {
+    const double* w = wts + (int64_t)node * 3 * P1;
+    for (int a = 0; a < P1; ++a)
+      for (int b = 0; b < P1; ++b) {
+        const int32_t s = lines[(int64_t)node * NL + a * P1 + b];
+        const double wab = w[a] * w[P1 + b];
+        for (int c = 0; c < P1; ++c) {
+          const int q = local_pos(srt, ps, d.n, s + c);
+          if (q >= 0) row[q] = (T)((double)row[q] - scale * (wab * w[2 * P1 + c]));
+        }
+      }
+  };
+  if (r < d.m) {
+    const int32_t x = U[d.u_off + r];
+    row[r] = (T)((double)row[r] + diag);
+    for (int e = 0; e < 6; ++e) {
+      const int32_t y = nbr[e * na + x];
+      if (y < na) {
+        const int q = local_pos(srt, ps, d.n, y);
+        if (q >= d.m) {  // ORAS transmission node
+          row[q] = (T)((double)row[q] - ih2);
+          continue;
+        }
+        if (q < 0) continue;  // RAS: u_b = 0
+      }
+      add_ext(y, ih2);
+    }
+    row[d.n + r] = (T)1;
+  } else if (r < d.n) {
+    const int32_t k = d.u_off + r;
+    row[r] = (T)((double)row[r] + diag);
+    if (oras) add_ext(bx[k], diag / (1.0 + ba[k] * bs[k]));
+  } else {
+    row[tilde_pos[d.t_off + (r - d.n)]] = (T)1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched right-looking LU with partial pivoting on the augmented matrices
+// (pivots searched in the first n_j rows only), panel width NB.
+// ---------------------------------------------------------------------------
+constexpr int LU_NB = 32;
+constexpr int PANEL_THREADS = 512;
+
+template <typename T>
+__global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __restrict__ desc, T* __restrict__ A,
+                                                            int k, int32_t* __restrict__ ipiv,
+                                                            int32_t* __restrict__ info) {
+  constexpr int NW = PANEL_THREADS / 64;
+  __shared__ T prow[LU_NB];
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
+  __shared__ int piv_s;
+  const int j = blockIdx.x;
+  const SubDesc d = desc[j];
+  if (k >= d.n) return;
+  const int kb = min(LU_NB, d.n - k);
+  T* a = A + d.a_off;
+  const int64_t lda = d.lda;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int jj = 0; jj < kb; ++jj) {
+    const int col = k + jj;
+    double best = -1.0;
+    int bi = INT32_MAX;
+    for (int r = col + threadIdx.x; r < d.n; r += PANEL_THREADS) {
+      const double v = fabs((double)a[r * lda + col]);
+      if (v > best) { best = v; bi = r; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { rv[wave] = best; ri[wave] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b0 = rv[0];
+      int i0 = ri[0];
+      for (int w = 1; w < NW; ++w)
+        if (rv[w] > b0 || (rv[w] == b0 && ri[w] < i0)) { b0 = rv[w]; i0 = ri[w]; }
+      piv_s = (i0 == INT32_MAX || b0 == 0.0) ? -1 : i0;
+      ipiv[d.u_off + col] = piv_s < 0 ? col : piv_s;
+      if (piv_s < 0 && info[j] == 0) info[j] = col + 1;
+    }
+    __syncthreads();
+    const int piv = piv_s;
+    if (piv < 0) continue;  // exactly singular column: recorded, elimination skipped
+    if (piv != col)
+      for (int c = k + threadIdx.x; c < k + kb; c += PANEL_THREADS) {
+        const T t = a[col * lda + c];
+        a[col * lda + c] = a[piv * lda + c];
+        a[piv * lda + c] = t;
+      }
+    __syncthreads();
+    const T pv = a[col * lda + col];
+    const int rest = kb - jj - 1;
+    for (int c = threadIdx.x; c < rest; c += PANEL_THREADS) prow[c] = a[col * lda + col + 1 + c];
+    __syncthreads();
+    for (int r = col + 1 + threadIdx.x; r < d.rows; r += PANEL_THREADS) {
+      T* ar = a + r * lda;
+      const T l = ar[col] / pv;
+      ar[col] = l;
+      for (int c = 0; c < rest; ++c) ar[col + 1 + c] -= l * prow[c];
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int find_sub(const int32_t* __restrict__ prefix, int n_sub, int blk) {
+  int lo = 0, hi = n_sub - 1;  // largest j with prefix[j] <= blk
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Row interchanges of the panel applied to the trailing columns, then
+// U12 = L11^{-1} A12 (unit lower triangular solve), 256 columns per block;
+// each thread owns one column, held in LDS during the substitution.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_swap_trsm(const SubDesc* __restrict__ desc, T* __restrict__ A, int k,
+                                                      const int32_t* __restrict__ ipiv,
+                                                      const int32_t* __restrict__ prefix, int n_sub) {
+  __shared__ T L[LU_NB][LU_NB + 1];
+  __shared__ T X[LU_NB][256];
+  const int j = find_sub(prefix, n_sub, blockIdx.x);
+  const SubDesc d = desc[j];
+  const int kb = min(LU_NB, d.n - k);
+  T* a = A + d.a_off;
+  const int64_t lda = d.lda;
+  for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
+    const int i = idx / kb, q = idx - (idx / kb) * kb;
+    L[i][q] = a[(k + i) * lda + k + q];
+  }
+  __syncthreads();
+  const int c = k + kb + (blockIdx.x - prefix[j]) * 256 + threadIdx.x;
+  if (c >= d.cols) return;
+  for (int jj = 0; jj < kb; ++jj) {
+    const int p = ipiv[d.u_off + k + jj];
+    if (p != k + jj) {
+      const T t = a[(k + jj) * lda + c];
+      a[(k + jj) * lda + c] = a[p * lda + c];
+      a[p * lda + c] = t;
+    }
+  }
+  const int t = threadIdx.x;
+  for (int i = 0; i < kb; ++i) X[i][t] = a[(k + i) * lda + c];
+  for (int q = 0; q < kb; ++q) {
+    const T xq = X[q][t];
+    for (int i = q + 1; i < kb; ++i) X[i][t] -= L[i][q] * xq;
+  }
+  for (int i = 1; i < kb; ++i) a[(k + i) * lda + c] = X[i][t];
+}
+
+// Trailing update A22 -= L21 U12 on matrix cores. 64x64 tile per block of 4
+// waves, each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K = panel width.
+// 16x16x4 operand layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, D[i][j] in lane j + 16(i/4), element i%4.
+__device__ __forceinline__ d4 mfma_16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<double> { typedef d4 type; };
+template <>
+struct Acc4<float> { typedef f4 type; };
+
+constexpr int GEMM_TILE = 64;
+
+template <typename T>
+__device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int rows, int cols, int kb,
+                                            int r0, int c0, const T* __restrict__ lsrc, int64_t lld,
+                                            const T* __restrict__ usrc, int64_t uld) {
+  // C[r0.., c0..] -= Lsrc[r0.., 0..kb) * Usrc[0..kb, c0..]
+  __shared__ T Ls[GEMM_TILE][LU_NB + 1];
+  __shared__ T Us[LU_NB][GEMM_TILE + 1];
+  typedef typename Acc4<T>::type AT;
+  for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
+    const int i = idx / LU_NB, q = idx - (idx / LU_NB) * LU_NB;
+    Ls[i][q] = (r0 + i < rows && q < kb) ? lsrc[(int64_t)(r0 + i) * lld + q] : (T)0;
+  }
+  for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
+    const int q = idx / GEMM_TILE, jx = idx - (idx / GEMM_TILE) * GEMM_TILE;
+    Us[q][jx] = (q < kb && c0 + jx < cols) ? usrc[(int64_t)q * uld + c0 + jx] : (T)0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  AT acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = r0 + wr + bi * 16 + 4 * lk + i, cc = c0 + wc + bj * 16 + li;
+        acc[bi][bj][i] = (rr < rows && cc < cols) ? a[(int64_t)rr * lda + cc] : (T)0;
+      }
+  const int ksteps = (kb + 3) >> 2;
+  for (int kk = 0; kk < ksteps; ++kk) {
+    T av[2], bv[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) av[bi] = -Ls[wr + bi * 16 + li][kk * 4 + lk];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) bv[bj] = Us[kk * 4 + lk][wc + bj * 16 + li];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_16x16x4(av[bi], bv[bj], acc[bi][bj]);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = r0 + wr + bi * 16 + 4 * lk + i, cc = c0 + wc + bj * 16 + li;
+        if (rr < rows && cc < cols) a[(int64_t)rr * lda + cc] = acc[bi][bj][i];
+      }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ desc, T* __restrict__ A, int k,
+                                                 const int32_t* __restrict__ prefix, int n_sub) {
+  const int j = find_sub(prefix, n_sub, blockIdx.x);
+  const SubDesc d = desc[j];
+  const int kb = min(LU_NB, d.n - k);
+  const int lo = k + kb;
+  const int ntc = (d.cols - lo + GEMM_TILE - 1) / GEMM_TILE;
+  const int tile = blockIdx.x - prefix[j];
+  const int tr = tile / ntc, tc = tile - (tile / ntc) * ntc;
+  T* a = A + d.a_off;
+  const int64_t lda = d.lda;
+  // rows/cols relative to the trailing block origin (lo, lo)
+  tile_update<T>(a + lo * lda + lo, lda, d.rows - lo, d.cols - lo, kb, tr * GEMM_TILE, tc * GEMM_TILE,
+                 a + lo * lda + k, lda, a + (int64_t)k * lda + lo, lda);
+}
+
+// Self-test of the matrix-core tile: C (64x64) -= A (64xkb) B (kbx64), row-major.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_selftest(T* C, const T* Am, const T* Bm, int kb) {
+  tile_update<T>(C, GEMM_TILE, GEMM_TILE, GEMM_TILE, kb, 0, 0, Am, LU_NB, Bm, GEMM_TILE);
+}
+
+// W_j = -(lower-right block) of the eliminated augmented matrix, row stride ldw.
+template <typename T>
+__global__ __launch_bounds__(256) void k_extract_w(const SubDesc* __restrict__ desc, const T* __restrict__ A,
+                                                   T* __restrict__ W) {
+  const int j = blockIdx.y;
+  const SubDesc d = desc[j];
+  const int q = blockIdx.x;
+  if (q >= d.t) return;
+  const T* src = A + d.a_off + (int64_t)(d.n + q) * d.lda + d.n;
+  T* dst = W + d.w_off + (int64_t)q * d.ldw;
+  for (int c = threadIdx.x; c < d.ldw; c += 256) dst[c] = c < d.m ? -src[c] : (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov kernels (FGMRES with classical Gram-Schmidt applied twice). All
+// reductions are two-stage with a fixed order, so results are reproducible.
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 256;
+constexpr int PART_LD = 64;  // partial-sum stride per block (columns per launch <= 64)
+
+__device__ __forceinline__ void row_range(int64_t n, int64_t& r0, int64_t& r1) {
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  r0 = (int64_t)blockIdx.x * chunk;
+  r1 = min(n, r0 + chunk);
+}
+
+// part[b][j] = sum_{rows of block b} X_j[r] w[r], j < ncols (X columns stride ldx)
+__device__ __forceinline__ void block_dots(int64_t r0, int64_t r1, const double* __restrict__ X, int64_t ldx,
+                                           int ncols, const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[4][4];
+  for (int j0 = 0; j0 < ncols; j0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+      const double wr = w[r];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u < ncols) acc[u] += X[(j0 + u) * ldx + r] * wr;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = wave_sum(acc[u]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) red[threadIdx.x >> 6][u] = acc[u];
+    __syncthreads();
+    if (threadIdx.x < 4 && j0 + (int)threadIdx.x < ncols) {
+      const int u = threadIdx.x;
+      part[blockIdx.x * PART_LD + j0 + u] = (red[0][u] + red[1][u]) + (red[2][u] + red[3][u]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dots(int64_t n, const double* __restrict__ X, int64_t ldx, int ncols,
+                                              const double* __restrict__ w, double* __restrict__ part) {
+  int64_t r0, r1;
+  row_range(n, r0, r1);
+  block_dots(r0, r1, X, ldx, ncols, w, part);
+}
+
+// w -= X h (h: ncols values), then part = X^T w (mode 0) or ||w||^2 (mode 1).
+__global__ __launch_bounds__(256) void k_axpy_dots(int64_t n, const double* __restrict__ X, int64_t ldx, int ncols,
+                                                   const double* __restrict__ h, double* __restrict__ w,
+                                                   double* __restrict__ part, int mode) {
+  __shared__ double hs[256];
+  for (int q = threadIdx.x; q < ncols; q += 256) hs[q] = h[q];
+  __syncthreads();
+  int64_t r0, r1;
+  row_range(n, r0, r1);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double s = 0.0;
+    for (int q = 0; q < ncols; ++q) s += X[q * ldx + r] * hs[q];
+    w[r] -= s;
+  }
+  if (mode == 0) block_dots(r0, r1, X, ldx, ncols, w, part);
+  else block_dots(r0, r1, w, 0, 1, w, part);
+}
+
+// out[j] = sum_b part[b][j] for j < ncols (fixed order).
+__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part, int ncols,
+                                                     double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < ncols; j += 4) {
+    double s = 0.0;
+    for (int b = lane; b < RED_BLOCKS; b += 64) s += part[b * PART_LD + j];
+    s = wave_sum(s);
+    if (lane == 0) out[j] = s;
+  }
+}
+
+// Layout of the small device buffer (doubles).
+struct SmallLayout {
+  int m;
+  __host__ __device__ int H() const { return 0; }                    // (m+1) x m, column-major
+  __host__ __device__ int cs() const { return (m + 1) * m; }
+  __host__ __device__ int sn() const { return cs() + m; }
+  __host__ __device__ int g() const { return sn() + m; }             // m+1
+  __host__ __device__ int y() const { return g() + m + 1; }          // m
+  __host__ __device__ int h1() const { return y() + m; }             // m+1
+  __host__ __device__ int h2() const { return h1() + m + 1; }        // m+1
+  __host__ __device__ int scal() const { return h2() + m + 1; }      // 8 scalars
+  __host__ __device__ int size() const { return scal() + 8; }
+};
+enum { S_EST = 0, S_HK1 = 1, S_INV = 2, S_BETA = 3, S_INVB = 4, S_NORM = 5 };
+
+// Norm of a reduced column: scal[S_BETA] = sqrt(sum), scal[S_INVB] = 1/that (0 if zero).
+__global__ __launch_bounds__(64) void k_reduce_norm(const double* __restrict__ part, double* __restrict__ scal) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < RED_BLOCKS; b += 64) s += part[b * PART_LD];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) {
+    const double nr = sqrt(s);
+    scal[S_BETA] = nr;
+    scal[S_INVB] = nr > 0.0 ? 1.0 / nr : 0.0;
+  }
+}
+
+// Arnoldi column k: H[:,k] = h1 + h2, H[k+1,k] = ||w||, Givens update of the
+// least-squares problem, residual estimate |g[k+1]|.
+__global__ __launch_bounds__(64) void k_arnoldi(int k, SmallLayout L, double* __restrict__ sm,
+                                                const double* __restrict__ part) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < RED_BLOCKS; b += 64) s += part[b * PART_LD];
+  s = wave_sum(s);
+  if (threadIdx.x != 0) return;
+  const int ld = L.m + 1;
+  double* H = sm + L.H() + (int64_t)k * ld;
+  double* cs = sm + L.cs();
+  double* sn = sm + L.sn();
+  double* g = sm + L.g();
+  double* scal = sm + L.scal();
+  const double hk1 = sqrt(s);
+  for (int i = 0; i <= k; ++i) H[i] = sm[L.h1() + i] + sm[L.h2() + i];
+  H[k + 1] = hk1;
+  for (int i = 0; i < k; ++i) {
+    const double a = H[i], b = H[i + 1];
+    H[i] = cs[i] * a + sn[i] * b;
+    H[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double den = hypot(H[k], H[k + 1]);
+  cs[k] = H[k] / den;
+  sn[k] = H[k + 1] / den;
+  H[k] = den;
+  H[k + 1] = 0.0;
+  g[k + 1] = -sn[k] * g[k];
+  g[k] = cs[k] * g[k];
+  scal[S_EST] = fabs(g[k + 1]);
+  scal[S_HK1] = hk1;
+  scal[S_INV] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_scale(int64_t n, double* __restrict__ w, const double* __restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] *= s[0];
+}
+
+// v0 = r / beta; g = (beta, 0, ..., 0)
+__global__ __launch_bounds__(256) void k_init_cycle(int64_t n, const double* __restrict__ r, double* __restrict__ v0,
+                                                    SmallLayout L, double* __restrict__ sm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double* scal = sm + L.scal();
+  if (i < n) v0[i] = r[i] * scal[S_INVB];
+  if (i <= L.m) sm[L.g() + i] = i == 0 ? scal[S_BETA] : 0.0;
+}
+
+// y = H[0:kk, 0:kk]^{-1} g[0:kk] (upper triangular after the rotations)
+__global__ void k_backsolve(int kk, SmallLayout L, double* __restrict__ sm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int ld = L.m + 1;
+  const double* H = sm + L.H();
+  double* y = sm + L.y();
+  const double* g = sm + L.g();
+  for (int i = kk - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int q = i + 1; q < kk; ++q) s -= H[i + q * ld] * y[q];
+    y[i] = s / H[i + i * ld];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update_x(int64_t n, const double* __restrict__ Z, int64_t ldz, int kk,
+                                                  const double* __restrict__ y, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < kk; ++q) s += Z[q * ldz + i] * y[q];
+  x[i] += s;
+}
+
+__global__ __launch_bounds__(256) void k_fill(int64_t n, double* __restrict__ x, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+}  // namespace cpm

@@ -1,0 +1,231 @@
+// Host construction of the overlapping decomposition (Sections 3, 4, 5):
+// disjoint coordinate partitions, breadth-first overlap layers, local ghost and
+// transmission-node sets, the subsurface closest points of eq. locCP, the
+// conormal term of eq. naConorm and the cross-point weights of Section 5.2.2.
+// Compiled with -ffp-contract=off (see setup_band.cpp).
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "cpm_internal.h"
+
+namespace cpm {
+namespace {
+
+// Recursive coordinate bisection on grid indices: split along the axis of
+// largest index extent (ties x < y < z), nodes ordered by (index on that
+// axis, L); the left floor(n/2) parts receive floor(|S| W_l / W) nodes.
+void rcb(const Band& b, std::vector<int32_t>& idx, int first, int n, const double* w,
+         std::vector<int32_t>& part) {
+  if (n == 1) {
+    for (int32_t q : idx) part[q] = first;
+    return;
+  }
+  int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  for (int32_t q : idx)
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = std::min(mn[a], b.ijk[(size_t)q * 3 + a]);
+      mx[a] = std::max(mx[a], b.ijk[(size_t)q * 3 + a]);
+    }
+  int axis = 0;
+  for (int a = 1; a < 3; ++a)
+    if (mx[a] - mn[a] > mx[axis] - mn[axis]) axis = a;
+  std::sort(idx.begin(), idx.end(), [&](int32_t u, int32_t v) {
+    const int32_t cu = b.ijk[(size_t)u * 3 + axis], cv = b.ijk[(size_t)v * 3 + axis];
+    if (cu != cv) return cu < cv;
+    return b.lin[u] < b.lin[v];
+  });
+  const int nl = n / 2;
+  size_t cut;
+  if (!w) {
+    cut = (idx.size() * (size_t)nl) / (size_t)n;
+  } else {
+    double wl = 0.0, wt = 0.0;
+    for (int q = first; q < first + nl; ++q) wl += w[q];
+    for (int q = first; q < first + n; ++q) wt += w[q];
+    cut = (size_t)std::floor((double)idx.size() * wl / wt);
+  }
+  std::vector<int32_t> left(idx.begin(), idx.begin() + cut), right(idx.begin() + cut, idx.end());
+  idx.clear();
+  idx.shrink_to_fit();
+  rcb(b, left, first, nl, w, part);
+  rcb(b, right, first + nl, n - nl, w, part);
+}
+
+void sort_unique(std::vector<int32_t>& v) {
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+}
+
+}  // namespace
+
+int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const double* weights,
+                        int overlap, int kind, double alpha, double alpha_cross,
+                        std::string& err) {
+  const int64_t na = b.n_act;
+  if (kind != CPM_RAS && kind != CPM_ORAS) { err = "partition: kind must be RAS or ORAS"; return CPM_EINVAL; }
+  if (overlap < 0 || (kind == CPM_ORAS && overlap < 1)) { err = "partition: overlap must be >= 1 for ORAS, >= 0 for RAS"; return CPM_EINVAL; }
+  if (kind == CPM_ORAS && !(alpha > 0 && std::isfinite(alpha))) { err = "partition: ORAS needs a positive finite alpha"; return CPM_EINVAL; }
+  if (!(alpha_cross >= 0) || !std::isfinite(alpha_cross)) { err = "partition: alpha_cross must be >= 0"; return CPM_EINVAL; }
+  if (n_sub < 1 || n_sub > na) { err = "partition: n_sub out of range"; return CPM_EINVAL; }
+  if (method == CPM_PART_OCTANT && n_sub != 8) { err = "partition: octant partition has 8 parts"; return CPM_EINVAL; }
+  if (method != CPM_PART_OCTANT && method != CPM_PART_RCB) { err = "partition: unknown method"; return CPM_EINVAL; }
+  if (weights)
+    for (int q = 0; q < n_sub; ++q)
+      if (!(weights[q] > 0) || !std::isfinite(weights[q])) { err = "partition: weights must be positive"; return CPM_EINVAL; }
+
+  Decomp nd;
+  nd.n_sub = n_sub;
+  nd.kind = kind;
+  nd.overlap = overlap;
+  nd.alpha = alpha;
+  nd.alpha_cross = alpha_cross;
+  nd.part.assign(na, -1);
+  if (method == CPM_PART_OCTANT) {
+    for (int64_t q = 0; q < na; ++q) {
+      const int32_t* x = &b.ijk[q * 3];
+      nd.part[q] = 4 * (x[0] >= b.n[0] / 2) + 2 * (x[1] >= b.n[1] / 2) + (x[2] >= b.n[2] / 2);
+    }
+  } else {
+    std::vector<int32_t> idx(na);
+    for (int64_t q = 0; q < na; ++q) idx[q] = (int32_t)q;
+    rcb(b, idx, 0, n_sub, weights, nd.part);
+  }
+  std::vector<int64_t> count(n_sub, 0);
+  for (int32_t q : nd.part) count[q]++;
+  for (int j = 0; j < n_sub; ++j)
+    if (count[j] == 0) { err = "partition: a part is empty"; return CPM_EINVAL; }
+
+  // Cross points: active nodes whose active neighbours lie in >= 2 other parts.
+  nd.cross.assign(na, 0);
+  for (int64_t q = 0; q < na; ++q) {
+    int32_t seen[6];
+    int ns = 0;
+    for (int e = 0; e < 6; ++e) {
+      const int32_t y = b.nbr[q * 6 + e];
+      if (y >= na) continue;
+      const int32_t py = nd.part[y];
+      if (py == nd.part[q]) continue;
+      bool dup = false;
+      for (int s = 0; s < ns; ++s) dup |= (seen[s] == py);
+      if (!dup) seen[ns++] = py;
+    }
+    nd.cross[q] = ns >= 2;
+  }
+  // Grid nodes within 2 N_O grid units (inclusive) of a cross point.
+  std::vector<uint8_t> near_cross;
+  if (kind == CPM_ORAS && alpha_cross > 0) {
+    near_cross.assign((size_t)(b.n[0] * b.n[1] * b.n[2]), 0);
+    const int R = 2 * overlap;
+    for (int64_t q = 0; q < na; ++q) {
+      if (!nd.cross[q]) continue;
+      const int32_t* x = &b.ijk[q * 3];
+      for (int di = -R; di <= R; ++di)
+        for (int dj = -R; dj <= R; ++dj)
+          for (int dk = -R; dk <= R; ++dk) {
+            if (di * di + dj * dj + dk * dk > R * R) continue;
+            const int64_t I = x[0] + di, J = x[1] + dj, K = x[2] + dk;
+            if (I < 0 || J < 0 || K < 0 || I >= b.n[0] || J >= b.n[1] || K >= b.n[2]) continue;
+            near_cross[(size_t)((I * b.n[1] + J) * b.n[2] + K)] = 1;
+          }
+    }
+  }
+
+  std::vector<std::vector<int32_t>> members(n_sub);
+  for (int64_t q = 0; q < na; ++q) members[nd.part[q]].push_back((int32_t)q);
+  nd.subs.resize(n_sub);
+  const int P1 = b.p + 1, NS = P1 * P1 * P1;
+  std::vector<int> fail(n_sub, 0);
+
+  auto build_one = [&](int j, std::vector<uint8_t>& mark) {
+    Sub& sd = nd.subs[j];
+    sd.tilde = members[j];
+    // Breadth-first overlap layers inside the active set.
+    std::vector<int32_t> sigma = sd.tilde, front = sd.tilde;
+    for (int32_t q : sigma) mark[q] = 1;
+    for (int layer = 0; layer < overlap; ++layer) {
+      std::vector<int32_t> next;
+      for (int32_t q : front)
+        for (int e = 0; e < 6; ++e) {
+          const int32_t y = b.nbr[(size_t)q * 6 + e];
+          if (y < na && !mark[y]) {
+            mark[y] = 1;
+            next.push_back(y);
+          }
+        }
+      sigma.insert(sigma.end(), next.begin(), next.end());
+      front.swap(next);
+    }
+    sort_unique(front);
+    sd.fin = front;
+    sort_unique(sigma);
+    sd.sigma = sigma;
+    // Local ghosts and transmission nodes.
+    std::vector<int32_t> bnd;
+    for (int32_t q : sd.sigma)
+      for (int e = 0; e < 6; ++e) {
+        const int32_t y = b.nbr[(size_t)q * 6 + e];
+        if (y >= na) sd.ghost.push_back(y);
+        else if (!mark[y]) bnd.push_back(y);
+      }
+    sort_unique(sd.ghost);
+    auto add_cols = [&](int32_t row) {
+      for (int a = 0; a < P1 * P1; ++a) {
+        const int32_t first = b.lines[(size_t)row * P1 * P1 + a];
+        for (int c = 0; c < P1; ++c)
+          if (!mark[first + c]) bnd.push_back(first + c);
+      }
+    };
+    for (int32_t q : sd.sigma) add_cols(q);
+    for (int32_t q : sd.ghost) add_cols(q);
+    sort_unique(bnd);
+    sd.bnd = bnd;
+    (void)NS;
+    for (int32_t q : sd.sigma) mark[q] = 0;
+    if (kind != CPM_ORAS) return;
+    const size_t nbd = sd.bnd.size();
+    sd.xstar.resize(nbd);
+    sd.s.resize(nbd);
+    sd.alpha.resize(nbd);
+    if (nbd && sd.fin.empty()) { fail[j] = 1; return; }
+    for (size_t q = 0; q < nbd; ++q) {
+      const int32_t bn = sd.bnd[q];
+      const double* xb = &b.xyz[(size_t)bn * 3];
+      double best = INFINITY;
+      int32_t arg = -1;
+      for (int32_t f : sd.fin) {  // ascending band index: the first minimum is kept
+        const double* c = &b.cp[(size_t)f * 3];
+        const double d0 = xb[0] - c[0], d1 = xb[1] - c[1], d2 = xb[2] - c[2];
+        const double dd = (d0 * d0 + d1 * d1) + d2 * d2;
+        if (dd < best) { best = dd; arg = f; }
+      }
+      sd.xstar[q] = arg;
+      const double* y = &b.cp[(size_t)arg * 3];
+      const double* nr = &b.nrm[(size_t)arg * 3];
+      const double d0 = xb[0] - y[0], d1 = xb[1] - y[1], d2 = xb[2] - y[2];
+      const double dn = (d0 * nr[0] + d1 * nr[1]) + d2 * nr[2];
+      const double t0 = d0 - dn * nr[0], t1 = d1 - dn * nr[1], t2 = d2 - dn * nr[2];
+      sd.s[q] = std::sqrt((t0 * t0 + t1 * t1) + t2 * t2);
+      sd.alpha[q] = alpha;
+      if (!near_cross.empty()) {
+        const int32_t* x = &b.ijk[(size_t)bn * 3];
+        if (near_cross[(size_t)(((int64_t)x[0] * b.n[1] + x[1]) * b.n[2] + x[2])]) sd.alpha[q] = alpha_cross;
+      }
+    }
+  };
+
+  const int nth = std::max(1, std::min<int>(n_sub, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&, t]() {
+      std::vector<uint8_t> mark(na, 0);
+      for (int j = t; j < n_sub; j += nth) build_one(j, mark);
+    });
+  for (auto& th : pool) th.join();
+  for (int j = 0; j < n_sub; ++j)
+    if (fail[j]) { err = "partition: subdomain has transmission nodes but no final overlap layer"; return CPM_EINVAL; }
+  d = std::move(nd);
+  return CPM_OK;
+}
+
+}  // namespace cpm

@@ -1,0 +1,123 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-side
+set-up (band, partitions, Schwarz node sets) equals the oracle bit for bit.
+No device calls: contexts are host-only (device = -1)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import cpm_inputs as ci
+import oracle
+from oracle import schwarz
+import paper_1909_08734_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "cpm.h")).read()
+    return sorted(set(re.findall(r"\b(cpm_[a-z_]+)\s*\(", text)) - {"cpm_cp_fn"})
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(P.binding.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(P.EXPORTED) == names
+
+
+CASES = [
+    (ci.Sphere(), 0.1, 3, "rcb", 8, 2),
+    (ci.Sphere(), 0.1, 3, "octant", 8, 2),
+    (ci.Torus(1.0, 0.4), 0.05, 3, "rcb", 12, 3),
+    (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08, 2, "wrcb", 6, 1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("kind", ["RAS", "ORAS"])
+def test_host_setup_matches_oracle(case, kind):
+    surf, h, p, method, n, no = CASES[case]
+    b = oracle.build_band(surf, h, p, [-2.0] * 3, [2.0] * 3)
+    ctx = P.Context(-1)
+    ctx.build_band(surf, h, p)
+    na, ng, shape = ctx.band_sizes()
+    assert (na, ng) == (b.n_act, b.n_ghost) and shape == b.shape
+    arr = ctx.band_arrays(p)
+    np.testing.assert_array_equal(arr["lin"], b.lin)
+    np.testing.assert_array_equal(arr["nbr"], b.nbr)
+    np.testing.assert_array_equal(arr["base"], b.base)
+    np.testing.assert_array_equal(arr["cp"], b.cp)
+    np.testing.assert_allclose(arr["wts"], b.wts, rtol=0, atol=1e-15)
+    ctx.build_operator(1.0)
+    weights = ci.wrcb_weights(n, seed=2) if method == "wrcb" else None
+    if method == "octant":
+        opart = oracle.octant_partition(b)
+        ctx.partition(P.PART_OCTANT, 8, None, no, getattr(P, kind), 3.0, 30.0)
+    else:
+        opart = oracle.rcb_partition(b, n, weights=weights)
+        ctx.partition(P.PART_RCB, n, weights, no, getattr(P, kind), 3.0, 30.0)
+    nsub, part, cross = ctx.partition_info()
+    dec = schwarz.decompose(b, opart, no, kind, alpha=3.0, alpha_cross=30.0)
+    assert nsub == len(dec.subs)
+    np.testing.assert_array_equal(part, opart)
+    np.testing.assert_array_equal(cross, dec.cross)
+    for j in range(nsub):
+        s = ctx.subdomain(j)
+        o = dec.subs[j]
+        for k in ("tilde", "sigma", "final", "ghost", "bnd"):
+            np.testing.assert_array_equal(s[k], getattr(o, k), err_msg=f"{k} of part {j}")
+        if kind == "ORAS":
+            np.testing.assert_array_equal(s["xstar"], o.xstar)
+            np.testing.assert_array_equal(s["alpha"], o.alpha)
+            np.testing.assert_allclose(s["s"], o.s, rtol=0, atol=1e-15)
+
+
+def test_state_machine_and_argument_errors():
+    ctx = P.Context(-1)
+    with pytest.raises(P.CpmError) as e:
+        ctx.build_operator(1.0)
+    assert e.value.code == P.ESTATE
+    with pytest.raises(P.CpmError) as e:
+        ctx.build_band(ci.Sphere(), 0.1, 4)
+    assert e.value.code == P.EINVAL
+    with pytest.raises(P.CpmError) as e:
+        ctx.build_band(ci.Sphere(), 0.1, 3, lo=(-1.2,) * 3, hi=(1.2,) * 3)  # ghosts leave the box
+    assert e.value.code == P.EINVAL
+
+    class Broken:
+        def cp(self, x):
+            raise RuntimeError("no")
+    with pytest.raises(P.CpmError) as e:
+        ctx.build_band(Broken(), 0.1, 3)
+    assert e.value.code == P.ECALLBACK
+    ctx.build_band(ci.Sphere(), 0.2, 3)
+    with pytest.raises(P.CpmError) as e:
+        ctx.partition(P.PART_RCB, 4, None, 2, P.RAS)
+    assert e.value.code == P.ESTATE
+    for bad_c in (0.0, -1.0, float("nan")):
+        with pytest.raises(P.CpmError) as e:
+            ctx.build_operator(bad_c)
+        assert e.value.code == P.EINVAL
+    ctx.build_operator(1.0)
+    with pytest.raises(P.CpmError) as e:
+        ctx.partition(P.PART_OCTANT, 4, None, 2, P.RAS)
+    assert e.value.code == P.EINVAL
+    with pytest.raises(P.CpmError) as e:
+        ctx.partition(P.PART_RCB, 4, None, 0, P.ORAS, 2.0)  # ORAS needs overlap >= 1
+    assert e.value.code == P.EINVAL
+    with pytest.raises(P.CpmError) as e:
+        ctx.partition(P.PART_RCB, 4, None, 2, P.ORAS, 0.0)  # and alpha > 0
+    assert e.value.code == P.EINVAL
+    with pytest.raises(P.CpmError) as e:
+        ctx.factor(P.FP64)
+    assert e.value.code == P.ESTATE
+    ctx.partition(P.PART_RCB, 4, None, 2, P.ORAS, 2.0)
+    with pytest.raises(P.CpmError) as e:
+        ctx.factor(P.FP64)  # host-only context
+    assert e.value.code == P.EDEVICE

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs. Floating-point bars:
+* operator apply: 1e-12 relative (same sums, different order);
+* FP64 local solves / M^{-1} v: 1e-9 relative (cond(A_j) * eps with margin);
+* FP32 local solves: 2e-3 relative (cond(A_j) ~ 1e3 times float eps, margin);
+* final solution: 1e-8 relative to the direct solution (both at tol 1e-12).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import cpm_inputs as ci
+import oracle
+from oracle import schwarz
+import paper_1909_08734_amd as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("prec,kb", [(P.FP64, 32), (P.FP64, 13), (P.FP32, 32), (P.FP32, 7)])
+def test_matrix_core_tile(prec, kb):
+    say("tile selftest", prec, kb)
+    rng = np.random.default_rng(kb)
+    a = rng.standard_normal((64, kb))
+    b = rng.standard_normal((kb, 64))
+    c = rng.standard_normal((64, 64))
+    if prec == P.FP32:
+        a, b, c = (x.astype(np.float32).astype(np.float64) for x in (a, b, c))
+    got = P.selftest_tile(a, b, c, prec)
+    want = c - a @ b
+    assert rel(got, want) < (1e-14 if prec == P.FP64 else 1e-5)
+
+
+SURF = {"sphere": (ci.Sphere(), 0.1), "torus": (ci.Torus(1.0, 0.4), 0.05),
+        "offsphere": (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08)}
+
+
+@pytest.mark.parametrize("name,p", [("sphere", 3), ("torus", 3), ("offsphere", 2)])
+def test_operator_apply(name, p):
+    say("operator", name, p)
+    surf, h = SURF[name]
+    b = oracle.build_band(surf, h, p, [-2.0] * 3, [2.0] * 3)
+    c = 0.7
+    A = oracle.stabilized_operator(b, c)
+    ctx = P.Context(0)
+    ctx.build_band(surf, h, p)
+    ctx.build_operator(c)
+    x = np.random.default_rng(1).standard_normal(b.n_act)
+    y = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
+    ctx.apply_operator(dev(x), y)
+    assert rel(y.cpu().numpy(), A @ x) < 1e-12
+    ctx.close()
+
+
+def _setup(name, p, method, n, no, kind, alpha, alpha_cross, c=1.0):
+    surf, h = SURF[name]
+    b = oracle.build_band(surf, h, p, [-2.0] * 3, [2.0] * 3)
+    part = oracle.octant_partition(b) if method == "octant" else oracle.rcb_partition(b, n)
+    dec = schwarz.decompose(b, part, no, kind, alpha=alpha, alpha_cross=alpha_cross)
+    ctx = P.Context(0)
+    ctx.build_band(surf, h, p)
+    ctx.build_operator(c)
+    ctx.partition(P.PART_OCTANT if method == "octant" else P.PART_RCB, n, None, no, getattr(P, kind),
+                  alpha, alpha_cross)
+    return b, dec, ctx
+
+
+PRECOND_CASES = [
+    ("sphere", 3, "octant", 8, 2, "RAS", 0.0, 0.0),
+    ("sphere", 3, "rcb", 7, 2, "ORAS", 3.16, 0.0),
+    ("torus", 3, "rcb", 16, 3, "ORAS", 4.47, 20.0),
+    ("offsphere", 2, "rcb", 5, 1, "ORAS", 2.0, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(PRECOND_CASES)))
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_preconditioner_apply(case, prec):
+    args = PRECOND_CASES[case]
+    say("precond", args, prec)
+    b, dec, ctx = _setup(*args)
+    c = 1.0
+    ctx.factor(prec)
+    # restricted local solution operator of one subdomain against the oracle's local matrix
+    j = len(dec.subs) // 2
+    sd = dec.subs[j]
+    Aj = schwarz.local_matrix(b, dec, j, c)
+    inv = np.linalg.inv(Aj)
+    pos = np.searchsorted(sd.sigma, sd.tilde)
+    W_ref = inv[np.ix_(pos, np.arange(len(sd.sigma)))]
+    W = ctx.factor_export(j)
+    tol = 1e-9 if prec == P.FP64 else 2e-3
+    assert rel(W, W_ref) < tol
+    # whole preconditioner on a random vector
+    M = schwarz.Preconditioner(b, dec, c)
+    v = np.random.default_rng(3).standard_normal(b.n_act)
+    z = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
+    ctx.apply_precond(dev(v), z)
+    assert rel(z.cpu().numpy(), M.apply(v)) < tol
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def direct_cfg1():
+    surf, h = SURF["sphere"]
+    b = oracle.build_band(surf, h, 3, [-2.0] * 3, [2.0] * 3)
+    A = oracle.stabilized_operator(b, 1.0)
+    f = ci.rhs_sphere_y20(b.cp[: b.n_act], 1.0)
+    return b, A, f, np.linalg.solve(A.toarray(), f)
+
+
+@pytest.mark.parametrize("kind,prec", [("RAS", P.FP64), ("ORAS", P.FP64), ("ORAS", P.FP32)])
+def test_solve_matches_direct_solution(direct_cfg1, kind, prec):
+    say("solve cfg1", kind, prec)
+    b, A, f, u_ref = direct_cfg1
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), 0.1, 3)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_OCTANT, 8, None, 2, getattr(P, kind), 1 / np.sqrt(0.1), 0.0)
+    ctx.factor(prec)
+    u, info, rc = ctx.solve(f, tol=1e-12, max_iter=500, restart=30)
+    assert rc == P.OK and info[0]["relres_true"] <= 1e-12
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-8
+    # the oracle's own preconditioned FGMRES takes about as many iterations
+    dec = schwarz.decompose(b, oracle.octant_partition(b), 2, kind, alpha=1 / np.sqrt(0.1))
+    _, oinfo = oracle.fgmres(lambda x: A @ x, f, schwarz.Preconditioner(b, dec, 1.0).apply, tol=1e-12)
+    slack = 2 if prec == P.FP64 else 8
+    assert abs(info[0]["iters"] - oinfo["iters"]) <= slack, (info, oinfo["iters"])
+    # device-pointer entry point gives the same answer
+    fu = dev(np.stack([f, 2 * f]))
+    uu = torch.zeros_like(fu)
+    infos, rc = ctx.solve_device(fu, uu, tol=1e-12, max_iter=500, restart=30)
+    got = uu.cpu().numpy()
+    np.testing.assert_allclose(got[0], u, rtol=0, atol=1e-13 * np.abs(u).max())
+    np.testing.assert_allclose(got[1], 2 * u, rtol=0, atol=1e-12 * np.abs(u).max())
+    ctx.close()
+
+
+def test_solve_edge_cases(direct_cfg1):
+    say("edge cases")
+    b, A, f, u_ref = direct_cfg1
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), 0.1, 3)
+    ctx.build_operator(1.0)
+    # one subdomain: M = A^{-1}, GMRES converges in one iteration
+    ctx.partition(P.PART_RCB, 1, None, 1, P.RAS)
+    ctx.factor(P.FP64)
+    u, info, rc = ctx.solve(f, tol=1e-12)
+    assert info[0]["iters"] == 1 and np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-10
+    ctx.partition(P.PART_RCB, 5, None, 2, P.ORAS, 3.0, 30.0)
+    with pytest.raises(P.CpmError) as e:
+        ctx.solve(f)  # new partition: factor again first
+    assert e.value.code == P.ESTATE
+    ctx.factor(P.FP64)
+    u, info, rc = ctx.solve(np.zeros_like(f))
+    assert rc == P.OK and info[0]["iters"] == 0 and not u.any()
+    bad = f.copy()
+    bad[17] = np.nan
+    with pytest.raises(P.CpmError) as e:
+        ctx.solve(bad)
+    assert e.value.code == P.EINVAL
+    u, info, rc = ctx.solve(f, tol=1e-15, max_iter=3, restart=2)
+    assert rc == P.ENOTCONV and info[0]["iters"] == 3 and info[0]["cycles"] == 2
+    for bad_args in ({"tol": 0.0}, {"max_iter": 0}, {"restart": 65}):
+        with pytest.raises(P.CpmError) as e:
+            ctx.solve(f, **bad_args)
+        assert e.value.code == P.EINVAL
+    ctx.close()
+
+
+def test_sphere_h0025_rcb64_oras_sampled():
+    """The benchmark configuration: unit sphere h = 0.025, 64 RCB parts, N_O = 3,
+    ORAS with alpha = h^{-1/2}. Three subdomains are checked against the oracle's
+    dense local solves; the full solve is checked by the oracle's residual."""
+    h = 0.025
+    alpha = h ** -0.5
+    say("sphere h=0.025 oracle set-up")
+    b = oracle.build_band(ci.Sphere(), h, 3, [-2.0] * 3, [2.0] * 3)
+    A = oracle.stabilized_operator(b, 1.0)
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, 64), 3, "ORAS", alpha=alpha)
+    sample = [0, 37, 63]
+    M = schwarz.Preconditioner(b, dec, 1.0, subs=sample)
+    v = np.random.default_rng(11).standard_normal(b.n_act)
+    z_ref = M.apply(v)
+    rows = np.concatenate([dec.subs[j].tilde for j in sample])
+    f, _ = ci.rhs_sphere_random_sh(b.cp[: b.n_act], 1.0, seed=1)
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), h, 3)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_RCB, 64, None, 3, P.ORAS, alpha, 0.0)
+    for prec, tol in ((P.FP64, 1e-9), (P.FP32, 2e-3)):
+        say("sphere h=0.025 factor", prec)
+        ctx.factor(prec)
+        z = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(dev(v), z)
+        assert rel(z.cpu().numpy()[rows], z_ref[rows]) < tol
+        say("sphere h=0.025 solve", prec)
+        u, info, rc = ctx.solve(f, tol=1e-10, max_iter=400, restart=30)
+        assert rc == P.OK
+        assert np.linalg.norm(f - A @ u) / np.linalg.norm(f) <= 1.05e-10
+    ctx.close()
