@@ -4,8 +4,10 @@ Workload (the single-GPU benchmark configuration): unit sphere, closest point
 x/|x|, grid h = 0.025 on [-2, 2]^3, tricubic extension (N_A = 139,886 band
 nodes), c = 1, f = sum_{l<=4,|m|<=l} (c + l(l+1)) a_lm Y_l^m(CP(x)) with
 a_lm ~ N(0,1) (a new seed per solve), 64 recursive-coordinate-bisection
-subdomains, overlap 3, ORAS with alpha = h^{-1/2}, FGMRES(30) to a true
-relative residual of 1e-8, x0 = 0. A step is one full solve with the factors
+subdomains, overlap 3, ORAS with the Robin weight swept over {h^{-1}, h^{-1/2}}
+(the latter with the cross-point weight alpha_x = h^{-1} of Section 5.2.2, without
+which restarted GMRES stagnates at 64 subdomains), FGMRES(30) to a true relative
+residual of 1e-8, x0 = 0. The headline `value` is alpha = h^{-1}. A step is one full solve with the factors
 resident in HBM; factorisation is timed separately. Both local-factor
 precisions are measured: `value` is the plain FP64 form, the FP32-factor form
 (FP64 Krylov) is reported beside it.
@@ -31,7 +33,7 @@ H = 0.025
 C_SHIFT = 1.0
 N_SUB = 64
 OVERLAP = 3
-ALPHA = H ** -0.5
+ALPHAS = (("alpha_1/h", 1.0 / H, 0.0), ("alpha_h^-1/2_cross_1/h", H ** -0.5, 1.0 / H))
 TOL = 1e-8
 RESTART = 30
 HBM_PEAK_GBS = 8000.0
@@ -100,71 +102,76 @@ def run_gpu(args):
     t0 = time.time()
     ctx.build_band(ci.Sphere(), H, 3)
     ctx.build_operator(C_SHIFT)
-    ctx.partition(P.PART_RCB, N_SUB, None, OVERLAP, P.ORAS, ALPHA, 0.0)
     na, ng, _ = ctx.band_sizes()
     cp = ctx.band_arrays(3)["cp"][:na]
-    log(f"set-up {time.time() - t0:.1f}s  N_A={na} N_G={ng}")
+    log(f"band {time.time() - t0:.1f}s  N_A={na} N_G={ng}")
     nrhs = args.warmup + args.steps
     F = np.stack([ci.rhs_sphere_random_sh(cp, C_SHIFT, seed=1 + q)[0] for q in range(nrhs)])
     f_dev = torch.from_numpy(F).cuda()
     u_dev = torch.zeros_like(f_dev)
     torch.cuda.synchronize()
     res = {}
-    for prec_name, prec, esz in (("fp64", P.FP64, 8), ("fp32", P.FP32, 4)):
-        ctx.set_timing(True)
+    for a_name, alpha, alpha_x in ALPHAS:
         t0 = time.time()
-        ctx.factor(prec)
-        factor_s = time.time() - t0
-        gemm_ms, gemm_n = ctx.kernel_time(P.TIMER_LU_GEMM)
-        ctx.set_timing(False)
-        log(f"{prec_name}: factor {factor_s:.2f}s (trailing update {gemm_ms:.0f} ms in {gemm_n} launches)")
-        for q in range(args.warmup):
-            ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
-        ctx.set_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = []
-        for q in range(args.warmup, nrhs):
-            info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
-            if rc != P.OK:
-                raise RuntimeError(f"solve did not converge: {info}")
-            infos.append(info[0])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        pre_ms, pre_n = ctx.kernel_time(P.TIMER_PRECOND)
-        ext_ms, ext_n = ctx.kernel_time(P.TIMER_EXTEND)
-        st_ms, st_n = ctx.kernel_time(P.TIMER_STENCIL)
-        ctx.set_timing(False)
-        lat = np.array([i["ms"] for i in infos])
-        its = np.array([i["iters"] for i in infos])
-        bytes_apply, w_elems = precond_bytes(ctx, N_SUB, esz)
-        avg_pre = pre_ms / max(pre_n, 1)
-        flops = lu_flops(ctx, N_SUB, True)
-        res[prec_name] = {
-            "solves_per_s": args.steps / wall,
-            "ms_per_solve": 1e3 * wall / args.steps,
-            "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)),
-            "iters_mean": float(its.mean()),
-            "relres_true_max": float(max(i["relres_true"] for i in infos)),
-            "factor_s": factor_s,
-            "lu_update_tflops": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None,
-            "precond_ms_avg": avg_pre,
-            "precond_launches": pre_n,
-            "precond_bytes": bytes_apply,
-            "precond_GBs": bytes_apply / (avg_pre * 1e-3) / 1e9,
-            "extend_ms_avg": ext_ms / max(ext_n, 1),
-            "stencil_ms_avg": st_ms / max(st_n, 1),
-            "footprint_GB": ctx.footprint_bytes() / 1e9,
-        }
-        log(f"{prec_name}: {json.dumps(res[prec_name])}")
-        if args.check:
-            import oracle
-            b = oracle.build_band(ci.Sphere(), H, 3, [-2.0] * 3, [2.0] * 3)
-            A = oracle.stabilized_operator(b, C_SHIFT)
-            u = u_dev[nrhs - 1].cpu().numpy()
-            r = np.linalg.norm(F[nrhs - 1] - A @ u) / np.linalg.norm(F[nrhs - 1])
-            log(f"{prec_name}: oracle residual of the last solve {r:.3e}")
+        ctx.partition(P.PART_RCB, N_SUB, None, OVERLAP, P.ORAS, alpha, alpha_x)
+        log(f"{a_name}: partition {time.time() - t0:.1f}s")
+        res[a_name] = {}
+        for prec_name, prec, esz in (("fp64", P.FP64, 8), ("fp32", P.FP32, 4)):
+            ctx.set_timing(True)
+            t0 = time.time()
+            ctx.factor(prec)
+            factor_s = time.time() - t0
+            gemm_ms, gemm_n = ctx.kernel_time(P.TIMER_LU_GEMM)
+            ctx.set_timing(False)
+            for q in range(args.warmup):
+                ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
+            ctx.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = []
+            for q in range(args.warmup, nrhs):
+                info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
+                if rc != P.OK:
+                    raise RuntimeError(f"solve did not converge: {info}")
+                infos.append(info[0])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            pre_ms, pre_n = ctx.kernel_time(P.TIMER_PRECOND)
+            ext_ms, ext_n = ctx.kernel_time(P.TIMER_EXTEND)
+            st_ms, st_n = ctx.kernel_time(P.TIMER_STENCIL)
+            ctx.set_timing(False)
+            lat = np.array([i["ms"] for i in infos])
+            its = np.array([i["iters"] for i in infos])
+            bytes_apply, _ = precond_bytes(ctx, N_SUB, esz)
+            avg_pre = pre_ms / max(pre_n, 1)
+            flops = lu_flops(ctx, N_SUB, True)
+            r = {
+                "solves_per_s": args.steps / wall,
+                "ms_per_solve": 1e3 * wall / args.steps,
+                "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)),
+                "iters_mean": float(its.mean()),
+                "relres_true_max": float(max(i["relres_true"] for i in infos)),
+                "factor_s": factor_s,
+                "lu_update_ms": gemm_ms,
+                "lu_update_tflops": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None,
+                "precond_ms_avg": avg_pre,
+                "precond_launches": pre_n,
+                "precond_bytes": bytes_apply,
+                "precond_GBs": bytes_apply / (avg_pre * 1e-3) / 1e9,
+                "extend_ms_avg": ext_ms / max(ext_n, 1),
+                "stencil_ms_avg": st_ms / max(st_n, 1),
+                "footprint_GB": ctx.footprint_bytes() / 1e9,
+            }
+            res[a_name][prec_name] = r
+            log(f"{a_name} {prec_name}: {json.dumps(r)}")
+            if args.check:
+                import oracle
+                b = oracle.build_band(ci.Sphere(), H, 3, [-2.0] * 3, [2.0] * 3)
+                A = oracle.stabilized_operator(b, C_SHIFT)
+                u = u_dev[nrhs - 1].cpu().numpy()
+                rr = np.linalg.norm(F[nrhs - 1] - A @ u) / np.linalg.norm(F[nrhs - 1])
+                log(f"{a_name} {prec_name}: oracle residual of the last solve {rr:.3e}")
     ctx.close()
     return res, na
 
@@ -184,7 +191,9 @@ def cpu_baseline(gpu_iters):
         cores = os.cpu_count()
     b = oracle.build_band(ci.Sphere(), H, 3, [-2.0] * 3, [2.0] * 3)
     A = oracle.stabilized_operator(b, C_SHIFT)
-    dec = schwarz.decompose(b, oracle.rcb_partition(b, N_SUB), OVERLAP, "ORAS", alpha=ALPHA)
+    _, alpha, alpha_x = ALPHAS[0]
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, N_SUB), OVERLAP, "ORAS", alpha=alpha,
+                            alpha_cross=alpha_x)
     sample = [0, 21, 42, 63]
     t0 = time.perf_counter()
     M = schwarz.Preconditioner(b, dec, C_SHIFT, subs=sample)
@@ -228,8 +237,12 @@ def main():
         sys.exit(2)
     res, na = run_gpu(args)
     src = kernel_source_hash()
-    r64 = res["fp64"]
-    r32 = res["fp32"]
+    head = ALPHAS[0][0]
+    r64 = res[head]["fp64"]
+    r32 = res[head]["fp32"]
+    sweep = {a: {p: {k: v[k] for k in ("solves_per_s", "p50_ms", "p99_ms", "iters_mean", "factor_s",
+                                        "precond_GBs", "relres_true_max")}
+                 for p, v in d.items()} for a, d in res.items()}
     out = {
         "metric": "ORAS-GMRES solves/s to rel.res 1e-8 (FP32 vs FP64 factors); p50/p99 latency",
         "value": r64["solves_per_s"],
@@ -244,12 +257,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "sphere_h0.025_rcb64_oras", "surface": "unit sphere", "h": H, "N_A": na,
-                   "degree": 3, "c": C_SHIFT, "n_sub": N_SUB, "overlap": OVERLAP, "alpha": ALPHA,
-                   "restart": RESTART, "tol": TOL, "rhs": "seeded random spherical harmonics l<=4"},
+                   "degree": 3, "c": C_SHIFT, "n_sub": N_SUB, "overlap": OVERLAP, "alpha": ALPHAS[0][1],
+                   "alpha_cross": ALPHAS[0][2], "restart": RESTART, "tol": TOL,
+                   "rhs": "seeded random spherical harmonics l<=4"},
         "p50_ms": r64["p50_ms"],
         "p99_ms": r64["p99_ms"],
         "fp64_factors": r64,
         "fp32_factors": dict(r32, speedup_vs_fp64=r32["solves_per_s"] / r64["solves_per_s"]),
+        "alpha_sweep": sweep,
         "roofline": {
             "kernel": "k_precond<double> (restricted local solves, eq. algRAS)",
             "bound": "hbm",
@@ -260,6 +275,7 @@ def main():
             "traffic": pmc_traffic("fp64", src),
             "algorithmic_bytes_per_launch": r64["precond_bytes"],
             "avg_launch_ms": r64["precond_ms_avg"],
+            "kernel_source_hash": src,
         },
     }
     if not args.no_cpu_baseline:

@@ -10,13 +10,14 @@ Node sets per subdomain j (Section 4.1, 4.2):
 * B_j (the active part of Sigma_j^BC): active nodes outside Sigma_j that are FD
   neighbours of Sigma_j or columns of the extension rows of Sigma_j u Sigma_j^G.
 
-Local operator (Section 5, eq. localOP):
+Local operator (Section 5, eq. localOP), taken literally:
   A_j = (c + 2d/h^2) I - (2d/h^2 + Delta_j^h) [E_j ; T_j]
-Rows of Sigma_j follow this formula with the local extension [E_j; T_j]
-(rows of E for Sigma_j u Sigma_j^G, rows T_j for B_j). Rows of B_j are
-transmission rows  sigma (u_b - (T_j u)_b) = 0  with zero right-hand side,
-sigma = c + 2d/h^2 a pure row scale.
-* RAS (Dirichlet, Section 5.1): T_j = [0 I], so u_b = 0; the B unknowns are
+with the local extension [E_j; T_j] (rows of E for Sigma_j u Sigma_j^G, rows
+T_j for B_j) and the local 7-point Laplacian Delta_j^h, which has rows only at
+Sigma_j (the stencils of B_j nodes are not complete in the local problem).
+So the rows of B_j read (c + 2d/h^2) u_b - (2d/h^2) (T_j u)_b = 0, with zero
+right-hand side (Section 5).
+* RAS (Dirichlet, Section 5.1): T_j = [0 I], so c u_b = 0; the B unknowns are
   identically zero and are dropped (local size |Sigma_j|).
 * ORAS (Robin, Section 5.2, eq. robfo): (T_j u)_b = u(CP_{S_j}(x_b)) / (1 + alpha_b d_b.q_b),
   where CP_{S_j}(x_b) is the closest point among Lambda_j = CP(F_j)
@@ -188,9 +189,10 @@ def local_matrix(band, dec, j, c):
     top = sig * I_mu - ((6.0 / h2) * sel + lap) @ ext
 
     if kind == ORAS:
+        # B rows: Delta_j^h has no row there, leaving (c + 6/h^2) u_b - (6/h^2) (T_j u)_b
         I_bu = sp.csr_matrix((np.ones(nbnd), (np.arange(nbnd), m + np.arange(nbnd))),
                              shape=(nbnd, n_unk))
-        bot = sig * (I_bu - T)
+        bot = sig * I_bu - (6.0 / h2) * T
         A = sp.vstack([top, bot]).toarray()
     else:
         A = top.toarray()[:, :m]

@@ -145,10 +145,11 @@ __global__ __launch_bounds__(256) void k_precond(const SubDesc* __restrict__ des
 //   [ R~_j          0    ]      R~_j: selects Sigma~_j
 // stored row-major. Eliminating the first n_j columns leaves -W_j in the
 // lower-right block. Interior rows: (c + 6/h^2) u_x - (1/h^2) sum over the FD
-// neighbours of their extended value: E row for Sigma_j / ghost neighbours,
-// the unknown u_b itself for a neighbour in B_j (ORAS; equal to its Robin
-// extension by the B row) or 0 (RAS). B rows (ORAS):
-// sigma u_b - sigma/(1 + alpha_b s_b) E[x*(b)] u = 0, sigma = c + 6/h^2.
+// neighbours of their extended value: the E row for Sigma_j and ghost
+// neighbours, the Robin row T_b = E[x*(b)] / (1 + alpha_b s_b) (eq. robfo) for
+// a neighbour in B_j (ORAS), 0 for RAS (T_j = [0 I] with u_b = 0). B rows
+// (ORAS), where the local Laplacian has no row:
+// (c + 6/h^2) u_b - (6/h^2) T_b u = 0.
 // Column lookup: binary search of the band index in the sorted unknown list.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int local_pos(const int32_t* __restrict__ srt, const int32_t* __restrict__ pos,
@@ -202,8 +203,9 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
       const int32_t y = nbr[e * na + x];
       if (y < na) {
         const int q = local_pos(srt, ps, d.n, y);
-        if (q >= d.m) {  // ORAS transmission node
-          row[q] = (T)((double)row[q] - ih2);
+        if (q >= d.m) {  // ORAS transmission node: its Robin extension row
+          const int32_t k = d.u_off + q;
+          add_ext(bx[k], ih2 / (1.0 + ba[k] * bs[k]));
           continue;
         }
         if (q < 0) continue;  // RAS: u_b = 0
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
   } else if (r < d.n) {
     const int32_t k = d.u_off + r;
     row[r] = (T)((double)row[r] + diag);
-    if (oras) add_ext(bx[k], diag / (1.0 + ba[k] * bs[k]));
+    if (oras) add_ext(bx[k], 6.0 * ih2 / (1.0 + ba[k] * bs[k]));
   } else {
     row[tilde_pos[d.t_off + (r - d.n)]] = (T)1;
   }
@@ -343,7 +345,8 @@ __global__ __launch_bounds__(256) void k_lu_swap_trsm(const SubDesc* __restrict_
 // Trailing update A22 -= L21 U12 on matrix cores. 64x64 tile per block of 4
 // waves, each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K = panel width.
 // 16x16x4 operand layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
-// j + 16k, D[i][j] in lane j + 16(i/4), element i%4.
+// j + 16k. Result D[i][j], j = lane % 16: for f32 element e of lane l holds
+// row 4(l/16) + e; for f64 it holds row l/16 + 4e (measured on gfx950).
 __device__ __forceinline__ d4 mfma_16x16x4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -353,9 +356,15 @@ __device__ __forceinline__ f4 mfma_16x16x4(float a, float b, f4 c) {
 template <typename T>
 struct Acc4;
 template <>
-struct Acc4<double> { typedef d4 type; };
+struct Acc4<double> {
+  typedef d4 type;
+  __device__ static int row(int lk, int e) { return lk + 4 * e; }
+};
 template <>
-struct Acc4<float> { typedef f4 type; };
+struct Acc4<float> {
+  typedef f4 type;
+  __device__ static int row(int lk, int e) { return 4 * lk + e; }
+};
 
 constexpr int GEMM_TILE = 64;
 
@@ -386,7 +395,7 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int rr = r0 + wr + bi * 16 + 4 * lk + i, cc = c0 + wc + bj * 16 + li;
+        const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
         acc[bi][bj][i] = (rr < rows && cc < cols) ? a[(int64_t)rr * lda + cc] : (T)0;
       }
   const int ksteps = (kb + 3) >> 2;
@@ -407,7 +416,7 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int rr = r0 + wr + bi * 16 + 4 * lk + i, cc = c0 + wc + bj * 16 + li;
+        const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
         if (rr < rows && cc < cols) a[(int64_t)rr * lda + cc] = acc[bi][bj][i];
       }
 }

@@ -152,6 +152,25 @@ def test_solve_matches_direct_solution(direct_cfg1, kind, prec):
     ctx.close()
 
 
+def test_restarted_solve_follows_oracle(direct_cfg1):
+    # short restart cycles: the restart path (update, true residual, new basis) is exercised
+    say("restarted solve")
+    b, A, f, u_ref = direct_cfg1
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), 0.1, 3)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_RCB, 8, None, 1, P.ORAS, 3.0, 30.0)
+    ctx.factor(P.FP64)
+    u, info, rc = ctx.solve(f, tol=1e-12, max_iter=400, restart=5)
+    assert rc == P.OK and info[0]["cycles"] > 2
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-8
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, 8), 1, "ORAS", alpha=3.0, alpha_cross=30.0)
+    _, oinfo = oracle.fgmres(lambda x: A @ x, f, schwarz.Preconditioner(b, dec, 1.0).apply, tol=1e-12,
+                             restart=5, max_iter=400)
+    assert abs(info[0]["iters"] - oinfo["iters"]) <= 3, (info, oinfo["iters"])
+    ctx.close()
+
+
 def test_solve_edge_cases(direct_cfg1):
     say("edge cases")
     b, A, f, u_ref = direct_cfg1
@@ -184,16 +203,19 @@ def test_solve_edge_cases(direct_cfg1):
     ctx.close()
 
 
-def test_sphere_h0025_rcb64_oras_sampled():
+@pytest.mark.parametrize("alpha_pow,cross", [(1.0, False), (0.5, True)])
+def test_sphere_h0025_rcb64_oras_sampled(alpha_pow, cross):
     """The benchmark configuration: unit sphere h = 0.025, 64 RCB parts, N_O = 3,
-    ORAS with alpha = h^{-1/2}. Three subdomains are checked against the oracle's
-    dense local solves; the full solve is checked by the oracle's residual."""
+    ORAS with alpha = h^{-1} or alpha = h^{-1/2} with the cross-point weight
+    alpha_x = h^{-1}. Three subdomains are checked against the oracle's dense
+    local solves; the full solve is checked by the oracle's residual."""
     h = 0.025
-    alpha = h ** -0.5
-    say("sphere h=0.025 oracle set-up")
+    alpha = h ** -alpha_pow
+    ax = 1.0 / h if cross else 0.0
+    say("sphere h=0.025 oracle set-up", alpha, ax)
     b = oracle.build_band(ci.Sphere(), h, 3, [-2.0] * 3, [2.0] * 3)
     A = oracle.stabilized_operator(b, 1.0)
-    dec = schwarz.decompose(b, oracle.rcb_partition(b, 64), 3, "ORAS", alpha=alpha)
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, 64), 3, "ORAS", alpha=alpha, alpha_cross=ax)
     sample = [0, 37, 63]
     M = schwarz.Preconditioner(b, dec, 1.0, subs=sample)
     v = np.random.default_rng(11).standard_normal(b.n_act)
@@ -203,7 +225,7 @@ def test_sphere_h0025_rcb64_oras_sampled():
     ctx = P.Context(0)
     ctx.build_band(ci.Sphere(), h, 3)
     ctx.build_operator(1.0)
-    ctx.partition(P.PART_RCB, 64, None, 3, P.ORAS, alpha, 0.0)
+    ctx.partition(P.PART_RCB, 64, None, 3, P.ORAS, alpha, ax)
     for prec, tol in ((P.FP64, 1e-9), (P.FP32, 2e-3)):
         say("sphere h=0.025 factor", prec)
         ctx.factor(prec)

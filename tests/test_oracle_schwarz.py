@@ -125,9 +125,10 @@ def test_local_rows_against_global_rows(tiny):
                 assert not A[x, rest].any()
                 checked += 1
         assert checked > 0
-        # B rows: sigma (e_b - E[x*]/(1 + alpha s)), so the row sum is sigma(1 - 1/(1 + alpha s))
+        # B rows: (c + 6/h^2) e_b - (6/h^2) E[x*]/(1 + alpha s); E rows sum to one
         rs = Aj[m:].sum(axis=1)
-        np.testing.assert_allclose(rs, sig_ * (1 - 1 / (1 + sd.alpha * sd.s)), rtol=1e-9, atol=1e-9)
+        want = sig_ - (6.0 / b.h ** 2) / (1 + sd.alpha * sd.s)
+        np.testing.assert_allclose(rs, want, rtol=1e-9, atol=1e-9)
 
 
 def test_oras_large_alpha_tends_to_ras():
@@ -154,7 +155,7 @@ def test_zero_conormal_rows_are_extension_rows(tiny):
     sig_ = 1.0 + 6.0 / b.h ** 2
     unk = np.concatenate([sd.sigma, sd.bnd])
     for q in range(0, len(sd.bnd), 7):
-        row = -sig_ * E[sd.xstar[q], unk]
+        row = -(6.0 / b.h ** 2) * E[sd.xstar[q], unk]
         row[m + q] += sig_
         np.testing.assert_allclose(Aj[m + q], row, atol=1e-9)
 
@@ -193,3 +194,25 @@ def test_oras_beats_ras_iterations():
         _, info = oracle.fgmres(lambda v: A @ v, f, M.apply, tol=1e-8)
         its[kind] = info["iters"]
     assert its["ORAS"] < its["RAS"], its
+
+
+def test_transmission_node_on_the_surface_keeps_local_matrix_regular():
+    # Overlap 1 on the h = 0.1 sphere: B nodes at (+-1, 0, 0) lie on the surface and their
+    # subsurface closest point is the node itself (d = 0, Kronecker extension row).
+    # eq. localOP leaves c u_b = 0 there; the local matrix stays regular.
+    b = oracle.build_band(ci.Sphere(), 0.1, 3, [-2.0] * 3, [2.0] * 3)
+    part = oracle.rcb_partition(b, 8)
+    dec = schwarz.decompose(b, part, 1, "ORAS", alpha=3.0, alpha_cross=30.0)
+    found = 0
+    for j, sd in enumerate(dec.subs):
+        deg = np.flatnonzero((sd.s == 0) & np.all(b.xyz[sd.bnd] == b.cp[sd.xstar], axis=1))
+        if len(deg) == 0:
+            continue
+        found += 1
+        Aj = schwarz.local_matrix(b, dec, j, 1.0)
+        m = len(sd.sigma)
+        for q in deg:
+            row = Aj[m + q]
+            assert row[m + q] == pytest.approx(1.0) and np.count_nonzero(row) == 1
+        assert np.linalg.cond(Aj) < 1e8
+    assert found >= 1
