@@ -11,6 +11,8 @@
 
 namespace cpm {
 
+struct HostSlot;
+
 // Band and extension data (Section 2.1). Band order: actives sorted by L, then ghosts.
 struct Band {
   double lo[3] = {0, 0, 0};
@@ -64,6 +66,7 @@ struct SubDesc {
   int32_t rows;      // n + t
   int32_t cols;      // n + m
   int32_t blk_off;   // first apply block of this subdomain
+  int32_t rpb;       // rows of W_j per apply block
 };
 
 enum { TIMER_PRECOND = 0, TIMER_EXTEND = 1, TIMER_STENCIL = 2, TIMER_LU_GEMM = 3, N_TIMERS = 4 };
@@ -99,12 +102,11 @@ struct Dev {
   int64_t ld = 0;               // padded vector length
   double* V = nullptr;          // (restart+1) x ld
   double* Z = nullptr;          // restart x ld
-  double* x = nullptr;
-  double* r = nullptr;
-  double* f = nullptr;
   double* part = nullptr;       // partial sums
   double* small = nullptr;      // H, cs, sn, g, y, h1, h2, scalars
-  double* host_small = nullptr; // pinned mirror of the scalars
+  struct HostSlot* slots = nullptr;  // mapped pinned scalars, one slot per step (host view)
+  struct HostSlot* slots_dev = nullptr;  // the same memory, device view
+  unsigned long long ticket = 0;     // last ticket handed out
   size_t krylov_bytes = 0;
   size_t op_bytes = 0;
 };

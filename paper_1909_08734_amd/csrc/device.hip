@@ -1,10 +1,13 @@
 // Device orchestration: operator upload, local operator factorisation,
 // preconditioner and operator applies, and the FGMRES driver.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
+
+#include <hip/hip_ext.h>
 
 #include "kernels.h"
 
@@ -38,31 +41,29 @@ int upload(cpm_ctx* ctx, T** dst, const std::vector<T>& src) {
   return CPM_OK;
 }
 
-// Event pair around a launch when per-kernel timing is on.
-struct Scope {
-  cpm_ctx* ctx;
-  int which;
-  hipEvent_t e1 = nullptr;
-  Scope(cpm_ctx* c, int w) : ctx(c), which(w) {
-    Timer& t = ctx->timer;
-    if (!t.on) return;
-    if (t.used + 2 > t.pool.size()) {
-      hipEvent_t a, b;
-      hipEventCreate(&a);
-      hipEventCreate(&b);
-      t.pool.push_back(a);
-      t.pool.push_back(b);
-    }
-    hipEvent_t e0 = t.pool[t.used];
-    e1 = t.pool[t.used + 1];
-    t.which.push_back(which);
-    t.used += 2;
-    hipEventRecord(e0, ctx->stream);
+// Launch on the context stream; with per-kernel timing on, the dispatch
+// itself carries the start/stop events (no extra packets in the stream).
+template <typename... KArgs, typename... Args>
+void launch(cpm_ctx* ctx, int which, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds,
+            Args... args) {
+  Timer& t = ctx->timer;
+  if (!t.on) {
+    hipLaunchKernelGGL(kernel, grid, block, lds, ctx->stream, static_cast<KArgs>(args)...);
+    return;
   }
-  ~Scope() {
-    if (e1) hipEventRecord(e1, ctx->stream);
+  if (t.used + 2 > t.pool.size()) {
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    t.pool.push_back(a);
+    t.pool.push_back(b);
   }
-};
+  hipEvent_t e0 = t.pool[t.used], e1 = t.pool[t.used + 1];
+  t.which.push_back(which);
+  t.used += 2;
+  hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, ctx->stream, e0, e1, 0,
+                        static_cast<KArgs>(args)...);
+}
 
 }  // namespace
 
@@ -98,13 +99,11 @@ static void free_krylov(cpm_ctx* ctx) {
   Dev& d = ctx->dev;
   dfree(d.V);
   dfree(d.Z);
-  dfree(d.x);
-  dfree(d.r);
-  dfree(d.f);
   dfree(d.part);
   dfree(d.small);
-  if (d.host_small) hipHostFree(d.host_small);
-  d.host_small = nullptr;
+  if (d.slots) hipHostFree(d.slots);
+  d.slots = nullptr;
+  d.slots_dev = nullptr;
   d.restart = 0;
   d.krylov_bytes = 0;
 }
@@ -143,29 +142,29 @@ static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const doub
   Dev& d = ctx->dev;
   const double ih2 = 1.0 / (b.h * b.h);
   const double diag = ctx->c + 6.0 * ih2;
-  {
-    Scope s(ctx, TIMER_EXTEND);
-    if (b.p == 3)
-      k_extend<3><<<nblk(b.total() * 16, 256), 256, 0, ctx->stream>>>(b.total(), d.lines, d.wts, x, d.e);
-    else
-      k_extend<2><<<nblk(b.total() * 16, 256), 256, 0, ctx->stream>>>(b.total(), d.lines, d.wts, x, d.e);
-  }
-  {
-    Scope s(ctx, TIMER_STENCIL);
-    k_stencil<<<nblk(b.n_act, 256), 256, 0, ctx->stream>>>(b.n_act, diag, ih2, d.nbr, x, d.e, f, y);
-  }
+  const int64_t nt = b.total(), na = b.n_act;
+  if (b.p == 3)
+    launch(ctx, TIMER_EXTEND, k_extend<3>, dim3(nblk(nt * 16, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
+           (const double*)d.wts, x, d.e);
+  else
+    launch(ctx, TIMER_EXTEND, k_extend<2>, dim3(nblk(nt * 16, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
+           (const double*)d.wts, x, d.e);
+  launch(ctx, TIMER_STENCIL, k_stencil, dim3(nblk(na, 256)), dim3(256), 0, na, diag, ih2, (const int32_t*)d.nbr, x,
+         (const double*)d.e, f, y);
 }
 
-static void launch_precond(cpm_ctx* ctx, const double* v, double* z) {
+// z = scale * M^{-1} v (scale: device scalar or nullptr for 1)
+static void launch_precond(cpm_ctx* ctx, const double* v, double* z, const double* scale = nullptr) {
   Dev& d = ctx->dev;
   const size_t lds = (size_t)d.max_m * sizeof(double);
-  Scope s(ctx, TIMER_PRECOND);
   if (d.prec == CPM_FP64)
-    k_precond<double><<<d.n_blocks, 256, lds, ctx->stream>>>(d.desc, d.blk_sub, d.sig_idx, d.tilde_idx,
-                                                              (const double*)d.W, v, z);
+    launch(ctx, TIMER_PRECOND, k_precond<double>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
+           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
+           (const int32_t*)d.tilde_idx, (const double*)d.W, v, scale, z);
   else
-    k_precond<float><<<d.n_blocks, 256, lds, ctx->stream>>>(d.desc, d.blk_sub, d.sig_idx, d.tilde_idx,
-                                                             (const float*)d.W, v, z);
+    launch(ctx, TIMER_PRECOND, k_precond<float>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
+           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
+           (const int32_t*)d.tilde_idx, (const float*)d.W, v, scale, z);
 }
 
 int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y) {
@@ -197,9 +196,11 @@ struct FactorPlan {
   int max_m = 0, max_n = 0, max_rows = 0, n_blocks = 0;
 };
 
-void make_plan(const cpm_ctx* ctx, FactorPlan& P) {
+void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots) {
   const Decomp& D = ctx->dec;
   const bool oras = D.kind == CPM_ORAS;
+  int64_t w_total = 0;
+  for (int j = 0; j < D.n_sub; ++j) w_total += (int64_t)D.subs[j].tilde.size() * D.subs[j].sigma.size();
   int32_t u_off = 0, t_off = 0, blk = 0;
   int64_t a_off = 0, w_off = 0;
   for (int j = 0; j < D.n_sub; ++j) {
@@ -217,7 +218,11 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P) {
     d.lda = (int32_t)round_up(d.cols, 16);
     d.a_off = a_off;
     d.blk_off = blk;
-    const int nb = (d.t + PRECOND_ROWS - 1) / PRECOND_ROWS;
+    // apply blocks: a share of the resident block slots proportional to the bytes of W_j
+    const double share = (double)d.t * d.m / (double)std::max<int64_t>(w_total, 1) * block_slots;
+    const int want = std::max(1, (int)std::lround(share));
+    d.rpb = std::max(1, (d.t + want - 1) / want);
+    const int nb = (d.t + d.rpb - 1) / d.rpb;
     for (int q = 0; q < nb; ++q) P.blk_sub.push_back(j);
     blk += nb;
     a_off += (int64_t)d.rows * d.lda;
@@ -356,10 +361,8 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     const int32_t* pt = pc + ns + 1;
     k_lu_panel<T><<<ns, PANEL_THREADS, 0, ctx->stream>>>(ddesc, dA, k, dipiv, dinfo);
     if (tot_c[st] > 0) k_lu_swap_trsm<T><<<tot_c[st], 256, 0, ctx->stream>>>(ddesc, dA, k, dipiv, pc, ns);
-    if (tot_t[st] > 0) {
-      Scope s(ctx, TIMER_LU_GEMM);
-      k_lu_gemm<T><<<tot_t[st], 256, 0, ctx->stream>>>(ddesc, dA, k, pt, ns);
-    }
+    if (tot_t[st] > 0)
+      launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(tot_t[st]), dim3(256), 0, (const SubDesc*)ddesc, dA, k, pt, ns);
   }
   FHIP(hipGetLastError());
   FHIP(hipMalloc((void**)&dW, P.w_elems * sizeof(T)));
@@ -399,9 +402,13 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
 int dev_factor(cpm_ctx* ctx, int prec) {
   HIPCHK(hipSetDevice(ctx->device));
   dev_free_factor(ctx);
-  FactorPlan P;
-  make_plan(ctx, P);
-  const size_t lds = (size_t)P.max_m * sizeof(double);
+  // Apply blocks resident at once (registers and the LDS copy of v|Sigma_j
+  // decide how many fit on a CU); the W bytes are spread evenly over them.
+  int n_cu = 0;
+  HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  int64_t max_m = 0;
+  for (const Sub& s : ctx->dec.subs) max_m = std::max<int64_t>(max_m, round_up(s.sigma.size(), 8));
+  const size_t lds = (size_t)max_m * sizeof(double);
   if (lds > 160 * 1024) {
     ctx->err = "factor: a subdomain is too large for the preconditioner apply (|Sigma_j| > 20480)";
     return CPM_EINVAL;
@@ -410,6 +417,14 @@ int dev_factor(cpm_ctx* ctx, int prec) {
     hipFuncSetAttribute((const void*)k_precond<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipFuncSetAttribute((const void*)k_precond<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
+  int per_cu = 0;
+  if (prec == CPM_FP64)
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<double>, PRECOND_THREADS, lds));
+  else
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<float>, PRECOND_THREADS, lds));
+  per_cu = std::max(1, per_cu);
+  FactorPlan P;
+  make_plan(ctx, P, n_cu * per_cu);
   return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec) : run_factor<float>(ctx, P, prec);
 }
 
@@ -441,14 +456,15 @@ static int ensure_krylov(cpm_ctx* ctx, int m) {
   SmallLayout L{m};
   HIPCHK(hipMalloc((void**)&d.V, (size_t)(m + 1) * d.ld * sizeof(double)));
   HIPCHK(hipMalloc((void**)&d.Z, (size_t)m * d.ld * sizeof(double)));
-  HIPCHK(hipMalloc((void**)&d.x, d.ld * sizeof(double)));
-  HIPCHK(hipMalloc((void**)&d.r, d.ld * sizeof(double)));
-  HIPCHK(hipMalloc((void**)&d.f, d.ld * sizeof(double)));
-  HIPCHK(hipMalloc((void**)&d.part, (size_t)RED_BLOCKS * PART_LD * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.part, (size_t)RED_MAX_BLOCKS * PART_LD * sizeof(double)));
   HIPCHK(hipMalloc((void**)&d.small, (size_t)L.size() * sizeof(double)));
-  HIPCHK(hipHostMalloc((void**)&d.host_small, 8 * sizeof(double)));
+  HIPCHK(hipHostMalloc((void**)&d.slots, (size_t)(m + 2) * sizeof(HostSlot),
+                       hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset((void*)d.slots, 0, (size_t)(m + 2) * sizeof(HostSlot));
+  HIPCHK(hipHostGetDevicePointer((void**)&d.slots_dev, d.slots, 0));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   d.restart = m;
-  d.krylov_bytes = ((size_t)(2 * m + 4) * d.ld + RED_BLOCKS * PART_LD + L.size()) * sizeof(double);
+  d.krylov_bytes = ((size_t)(2 * m + 1) * d.ld + RED_MAX_BLOCKS * PART_LD + L.size()) * sizeof(double);
   return CPM_OK;
 }
 
@@ -461,7 +477,6 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   const SmallLayout L{m};
   double* sm = d.small;
   double* scal = sm + L.scal();
-  double* hs = d.host_small;
   hipStream_t st = ctx->stream;
   const unsigned gv = nblk(na, 256);
   hipEvent_t t0, t1;
@@ -469,9 +484,34 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, st));
 
-  auto fetch_scal = [&]() -> int {
-    HIPCHK(hipMemcpyAsync(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+  // The last block of k_cgs3 / k_norm_init writes the scalars of a step into
+  // mapped pinned memory and then the step's ticket; the host polls for it
+  // (and checks the stream for errors while it waits).
+  HostSlot* slots = d.slots;
+  HostSlot* slots_dev = d.slots_dev;
+  std::vector<unsigned long long> expect(m + 2, 0);
+  auto ticket_for = [&](int slot) -> unsigned long long {
+    expect[slot] = ++d.ticket;
+    return expect[slot];
+  };
+  auto wait = [&](int slot, const double** out) -> int {
+    volatile unsigned long long* tk = &slots[slot].ticket;
+    for (long spin = 0;; ++spin) {
+      if (*tk == expect[slot]) break;
+      if ((spin & 1023) == 1023) {
+        const hipError_t q = hipStreamQuery(st);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+          ctx->err = std::string("solve: device error ") + hipGetErrorString(q);
+          return CPM_EDEVICE;
+        }
+        if (q == hipSuccess && *tk != expect[slot]) {
+          ctx->err = "solve: stream idle but the step's result never arrived";
+          return CPM_EDEVICE;
+        }
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *out = (const double*)slots[slot].v;
     return CPM_OK;
   };
   auto finish = [&](int code, int iters, int cycles, double rel_true, double rel_est) -> int {
@@ -492,53 +532,63 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
     return code;
   };
 
-  // ||f||
-  k_dots<<<RED_BLOCKS, 256, 0, st>>>(na, f, 0, 1, f, d.part);
-  k_reduce_norm<<<1, 64, 0, st>>>(d.part, scal);
-  if ((rc = fetch_scal()) != CPM_OK) return rc;
-  const double bnorm = hs[S_BETA];
+  // ||f||, with V[0] = f (x0 = 0) as the first residual
+  k_copy<<<gv, 256, 0, st>>>(na, f, d.V);
+  k_fill<<<gv, 256, 0, st>>>(na, u, 0.0);
+  const int rb = red_blocks(na);
+  k_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, 0, 1, d.V, d.part, -1, nullptr);
+  k_norm_finish<<<1, RED_THREADS, 0, st>>>(d.part, rb, L, sm, slots_dev + (m + 1), ticket_for(m + 1));
+  const double* hv = nullptr;
+  if ((rc = wait(m + 1, &hv)) != CPM_OK) return rc;
+  const double bnorm = hv[S_BETA];
   if (!std::isfinite(bnorm)) {
     finish(CPM_EINVAL, 0, 0, NAN, NAN);
     ctx->err = "solve: right-hand side is not finite";
     return CPM_EINVAL;
   }
-  k_fill<<<gv, 256, 0, st>>>(na, u, 0.0);
   if (bnorm == 0.0) return finish(CPM_OK, 0, 0, 0.0, 0.0);
-  k_copy<<<gv, 256, 0, st>>>(na, f, d.r);
 
   int iters = 0, cycles = 0;
   double rel_true = 1.0, rel_est = 1.0;
   int status = CPM_ENOTCONV;
+  auto enqueue_iteration = [&](int k) -> int {
+    double* vk = d.V + (size_t)k * d.ld;
+    double* w = d.V + (size_t)(k + 1) * d.ld;
+    double* zk = d.Z + (size_t)k * d.ld;
+    launch_precond(ctx, vk, zk, scal + S_INV);  // z_k = M^{-1} (V[k] / ||V[k]||)
+    launch_operator(ctx, zk, w, nullptr);       // w = A z_k
+    // CGS pass 1 (normalising V[k] in place), pass 2, then ||w|| and the Givens update
+    k_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k + 1, w, d.part, k, scal + S_INV);
+    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h1());
+    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0);
+    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h2());
+    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h2(), w, d.part, 1);
+    k_arnoldi<<<1, RED_THREADS, 0, st>>>(d.part, rb, k, L, sm, slots_dev + k, ticket_for(k));
+    return CPM_OK;
+  };
   for (;;) {
-    k_init_cycle<<<gv, 256, 0, st>>>(na, d.r, d.V, L, sm);
+    // Iteration k is checked while iteration k+1 already runs (at most one
+    // iteration of work is discarded when the cycle stops).
     int kk = 0;
+    if ((rc = enqueue_iteration(0)) != CPM_OK) return rc;
     for (int k = 0; k < m; ++k) {
-      double* vk = d.V + (size_t)k * d.ld;
-      double* w = d.V + (size_t)(k + 1) * d.ld;
-      double* zk = d.Z + (size_t)k * d.ld;
-      launch_precond(ctx, vk, zk);
-      launch_operator(ctx, zk, w, nullptr);
-      k_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.V, d.ld, k + 1, w, d.part);
-      k_reduce_cols<<<1, 256, 0, st>>>(d.part, k + 1, sm + L.h1());
-      k_axpy_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.V, d.ld, k + 1, sm + L.h1(), w, d.part, 0);
-      k_reduce_cols<<<1, 256, 0, st>>>(d.part, k + 1, sm + L.h2());
-      k_axpy_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.V, d.ld, k + 1, sm + L.h2(), w, d.part, 1);
-      k_arnoldi<<<1, 64, 0, st>>>(k, L, sm, d.part);
-      k_scale<<<gv, 256, 0, st>>>(na, w, scal + S_INV);
-      if ((rc = fetch_scal()) != CPM_OK) return rc;
+      const bool more = k + 1 < m && iters + 1 < max_iter;
+      if (more && (rc = enqueue_iteration(k + 1)) != CPM_OK) return rc;
+      const double* hs = nullptr;
+      if ((rc = wait(k, &hs)) != CPM_OK) return rc;
       ++iters;
       kk = k + 1;
       rel_est = hs[S_EST] / bnorm;
-      if (!(hs[S_EST] > tol * bnorm) || iters >= max_iter || hs[S_HK1] == 0.0) break;
+      if (!(hs[S_EST] > tol * bnorm) || hs[S_HK1] == 0.0 || !more) break;
     }
     k_backsolve<<<1, 64, 0, st>>>(kk, L, sm);
     k_update_x<<<gv, 256, 0, st>>>(na, d.Z, d.ld, kk, sm + L.y(), u);
-    launch_operator(ctx, u, d.r, f);
-    k_dots<<<RED_BLOCKS, 256, 0, st>>>(na, d.r, 0, 1, d.r, d.part);
-    k_reduce_norm<<<1, 64, 0, st>>>(d.part, scal);
-    if ((rc = fetch_scal()) != CPM_OK) return rc;
+    launch_operator(ctx, u, d.V, f);  // new residual into V[0]
+    k_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, 0, 1, d.V, d.part, -1, nullptr);
+    k_norm_finish<<<1, RED_THREADS, 0, st>>>(d.part, rb, L, sm, slots_dev + (m + 1), ticket_for(m + 1));
+    if ((rc = wait(m + 1, &hv)) != CPM_OK) return rc;
     ++cycles;
-    rel_true = hs[S_BETA] / bnorm;
+    rel_true = hv[S_BETA] / bnorm;
     if (rel_true <= tol) { status = CPM_OK; break; }
     if (iters >= max_iter || !std::isfinite(rel_true)) break;
   }

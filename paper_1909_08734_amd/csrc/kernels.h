@@ -84,35 +84,45 @@ template <>
 struct VecOf<double> {
   typedef d2v type;
   static constexpr int n = 2;
+  static constexpr int unroll = 2;  // 16-byte chunks in flight per row and lane
 };
 template <>
 struct VecOf<float> {
   typedef f4 type;
   static constexpr int n = 4;
+  static constexpr int unroll = 2;
 };
 
-constexpr int PRECOND_ROWS = 32;   // rows of W per block
-constexpr int PRECOND_RPW = 4;     // rows a wave streams at once
+constexpr int PRECOND_THREADS = 512;  // 8 waves per block
+constexpr int PRECOND_RPW = 2;        // rows a wave streams at once
 
+// Block b serves rows [(b - blk_off) rpb, ...) of subdomain blk_sub[b]; the
+// host sizes rpb so that every block streams about the same number of bytes
+// and all blocks are resident at once (no partial last round).
 template <typename T>
-__global__ __launch_bounds__(256) void k_precond(const SubDesc* __restrict__ desc,
-                                                 const int32_t* __restrict__ blk_sub,
-                                                 const int32_t* __restrict__ sig_idx,
-                                                 const int32_t* __restrict__ tilde_idx,
-                                                 const T* __restrict__ W, const double* __restrict__ v,
-                                                 double* __restrict__ z) {
+__global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* __restrict__ desc,
+                                                             const int32_t* __restrict__ blk_sub,
+                                                             const int32_t* __restrict__ sig_idx,
+                                                             const int32_t* __restrict__ tilde_idx,
+                                                             const T* __restrict__ W,
+                                                             const double* __restrict__ v,
+                                                             const double* __restrict__ scale,
+                                                             double* __restrict__ z) {
   extern __shared__ double vs[];
   typedef typename VecOf<T>::type VT;
   constexpr int VN = VecOf<T>::n;
+  constexpr int PRECOND_UNROLL = VecOf<T>::unroll;
+  constexpr int NWAVE = PRECOND_THREADS / 64;
   const int blk = blockIdx.x;
   const int j = blk_sub[blk];
   const SubDesc d = desc[j];
-  for (int c = threadIdx.x; c < d.ldw; c += blockDim.x) vs[c] = c < d.m ? v[sig_idx[d.u_off + c]] : 0.0;
+  const double sc = scale ? *scale : 1.0;  // z = sc * M^{-1} v (M^{-1} is linear)
+  for (int c = threadIdx.x; c < d.ldw; c += PRECOND_THREADS) vs[c] = c < d.m ? sc * v[sig_idx[d.u_off + c]] : 0.0;
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r_begin = (blk - d.blk_off) * PRECOND_ROWS;
-  const int r_end = min(r_begin + PRECOND_ROWS, d.t);
-  for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += 4 * PRECOND_RPW) {
+  const int r_begin = (blk - d.blk_off) * d.rpb;
+  const int r_end = min(r_begin + d.rpb, d.t);
+  for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += NWAVE * PRECOND_RPW) {
     const T* wr[PRECOND_RPW];
     double acc[PRECOND_RPW];
 #pragma unroll
@@ -120,15 +130,33 @@ __global__ __launch_bounds__(256) void k_precond(const SubDesc* __restrict__ des
       wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw;
       acc[i] = 0.0;
     }
-    for (int c = lane * VN; c < d.ldw; c += 64 * VN) {
+    int c = lane * VN;
+    for (; c + (PRECOND_UNROLL - 1) * 64 * VN < d.ldw; c += PRECOND_UNROLL * 64 * VN) {
+      VT wv[PRECOND_UNROLL][PRECOND_RPW];
+#pragma unroll
+      for (int u = 0; u < PRECOND_UNROLL; ++u)
+#pragma unroll
+        for (int i = 0; i < PRECOND_RPW; ++i)
+          wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c + u * 64 * VN));
+#pragma unroll
+      for (int u = 0; u < PRECOND_UNROLL; ++u)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          const double xv = vs[c + u * 64 * VN + e];
+#pragma unroll
+          for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[u][i][e] * xv;
+        }
+    }
+    for (; c < d.ldw; c += 64 * VN) {
       VT wv[PRECOND_RPW];
 #pragma unroll
-      for (int i = 0; i < PRECOND_RPW; ++i) wv[i] = *reinterpret_cast<const VT*>(wr[i] + c);
+      for (int i = 0; i < PRECOND_RPW; ++i)
+        wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
 #pragma unroll
-      for (int u = 0; u < VN; ++u) {
-        const double xv = vs[c + u];
+      for (int e = 0; e < VN; ++e) {
+        const double xv = vs[c + e];
 #pragma unroll
-        for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[i][u] * xv;
+        for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[i][e] * xv;
       }
     }
 #pragma unroll
@@ -458,79 +486,21 @@ __global__ __launch_bounds__(256) void k_extract_w(const SubDesc* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
-// Krylov kernels (FGMRES with classical Gram-Schmidt applied twice). All
-// reductions are two-stage with a fixed order, so results are reproducible.
+// Krylov kernels (FGMRES with classical Gram-Schmidt applied twice). Every
+// reduction is two-stage with a fixed order: a pass kernel writes one partial
+// sum per block and column, a reduction kernel (one block per column) adds
+// them in block order, so results are reproducible run to run. Each thread
+// owns one row and keeps that row of the basis in registers, so the fused
+// "w -= V h, then V^T w" pass reads V once.
 // ---------------------------------------------------------------------------
-constexpr int RED_BLOCKS = 256;
-constexpr int PART_LD = 64;  // partial-sum stride per block (columns per launch <= 64)
+constexpr int RED_THREADS = 256;
+constexpr int MAX_BASIS = 64;       // restart length limit (columns of V per pass)
+constexpr int RED_MAX_BLOCKS = 4096;
+constexpr int PART_LD = MAX_BASIS;  // partial-sum stride per block
 
-__device__ __forceinline__ void row_range(int64_t n, int64_t& r0, int64_t& r1) {
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  r0 = (int64_t)blockIdx.x * chunk;
-  r1 = min(n, r0 + chunk);
-}
-
-// part[b][j] = sum_{rows of block b} X_j[r] w[r], j < ncols (X columns stride ldx)
-__device__ __forceinline__ void block_dots(int64_t r0, int64_t r1, const double* __restrict__ X, int64_t ldx,
-                                           int ncols, const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double red[4][4];
-  for (int j0 = 0; j0 < ncols; j0 += 4) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-      const double wr = w[r];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (j0 + u < ncols) acc[u] += X[(j0 + u) * ldx + r] * wr;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = wave_sum(acc[u]);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) red[threadIdx.x >> 6][u] = acc[u];
-    __syncthreads();
-    if (threadIdx.x < 4 && j0 + (int)threadIdx.x < ncols) {
-      const int u = threadIdx.x;
-      part[blockIdx.x * PART_LD + j0 + u] = (red[0][u] + red[1][u]) + (red[2][u] + red[3][u]);
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_dots(int64_t n, const double* __restrict__ X, int64_t ldx, int ncols,
-                                              const double* __restrict__ w, double* __restrict__ part) {
-  int64_t r0, r1;
-  row_range(n, r0, r1);
-  block_dots(r0, r1, X, ldx, ncols, w, part);
-}
-
-// w -= X h (h: ncols values), then part = X^T w (mode 0) or ||w||^2 (mode 1).
-__global__ __launch_bounds__(256) void k_axpy_dots(int64_t n, const double* __restrict__ X, int64_t ldx, int ncols,
-                                                   const double* __restrict__ h, double* __restrict__ w,
-                                                   double* __restrict__ part, int mode) {
-  __shared__ double hs[256];
-  for (int q = threadIdx.x; q < ncols; q += 256) hs[q] = h[q];
-  __syncthreads();
-  int64_t r0, r1;
-  row_range(n, r0, r1);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-    double s = 0.0;
-    for (int q = 0; q < ncols; ++q) s += X[q * ldx + r] * hs[q];
-    w[r] -= s;
-  }
-  if (mode == 0) block_dots(r0, r1, X, ldx, ncols, w, part);
-  else block_dots(r0, r1, w, 0, 1, w, part);
-}
-
-// out[j] = sum_b part[b][j] for j < ncols (fixed order).
-__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part, int ncols,
-                                                     double* __restrict__ out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < ncols; j += 4) {
-    double s = 0.0;
-    for (int b = lane; b < RED_BLOCKS; b += 64) s += part[b * PART_LD + j];
-    s = wave_sum(s);
-    if (lane == 0) out[j] = s;
-  }
+inline int red_blocks(int64_t n) {
+  const int64_t b = (n + RED_THREADS - 1) / RED_THREADS;
+  return (int)(b < RED_MAX_BLOCKS ? (b < 1 ? 1 : b) : RED_MAX_BLOCKS);
 }
 
 // Layout of the small device buffer (doubles).
@@ -546,35 +516,189 @@ struct SmallLayout {
   __host__ __device__ int scal() const { return h2() + m + 1; }      // 8 scalars
   __host__ __device__ int size() const { return scal() + 8; }
 };
-enum { S_EST = 0, S_HK1 = 1, S_INV = 2, S_BETA = 3, S_INVB = 4, S_NORM = 5 };
+// scal[]: residual estimate, ||w||, 1/||w|| (scale of the newest basis vector), ||r|| at the cycle start
+enum { S_EST = 0, S_HK1 = 1, S_INV = 2, S_BETA = 3, S_NSCAL = 8 };
 
-// Norm of a reduced column: scal[S_BETA] = sqrt(sum), scal[S_INVB] = 1/that (0 if zero).
-__global__ __launch_bounds__(64) void k_reduce_norm(const double* __restrict__ part, double* __restrict__ scal) {
-  double s = 0.0;
-  for (int b = threadIdx.x; b < RED_BLOCKS; b += 64) s += part[b * PART_LD];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) {
-    const double nr = sqrt(s);
-    scal[S_BETA] = nr;
-    scal[S_INVB] = nr > 0.0 ? 1.0 / nr : 0.0;
+// Scalars handed to the host through mapped pinned memory: the values, then
+// (after a system-scope fence) the ticket the host waits for.
+struct HostSlot {
+  double v[8];
+  unsigned long long ticket;
+  unsigned long long pad[7];
+};
+
+__device__ __forceinline__ void publish(HostSlot* slot, unsigned long long ticket, const double* scal) {
+  if (!slot) return;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) slot->v[q] = scal[q];
+  __threadfence_system();
+  *(volatile unsigned long long*)&slot->ticket = ticket;
+}
+
+// Block partial sums of acc[0..nc) (one value per thread and column) into part[blk][j0 + j].
+template <int NC>
+__device__ __forceinline__ void block_partials(const double (&acc)[NC], int j0, int nc, double* __restrict__ part) {
+  __shared__ double red[RED_THREADS / 64][NC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    if (u < nc) {
+      const double t = wave_sum(acc[u]);
+      if (lane == 0) red[wave][u] = t;
+    }
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < nc; u += RED_THREADS) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < RED_THREADS / 64; ++q) s += red[q][u];
+    part[(int64_t)blockIdx.x * PART_LD + j0 + u] = s;
+  }
+  __syncthreads();
+}
+
+// part[blk][j] = sum over the block's rows of X_j[r] w[r], j < ncols. With
+// `scale_col` >= 0 that column of X is first scaled in place by *scale.
+__global__ __launch_bounds__(RED_THREADS) void k_dots(int64_t n, double* __restrict__ X, int64_t ldx, int ncols,
+                                                      const double* __restrict__ w, double* __restrict__ part,
+                                                      int scale_col, const double* __restrict__ scale) {
+  constexpr int NC = 32;
+  const double sc = scale_col >= 0 ? *scale : 1.0;
+  for (int j0 = 0; j0 < ncols; j0 += NC) {
+    const int nc = min(NC, ncols - j0);
+    double acc[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) acc[u] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
+      const double wr = w[r];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        if (u < nc) {
+          double x = X[(int64_t)(j0 + u) * ldx + r];
+          if (j0 + u == scale_col) {
+            x *= sc;
+            X[(int64_t)(j0 + u) * ldx + r] = x;
+          }
+          acc[u] += x * wr;
+        }
+      }
+    }
+    block_partials<NC>(acc, j0, nc, part);
   }
 }
 
-// Arnoldi column k: H[:,k] = h1 + h2, H[k+1,k] = ||w||, Givens update of the
-// least-squares problem, residual estimate |g[k+1]|.
-__global__ __launch_bounds__(64) void k_arnoldi(int k, SmallLayout L, double* __restrict__ sm,
-                                                const double* __restrict__ part) {
+// w -= V[0..k] h (h: k+1 values), then part = V^T w (mode 0) or ||w||^2 (mode 1).
+__global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const double* __restrict__ V, int64_t ld, int k,
+                                                           const double* __restrict__ h, double* __restrict__ w,
+                                                           double* __restrict__ part, int mode) {
+  constexpr int NC = 32;
+  __shared__ double hs[MAX_BASIS];
+  for (int q = threadIdx.x; q <= k; q += RED_THREADS) hs[q] = h[q];
+  __syncthreads();
+  const int ncols = k + 1;
+  if (ncols <= NC) {
+    double acc[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) acc[u] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
+      double v[NC];
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        v[u] = u < ncols ? V[(int64_t)u * ld + r] : 0.0;
+        if (u < ncols) s += v[u] * hs[u];
+      }
+      const double wn = w[r] - s;
+      w[r] = wn;
+      if (mode == 0) {
+#pragma unroll
+        for (int u = 0; u < NC; ++u) acc[u] += v[u] * wn;
+      } else {
+        acc[0] += wn * wn;
+      }
+    }
+    block_partials<NC>(acc, 0, mode == 0 ? ncols : 1, part);
+    return;
+  }
+  // long bases: two sweeps over V
+  for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
+    double s = 0.0;
+    for (int q = 0; q < ncols; ++q) s += V[(int64_t)q * ld + r] * hs[q];
+    w[r] -= s;
+  }
+  if (mode == 0) {
+    for (int j0 = 0; j0 < ncols; j0 += NC) {
+      const int nc = min(NC, ncols - j0);
+      double acc[NC];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) acc[u] = 0.0;
+      for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n;
+           r += (int64_t)gridDim.x * RED_THREADS) {
+        const double wr = w[r];
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+          if (u < nc) acc[u] += V[(int64_t)(j0 + u) * ld + r] * wr;
+      }
+      block_partials<NC>(acc, j0, nc, part);
+    }
+  } else {
+    double acc[1] = {0.0};
+    for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * RED_THREADS)
+      acc[0] += w[r] * w[r];
+    block_partials<1>(acc, 0, 1, part);
+  }
+}
+
+// out[j] = sum_b part[b][j], one block per column, fixed order.
+__device__ __forceinline__ double column_total(const double* __restrict__ part, int nblocks, int j) {
+  __shared__ double red[RED_THREADS / 64];
   double s = 0.0;
-  for (int b = threadIdx.x; b < RED_BLOCKS; b += 64) s += part[b * PART_LD];
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) s += part[(int64_t)b * PART_LD + j];
   s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_cols(const double* __restrict__ part, int nblocks,
+                                                             double* __restrict__ out) {
+  const double t = column_total(part, nblocks, blockIdx.x);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// ||x|| from partials: scal[S_BETA] = ||x||, scal[S_INV] = 1/||x|| (0 if zero),
+// g = (||x||, 0, ..., 0); published to the host.
+__global__ __launch_bounds__(RED_THREADS) void k_norm_finish(const double* __restrict__ part, int nblocks,
+                                                             SmallLayout L, double* __restrict__ sm,
+                                                             HostSlot* slot, unsigned long long ticket) {
+  const double nr = sqrt(column_total(part, nblocks, 0));
+  double* scal = sm + L.scal();
+  for (int i = threadIdx.x; i <= L.m; i += RED_THREADS) sm[L.g() + i] = i == 0 ? nr : 0.0;
+  if (threadIdx.x == 0) {
+    scal[S_BETA] = nr;
+    scal[S_INV] = nr > 0.0 ? 1.0 / nr : 0.0;
+    publish(slot, ticket, scal);
+  }
+}
+
+// Arnoldi column k: H[:,k] = h1 + h2, H[k+1,k] = ||w|| (from partials), the
+// Givens update of the least-squares problem and the residual estimate
+// |g[k+1]|; published to the host.
+__global__ __launch_bounds__(RED_THREADS) void k_arnoldi(const double* __restrict__ part, int nblocks, int k,
+                                                         SmallLayout L, double* __restrict__ sm, HostSlot* slot,
+                                                         unsigned long long ticket) {
+  const double tot = column_total(part, nblocks, 0);
   if (threadIdx.x != 0) return;
-  const int ld = L.m + 1;
-  double* H = sm + L.H() + (int64_t)k * ld;
+  const int ldh = L.m + 1;
+  double* H = sm + L.H() + (int64_t)k * ldh;
   double* cs = sm + L.cs();
   double* sn = sm + L.sn();
   double* g = sm + L.g();
   double* scal = sm + L.scal();
-  const double hk1 = sqrt(s);
+  const double hk1 = sqrt(tot);
   for (int i = 0; i <= k; ++i) H[i] = sm[L.h1() + i] + sm[L.h2() + i];
   H[k + 1] = hk1;
   for (int i = 0; i < k; ++i) {
@@ -592,20 +716,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(int k, SmallLayout L, double* __
   scal[S_EST] = fabs(g[k + 1]);
   scal[S_HK1] = hk1;
   scal[S_INV] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
-}
-
-__global__ __launch_bounds__(256) void k_scale(int64_t n, double* __restrict__ w, const double* __restrict__ s) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) w[i] *= s[0];
-}
-
-// v0 = r / beta; g = (beta, 0, ..., 0)
-__global__ __launch_bounds__(256) void k_init_cycle(int64_t n, const double* __restrict__ r, double* __restrict__ v0,
-                                                    SmallLayout L, double* __restrict__ sm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double* scal = sm + L.scal();
-  if (i < n) v0[i] = r[i] * scal[S_INVB];
-  if (i <= L.m) sm[L.g() + i] = i == 0 ? scal[S_BETA] : 0.0;
+  publish(slot, ticket, scal);
 }
 
 // y = H[0:kk, 0:kk]^{-1} g[0:kk] (upper triangular after the rotations)
