@@ -196,11 +196,34 @@ struct FactorPlan {
   int max_m = 0, max_n = 0, max_rows = 0, n_blocks = 0;
 };
 
+// Apply blocks per subdomain: the resident block slots apportioned by W bytes
+// (largest remainder, at least one each), so that no block waits for a slot.
+std::vector<int> apportion_blocks(const Decomp& D, int slots) {
+  const int ns = D.n_sub;
+  std::vector<double> bytes(ns);
+  double total = 0;
+  for (int j = 0; j < ns; ++j) total += bytes[j] = (double)D.subs[j].tilde.size() * D.subs[j].sigma.size();
+  std::vector<int> want(ns, 1);
+  if (slots <= ns || total <= 0) return want;
+  std::vector<std::pair<double, int>> rem;
+  int given = 0;
+  for (int j = 0; j < ns; ++j) {
+    const double share = bytes[j] / total * slots;
+    want[j] = std::max(1, (int)std::floor(share));
+    given += want[j];
+    rem.push_back({share - std::floor(share), j});
+  }
+  std::sort(rem.begin(), rem.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  for (size_t q = 0; given < slots && q < rem.size(); ++q, ++given) want[rem[q].second] += 1;
+  return want;
+}
+
 void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots) {
   const Decomp& D = ctx->dec;
   const bool oras = D.kind == CPM_ORAS;
-  int64_t w_total = 0;
-  for (int j = 0; j < D.n_sub; ++j) w_total += (int64_t)D.subs[j].tilde.size() * D.subs[j].sigma.size();
+  const std::vector<int> want_blocks = apportion_blocks(D, block_slots);
   int32_t u_off = 0, t_off = 0, blk = 0;
   int64_t a_off = 0, w_off = 0;
   for (int j = 0; j < D.n_sub; ++j) {
@@ -218,9 +241,7 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots) {
     d.lda = (int32_t)round_up(d.cols, 16);
     d.a_off = a_off;
     d.blk_off = blk;
-    // apply blocks: a share of the resident block slots proportional to the bytes of W_j
-    const double share = (double)d.t * d.m / (double)std::max<int64_t>(w_total, 1) * block_slots;
-    const int want = std::max(1, (int)std::lround(share));
+    const int want = want_blocks[j];
     d.rpb = std::max(1, (d.t + want - 1) / want);
     const int nb = (d.t + d.rpb - 1) / d.rpb;
     for (int q = 0; q < nb; ++q) P.blk_sub.push_back(j);
