@@ -46,10 +46,18 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the preconditioner-apply kernel source and of its launch planning
+    (the code that decides the traffic the counters measured)."""
+    csrc = os.path.join(ROOT, "paper_1909_08734_amd", "csrc")
+    with open(os.path.join(csrc, "kernels.h")) as fh:
+        k = fh.read()
+    with open(os.path.join(csrc, "device.hip")) as fh:
+        d = fh.read()
+    kern = k[k.index("constexpr int PRECOND_THREADS"):k.index("// Local operator assembly")]
+    plan = d[d.index("std::vector<int> apportion_blocks("):d.index("template <typename T>\nint run_factor(")]
     h = hashlib.sha256()
-    for name in ("kernels.h", "device.hip"):
-        with open(os.path.join(ROOT, "paper_1909_08734_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    h.update(kern.encode())
+    h.update(plan.encode())
     return h.hexdigest()[:16]
 
 
@@ -67,18 +75,25 @@ def precond_bytes(ctx, n_sub, esz):
     return w * esz + g * (8 + 4) + t * (8 + 4), w
 
 
-def lu_flops(ctx, n_sub, kind_oras, nb=32):
-    """Flops of the trailing updates of the augmented-matrix LU (all panels)."""
+def lu_flops(ctx, n_sub, kind_oras, nb=32, kmax=128):
+    """Matrix-core flops of the two-level blocked LU of the bordered local
+    matrices: the left-looking catch-up of each panel inside an outer block
+    plus one trailing update per outer block."""
     tot = 0
     for j in range(n_sub):
         s = ctx.subdomain(j)
         m, t = len(s["sigma"]), len(s["tilde"])
         n = m + (len(s["bnd"]) if kind_oras else 0)
         rows, cols = n + t, n + m
-        for k in range(0, n, nb):
-            kb = min(nb, n - k)
-            lo = k + kb
-            tot += 2 * kb * (rows - lo) * (cols - lo)
+        for k0 in range(0, n, kmax):
+            for p in range(1, kmax // nb):
+                k = k0 + p * nb
+                if k >= n:
+                    break
+                kb = min(nb, n - k)
+                tot += 2 * (k - k0) * (rows - k) * kb
+            k1 = min(k0 + kmax, n)
+            tot += 2 * (k1 - k0) * (rows - k1) * (cols - k1)
     return tot
 
 

@@ -165,9 +165,9 @@ int cpm_set_timing(cpm_ctx* ctx, int on);
 int cpm_kernel_time(cpm_ctx* ctx, int which, double* total_ms, int64_t* launches);
 
 /* Diagnostic: run the matrix-core tile of the LU trailing update once on
- * device `device`: c (64x64, row-major, in/out) -= a (64 x kb, row stride 32)
- * * b (kb x 64, row-major), kb <= 32, in `prec` (CPM_FP64 or CPM_FP32; values
- * are rounded to float for CPM_FP32). Host pointers. */
+ * device `device`: c (64x64, row-major, in/out) -= a (64 x kb, row stride 128)
+ * * b (kb x 64, row-major), 1 <= kb <= 128, in `prec` (CPM_FP64 or CPM_FP32;
+ * values are rounded to float for CPM_FP32). Host pointers. */
 int cpm_selftest_tile(int device, int prec, const double* a, const double* b, double* c, int kb);
 
 #ifdef __cplusplus

@@ -114,9 +114,9 @@ def _sync_torch():
 def selftest_tile(a, b, c, prec=FP64, device=0):
     """c - a @ b on one 64x64 matrix-core tile of the LU trailing update (returns new c)."""
     kb = a.shape[1]
-    A = np.zeros((64, 32))
+    A = np.zeros((64, 128))
     A[:, :kb] = a
-    B = np.zeros((32, 64))
+    B = np.zeros((128, 64))
     B[:kb] = b
     Cm = np.ascontiguousarray(c, dtype=np.float64).copy()
     rc = lib().cpm_selftest_tile(device, prec, _ptr(A), _ptr(B), _ptr(Cm), kb)

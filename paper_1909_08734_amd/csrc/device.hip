@@ -296,13 +296,16 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   int32_t *dU = nullptr, *dsrt = nullptr, *dpos = nullptr, *dbx = nullptr, *dtpos = nullptr, *dtidx = nullptr,
           *dblk = nullptr, *dipiv = nullptr, *dinfo = nullptr, *dpre = nullptr;
   double *dbs = nullptr, *dba = nullptr;
+  int64_t* dscr_off = nullptr;
+  LuJob* jobs_buf = nullptr;
   T* dA = nullptr;
   T* dW = nullptr;
+  T* dscr = nullptr;
   int rc = CPM_OK;
   auto cleanup = [&]() {
     hipStreamSynchronize(ctx->stream);
     dfree(dsrt); dfree(dpos); dfree(dbx); dfree(dtpos); dfree(dipiv); dfree(dinfo);
-    dfree(dpre); dfree(dbs); dfree(dba); dfree(dA);
+    dfree(dpre); dfree(dbs); dfree(dba); dfree(dA); dfree(dscr); dfree(dscr_off); dfree(jobs_buf);
   };
   auto bail = [&](int code) {
     cleanup();
@@ -351,39 +354,102 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     FHIP(hipGetLastError());
   }
 
-  // Per-step work lists: blocks of 256 trailing columns (swap + TRSM) and
-  // 64x64 tiles (trailing update), as prefix sums over subdomains.
-  const int nsteps = (P.max_n + LU_NB - 1) / LU_NB;
-  std::vector<int32_t> pre((size_t)nsteps * 2 * (ns + 1));
-  std::vector<int> tot_c(nsteps), tot_t(nsteps);
-  for (int st = 0; st < nsteps; ++st) {
-    const int k = st * LU_NB;
-    int32_t* pc = &pre[(size_t)st * 2 * (ns + 1)];
-    int32_t* pt = pc + ns + 1;
-    int ac = 0, at = 0;
+  // Two-level blocked LU. Outer blocks of LU_KMAX columns; inside one, each
+  // LU_NB-wide panel is first brought up to date left-looking (row
+  // interchanges + unit-lower solve + MFMA update from the block's earlier
+  // panels), then factored; its interchanges are applied to the block's
+  // earlier L columns. After the outer block, the trailing matrix gets the
+  // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
+  // and one MFMA update with K = LU_KMAX.
+  enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3 };
+  struct Launch {
+    int kind, k, job_off, n_jobs, units;
+  };
+  std::vector<LuJob> jobs;
+  std::vector<int32_t> prefix;  // per launch: n_jobs entries (job_off-aligned)
+  std::vector<Launch> lplan;
+  auto add = [&](int kind, int k, const std::vector<std::pair<LuJob, int>>& list) {
+    Launch L{kind, k, (int)jobs.size(), 0, 0};
+    for (const auto& e : list) {
+      if (e.second <= 0) continue;
+      jobs.push_back(e.first);
+      prefix.push_back(L.units);
+      L.units += e.second;
+      L.n_jobs++;
+    }
+    if (L.n_jobs > 0) lplan.push_back(L);
+  };
+  auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
+  for (int K0 = 0; K0 < P.max_n; K0 += LU_KMAX) {
+    for (int p = 0; p < LU_KMAX / LU_NB; ++p) {
+      const int k = K0 + p * LU_NB;
+      if (k >= P.max_n) break;
+      if (p > 0) {
+        std::vector<std::pair<LuJob, int>> ts, gm;
+        for (int j = 0; j < ns; ++j) {
+          const SubDesc& d = P.desc[j];
+          if (k >= d.n) continue;
+          const int kb = std::min(LU_NB, d.n - k);
+          const LuJob jb{j, K0, k - K0, k, k, k + kb};
+          ts.push_back({jb, 1});
+          gm.push_back({jb, cdiv(d.rows - k, GEMM_TILE)});
+        }
+        add(L_SWAP_TRSM, k, ts);
+        add(L_GEMM, k, gm);
+      }
+      lplan.push_back(Launch{L_PANEL, k, 0, 0, ns});
+      if (p > 0) {
+        std::vector<std::pair<LuJob, int>> sw;
+        for (int j = 0; j < ns; ++j) {
+          const SubDesc& d = P.desc[j];
+          if (k >= d.n) continue;
+          sw.push_back({LuJob{j, k, std::min(LU_NB, d.n - k), 0, K0, k}, cdiv(k - K0, TRSM_COLS)});
+        }
+        add(L_SWAP, k, sw);
+      }
+    }
+    std::vector<std::pair<LuJob, int>> ts, gm;
     for (int j = 0; j < ns; ++j) {
       const SubDesc& d = P.desc[j];
-      pc[j] = ac;
-      pt[j] = at;
-      if (k >= d.n) continue;
-      const int lo = k + std::min(LU_NB, d.n - k);
-      ac += (d.cols - lo + 255) / 256;
-      at += ((d.rows - lo + GEMM_TILE - 1) / GEMM_TILE) * ((d.cols - lo + GEMM_TILE - 1) / GEMM_TILE);
+      if (K0 >= d.n) continue;
+      const int K1 = std::min(K0 + LU_KMAX, d.n);
+      const LuJob jb{j, K0, K1 - K0, K1, K1, d.cols};
+      ts.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
+      gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE) * cdiv(d.cols - K1, GEMM_TILE)});
     }
-    pc[ns] = ac;
-    pt[ns] = at;
-    tot_c[st] = ac;
-    tot_t[st] = at;
+    add(L_SWAP_TRSM, K0, ts);
+    add(L_GEMM, K0, gm);
   }
-  FCHK(upload(ctx, &dpre, pre));
-  for (int st = 0; st < nsteps; ++st) {
-    const int k = st * LU_NB;
-    const int32_t* pc = dpre + (size_t)st * 2 * (ns + 1);
-    const int32_t* pt = pc + ns + 1;
-    k_lu_panel<T><<<ns, PANEL_THREADS, 0, ctx->stream>>>(ddesc, dA, k, dipiv, dinfo);
-    if (tot_c[st] > 0) k_lu_swap_trsm<T><<<tot_c[st], 256, 0, ctx->stream>>>(ddesc, dA, k, dipiv, pc, ns);
-    if (tot_t[st] > 0)
-      launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(tot_t[st]), dim3(256), 0, (const SubDesc*)ddesc, dA, k, pt, ns);
+  LuJob* djobs = nullptr;
+  FCHK(upload(ctx, &djobs, jobs));
+  FCHK(upload(ctx, &dpre, prefix));
+  jobs_buf = djobs;
+  // column-major panel scratch, LU_NB x rows_j per subdomain
+  std::vector<int64_t> scr_off(ns);
+  int64_t scr_total = 0;
+  for (int j = 0; j < ns; ++j) {
+    scr_off[j] = scr_total;
+    scr_total += (int64_t)LU_NB * P.desc[j].rows;
+  }
+  FCHK(upload(ctx, &dscr_off, scr_off));
+  FHIP(hipMalloc((void**)&dscr, scr_total * sizeof(T)));
+  for (const Launch& L : lplan) {
+    const LuJob* jb = djobs + L.job_off;
+    const int32_t* pre = dpre + L.job_off;
+    switch (L.kind) {
+      case L_PANEL:
+        k_lu_panel<T><<<ns, PANEL_THREADS, 0, ctx->stream>>>(ddesc, dA, L.k, dipiv, dinfo, dscr, dscr_off);
+        break;
+      case L_SWAP_TRSM:
+      case L_SWAP:
+        k_lu_swap_trsm<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(ddesc, dA, dipiv, jb, pre, L.n_jobs,
+                                                                   L.kind == L_SWAP_TRSM ? 1 : 0);
+        break;
+      case L_GEMM:
+        launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(L.units), dim3(256), 0, (const SubDesc*)ddesc, dA, jb, pre,
+               L.n_jobs);
+        break;
+    }
   }
   FHIP(hipGetLastError());
   FHIP(hipMalloc((void**)&dW, P.w_elems * sizeof(T)));
@@ -618,11 +684,11 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
 }
 
 template <typename T>
-static int selftest_tile(const double* a, const double* b, double* c, int kb) {
-  std::vector<T> ha(GEMM_TILE * LU_NB, (T)0), hb(LU_NB * GEMM_TILE, (T)0), hc(GEMM_TILE * GEMM_TILE);
+static int selftest_tile(const double* a, const double* b, double* c, int kdim) {
+  std::vector<T> ha(GEMM_TILE * LU_KMAX, (T)0), hb(LU_KMAX * GEMM_TILE, (T)0), hc(GEMM_TILE * GEMM_TILE);
   for (int i = 0; i < GEMM_TILE; ++i)
-    for (int q = 0; q < kb; ++q) ha[i * LU_NB + q] = (T)a[i * LU_NB + q];
-  for (int q = 0; q < kb; ++q)
+    for (int q = 0; q < kdim; ++q) ha[i * LU_KMAX + q] = (T)a[i * LU_KMAX + q];
+  for (int q = 0; q < kdim; ++q)
     for (int jx = 0; jx < GEMM_TILE; ++jx) hb[q * GEMM_TILE + jx] = (T)b[q * GEMM_TILE + jx];
   for (int q = 0; q < GEMM_TILE * GEMM_TILE; ++q) hc[q] = (T)c[q];
   T *da = nullptr, *db = nullptr, *dc = nullptr;
@@ -632,7 +698,7 @@ static int selftest_tile(const double* a, const double* b, double* c, int kb) {
   hipMemcpy(da, ha.data(), ha.size() * sizeof(T), hipMemcpyHostToDevice);
   hipMemcpy(db, hb.data(), hb.size() * sizeof(T), hipMemcpyHostToDevice);
   hipMemcpy(dc, hc.data(), hc.size() * sizeof(T), hipMemcpyHostToDevice);
-  k_tile_selftest<T><<<1, 256>>>(dc, da, db, kb);
+  k_tile_selftest<T><<<1, 256>>>(dc, da, db, kdim);
   hipError_t e = hipDeviceSynchronize();
   hipMemcpy(hc.data(), dc, hc.size() * sizeof(T), hipMemcpyDeviceToHost);
   hipFree(da);
@@ -646,7 +712,7 @@ static int selftest_tile(const double* a, const double* b, double* c, int kb) {
 }  // namespace cpm
 
 extern "C" int cpm_selftest_tile(int device, int prec, const double* a, const double* b, double* c, int kb) {
-  if (!a || !b || !c || kb < 1 || kb > cpm::LU_NB) return CPM_EINVAL;
+  if (!a || !b || !c || kb < 1 || kb > cpm::LU_KMAX) return CPM_EINVAL;
   if (prec != CPM_FP64 && prec != CPM_FP32) return CPM_EINVAL;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CPM_EDEVICE;

@@ -39,22 +39,30 @@ template <int P>
 __global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
                                                 const double* __restrict__ wts,
                                                 const double* __restrict__ x, double* __restrict__ e) {
-  constexpr int P1 = P + 1, NL = P1 * P1;
+  constexpr int P1 = P + 1, NL = P1 * P1, NW = 3 * P1;
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int q = threadIdx.x & 15;
+  const bool live = row < n_rows;
+  // lane q holds weight q of the row (w_x[0..p], w_y[0..p], w_z[0..p]); the
+  // 16-lane group shares them by shuffles
+  const double wq = (live && q < NW) ? wts[row * NW + q] : 0.0;
+  const int a = q / P1, b = q - (q / P1) * P1;
+  const double wxa = __shfl(wq, a, 16);
+  const double wyb = __shfl(wq, P1 + b, 16);
+  double wz[P1];
+#pragma unroll
+  for (int c = 0; c < P1; ++c) wz[c] = __shfl(wq, 2 * P1 + c, 16);
   double acc = 0.0;
-  if (row < n_rows && q < NL) {
-    const int a = q / P1, b = q - (q / P1) * P1;
-    const double* w = wts + row * (3 * P1);
+  if (live && q < NL) {
     const int32_t s = lines[row * NL + q];
     double lz = 0.0;
 #pragma unroll
-    for (int c = 0; c < P1; ++c) lz += w[2 * P1 + c] * x[s + c];
-    acc = (w[a] * w[P1 + b]) * lz;
+    for (int c = 0; c < P1; ++c) lz += wz[c] * x[s + c];
+    acc = (wxa * wyb) * lz;
   }
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-  if (row < n_rows && q == 0) e[row] = acc;
+  if (live && q == 0) e[row] = acc;
 }
 
 // y = diag x - ih2 * sum_nb e[nb]           (f == nullptr)
@@ -255,13 +263,42 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
 // (pivots searched in the first n_j rows only), panel width NB.
 // ---------------------------------------------------------------------------
 constexpr int LU_NB = 32;
-constexpr int PANEL_THREADS = 512;
+constexpr int PANEL_THREADS = 1024;
 
+// (value, row) pair reduction over the block: largest |value|, lowest row on ties.
+__device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri, int* out) {
+  constexpr int NW = PANEL_THREADS / 64;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { rv[wave] = best; ri[wave] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b0 = rv[0];
+    int i0 = ri[0];
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > b0 || (rv[w] == b0 && ri[w] < i0)) { b0 = rv[w]; i0 = ri[w]; }
+    *out = (i0 == INT32_MAX || b0 == 0.0) ? -1 : i0;
+  }
+  __syncthreads();
+  return *out;
+}
+
+// Unblocked LU with partial pivoting of the panel A[k:rows, k:k+kb] of every
+// subdomain (one block each). The panel is moved to a column-major scratch so
+// that every pass is coalesced; the pass that eliminates column jj also finds
+// the pivot of column jj+1. Pivots are searched in the A_j rows only.
 template <typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                             int k, int32_t* __restrict__ ipiv,
-                                                            int32_t* __restrict__ info) {
+                                                            int32_t* __restrict__ info, T* __restrict__ scratch,
+                                                            const int64_t* __restrict__ scr_off) {
   constexpr int NW = PANEL_THREADS / 64;
+  __shared__ T tile[32][33];
   __shared__ T prow[LU_NB];
   __shared__ double rv[NW];
   __shared__ int ri[NW];
@@ -270,60 +307,93 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
   const SubDesc d = desc[j];
   if (k >= d.n) return;
   const int kb = min(LU_NB, d.n - k);
-  T* a = A + d.a_off;
+  const int rows = d.rows - k;  // panel height
+  const int np = d.n - k;       // pivot-eligible rows
+  T* a = A + d.a_off + (int64_t)k * d.lda + k;
   const int64_t lda = d.lda;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T* P = scratch + scr_off[j];  // column c at P + c * rows
+  const int t = threadIdx.x;
+  // gather the panel (32-row tiles, transposed through LDS)
+  for (int r0 = 0; r0 < rows; r0 += 32) {
+    {
+      const int rl = t >> 5, c = t & 31;
+      if (r0 + rl < rows && c < kb) tile[rl][c] = a[(int64_t)(r0 + rl) * lda + c];
+    }
+    __syncthreads();
+    {
+      const int c = t >> 5, rl = t & 31;
+      if (r0 + rl < rows && c < kb) P[(int64_t)c * rows + r0 + rl] = tile[rl][c];
+    }
+    __syncthreads();
+  }
+  // pivot of column 0
+  double best = -1.0;
+  int bi = INT32_MAX;
+  for (int r = t; r < np; r += PANEL_THREADS) {
+    const double v = fabs((double)P[r]);
+    if (v > best) { best = v; bi = r; }
+  }
+  int piv = block_argmax(best, bi, rv, ri, &piv_s);
   for (int jj = 0; jj < kb; ++jj) {
-    const int col = k + jj;
-    double best = -1.0;
-    int bi = INT32_MAX;
-    for (int r = col + threadIdx.x; r < d.n; r += PANEL_THREADS) {
-      const double v = fabs((double)a[r * lda + col]);
-      if (v > best) { best = v; bi = r; }
+    T* pj = P + (int64_t)jj * rows;
+    if (t == 0) {
+      ipiv[d.u_off + k + jj] = k + (piv < 0 ? jj : piv);
+      if (piv < 0 && info[j] == 0) info[j] = k + jj + 1;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { rv[wave] = best; ri[wave] = bi; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double b0 = rv[0];
-      int i0 = ri[0];
-      for (int w = 1; w < NW; ++w)
-        if (rv[w] > b0 || (rv[w] == b0 && ri[w] < i0)) { b0 = rv[w]; i0 = ri[w]; }
-      piv_s = (i0 == INT32_MAX || b0 == 0.0) ? -1 : i0;
-      ipiv[d.u_off + col] = piv_s < 0 ? col : piv_s;
-      if (piv_s < 0 && info[j] == 0) info[j] = col + 1;
-    }
-    __syncthreads();
-    const int piv = piv_s;
-    if (piv < 0) continue;  // exactly singular column: recorded, elimination skipped
-    if (piv != col)
-      for (int c = k + threadIdx.x; c < k + kb; c += PANEL_THREADS) {
-        const T t = a[col * lda + c];
-        a[col * lda + c] = a[piv * lda + c];
-        a[piv * lda + c] = t;
+    if (piv >= 0 && piv != jj)
+      for (int c = t; c < kb; c += PANEL_THREADS) {
+        T* pc = P + (int64_t)c * rows;
+        const T tmp = pc[jj];
+        pc[jj] = pc[piv];
+        pc[piv] = tmp;
       }
     __syncthreads();
-    const T pv = a[col * lda + col];
-    const int rest = kb - jj - 1;
-    for (int c = threadIdx.x; c < rest; c += PANEL_THREADS) prow[c] = a[col * lda + col + 1 + c];
+    if (t < kb) prow[t] = P[(int64_t)t * rows + jj];
     __syncthreads();
-    for (int r = col + 1 + threadIdx.x; r < d.rows; r += PANEL_THREADS) {
-      T* ar = a + r * lda;
-      const T l = ar[col] / pv;
-      ar[col] = l;
-      for (int c = 0; c < rest; ++c) ar[col + 1 + c] -= l * prow[c];
+    const T pv = prow[jj];
+    best = -1.0;
+    bi = INT32_MAX;
+    if (piv >= 0) {
+      for (int r = jj + 1 + t; r < rows; r += PANEL_THREADS) {
+        const T l = pj[r] / pv;
+        pj[r] = l;
+        for (int c = jj + 1; c < kb; ++c) {
+          T* pc = P + (int64_t)c * rows;
+          const T nv = pc[r] - l * prow[c];
+          pc[r] = nv;
+          if (c == jj + 1 && r < np) {
+            const double av = fabs((double)nv);
+            if (av > best) { best = av; bi = r; }
+          }
+        }
+      }
+    } else if (jj + 1 < kb) {  // singular column: nothing eliminated, search the next one
+      const T* pn = P + (int64_t)(jj + 1) * rows;
+      for (int r = jj + 1 + t; r < np; r += PANEL_THREADS) {
+        const double av = fabs((double)pn[r]);
+        if (av > best) { best = av; bi = r; }
+      }
+    }
+    if (jj + 1 < kb) piv = block_argmax(best, bi, rv, ri, &piv_s);
+    else __syncthreads();
+  }
+  // write the factored panel back
+  for (int r0 = 0; r0 < rows; r0 += 32) {
+    {
+      const int c = t >> 5, rl = t & 31;
+      if (r0 + rl < rows && c < kb) tile[rl][c] = P[(int64_t)c * rows + r0 + rl];
+    }
+    __syncthreads();
+    {
+      const int rl = t >> 5, c = t & 31;
+      if (r0 + rl < rows && c < kb) a[(int64_t)(r0 + rl) * lda + c] = tile[rl][c];
     }
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ int find_sub(const int32_t* __restrict__ prefix, int n_sub, int blk) {
-  int lo = 0, hi = n_sub - 1;  // largest j with prefix[j] <= blk
+__device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int n_jobs, int blk) {
+  int lo = 0, hi = n_jobs - 1;  // largest q with prefix[q] <= blk
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (prefix[mid] <= blk) lo = mid;
@@ -332,46 +402,55 @@ __device__ __forceinline__ int find_sub(const int32_t* __restrict__ prefix, int 
   return lo;
 }
 
-// Row interchanges of the panel applied to the trailing columns, then
-// U12 = L11^{-1} A12 (unit lower triangular solve), 256 columns per block;
-// each thread owns one column, held in LDS during the substitution.
+// One unit of blocked-LU work on subdomain j: the L block is columns
+// [kstart, kstart + kdim) (rows interchanged by ipiv[kstart .. kstart+kdim)),
+// applied to rows >= r_lo and columns [c_lo, c_hi).
+struct LuJob {
+  int32_t j, kstart, kdim, r_lo, c_lo, c_hi;
+};
+
+constexpr int LU_KMAX = 4 * LU_NB;  // outer block width (panels caught up left-looking inside it)
+constexpr int TRSM_COLS = 64;
+
+// Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
+// [c_lo, c_hi); with `trsm`, then U = L11^{-1} A on rows [kstart, kstart+kdim)
+// (L11 unit lower triangular). One wave per 64 columns, column values in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_swap_trsm(const SubDesc* __restrict__ desc, T* __restrict__ A, int k,
-                                                      const int32_t* __restrict__ ipiv,
-                                                      const int32_t* __restrict__ prefix, int n_sub) {
-  __shared__ T L[LU_NB][LU_NB + 1];
-  __shared__ T X[LU_NB][256];
-  const int j = find_sub(prefix, n_sub, blockIdx.x);
-  const SubDesc d = desc[j];
-  const int kb = min(LU_NB, d.n - k);
+__global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __restrict__ desc, T* __restrict__ A,
+                                                            const int32_t* __restrict__ ipiv,
+                                                            const LuJob* __restrict__ jobs,
+                                                            const int32_t* __restrict__ prefix, int n_jobs,
+                                                            int trsm) {
+  __shared__ T X[LU_KMAX][TRSM_COLS];
+  const int q = find_job(prefix, n_jobs, blockIdx.x);
+  const LuJob jb = jobs[q];
+  const SubDesc d = desc[jb.j];
+  const int c = jb.c_lo + (blockIdx.x - prefix[q]) * TRSM_COLS + threadIdx.x;
+  if (c >= jb.c_hi) return;
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
-  for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
-    const int i = idx / kb, q = idx - (idx / kb) * kb;
-    L[i][q] = a[(k + i) * lda + k + q];
-  }
-  __syncthreads();
-  const int c = k + kb + (blockIdx.x - prefix[j]) * 256 + threadIdx.x;
-  if (c >= d.cols) return;
-  for (int jj = 0; jj < kb; ++jj) {
-    const int p = ipiv[d.u_off + k + jj];
-    if (p != k + jj) {
-      const T t = a[(k + jj) * lda + c];
-      a[(k + jj) * lda + c] = a[p * lda + c];
-      a[p * lda + c] = t;
+  for (int i = 0; i < jb.kdim; ++i) {
+    const int p = ipiv[d.u_off + jb.kstart + i];
+    const int r = jb.kstart + i;
+    if (p != r) {
+      const T tmp = a[r * lda + c];
+      a[r * lda + c] = a[p * lda + c];
+      a[p * lda + c] = tmp;
     }
   }
+  if (!trsm) return;
   const int t = threadIdx.x;
-  for (int i = 0; i < kb; ++i) X[i][t] = a[(k + i) * lda + c];
-  for (int q = 0; q < kb; ++q) {
-    const T xq = X[q][t];
-    for (int i = q + 1; i < kb; ++i) X[i][t] -= L[i][q] * xq;
+  const T* l = a + (int64_t)jb.kstart * lda + jb.kstart;
+  for (int i = 0; i < jb.kdim; ++i) X[i][t] = a[(jb.kstart + i) * lda + c];
+  for (int qq = 0; qq < jb.kdim; ++qq) {
+    const T xq = X[qq][t];
+    for (int i = qq + 1; i < jb.kdim; ++i) X[i][t] -= l[(int64_t)i * lda + qq] * xq;
   }
-  for (int i = 1; i < kb; ++i) a[(k + i) * lda + c] = X[i][t];
+  for (int i = 1; i < jb.kdim; ++i) a[(jb.kstart + i) * lda + c] = X[i][t];
 }
 
-// Trailing update A22 -= L21 U12 on matrix cores. 64x64 tile per block of 4
-// waves, each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K = panel width.
+// Trailing update on matrix cores: C -= Lsrc * Usrc for one 64x64 tile of C,
+// K = kdim in chunks of LU_NB staged through LDS; C is read and written once.
 // 16x16x4 operand layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k. Result D[i][j], j = lane % 16: for f32 element e of lane l holds
 // row 4(l/16) + e; for f64 it holds row l/16 + 4e (measured on gfx950).
@@ -397,22 +476,13 @@ struct Acc4<float> {
 constexpr int GEMM_TILE = 64;
 
 template <typename T>
-__device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int rows, int cols, int kb,
+__device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int rows, int cols, int kdim,
                                             int r0, int c0, const T* __restrict__ lsrc, int64_t lld,
                                             const T* __restrict__ usrc, int64_t uld) {
-  // C[r0.., c0..] -= Lsrc[r0.., 0..kb) * Usrc[0..kb, c0..]
+  // C[r0.., c0..] -= Lsrc[r0.., 0..kdim) * Usrc[0..kdim, c0..]   (C = a, rows x cols in view)
   __shared__ T Ls[GEMM_TILE][LU_NB + 1];
   __shared__ T Us[LU_NB][GEMM_TILE + 1];
   typedef typename Acc4<T>::type AT;
-  for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
-    const int i = idx / LU_NB, q = idx - (idx / LU_NB) * LU_NB;
-    Ls[i][q] = (r0 + i < rows && q < kb) ? lsrc[(int64_t)(r0 + i) * lld + q] : (T)0;
-  }
-  for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
-    const int q = idx / GEMM_TILE, jx = idx - (idx / GEMM_TILE) * GEMM_TILE;
-    Us[q][jx] = (q < kb && c0 + jx < cols) ? usrc[(int64_t)q * uld + c0 + jx] : (T)0;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
@@ -426,17 +496,30 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
         const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
         acc[bi][bj][i] = (rr < rows && cc < cols) ? a[(int64_t)rr * lda + cc] : (T)0;
       }
-  const int ksteps = (kb + 3) >> 2;
-  for (int kk = 0; kk < ksteps; ++kk) {
-    T av[2], bv[2];
+  for (int kc = 0; kc < kdim; kc += LU_NB) {
+    const int kb = min(LU_NB, kdim - kc);
+    for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
+      const int i = idx / LU_NB, qq = idx - (idx / LU_NB) * LU_NB;
+      Ls[i][qq] = (r0 + i < rows && qq < kb) ? lsrc[(int64_t)(r0 + i) * lld + kc + qq] : (T)0;
+    }
+    for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
+      const int qq = idx / GEMM_TILE, jx = idx - (idx / GEMM_TILE) * GEMM_TILE;
+      Us[qq][jx] = (qq < kb && c0 + jx < cols) ? usrc[(int64_t)(kc + qq) * uld + c0 + jx] : (T)0;
+    }
+    __syncthreads();
+    const int ksteps = (kb + 3) >> 2;
+    for (int kk = 0; kk < ksteps; ++kk) {
+      T av[2], bv[2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) av[bi] = -Ls[wr + bi * 16 + li][kk * 4 + lk];
+      for (int bi = 0; bi < 2; ++bi) av[bi] = -Ls[wr + bi * 16 + li][kk * 4 + lk];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) bv[bj] = Us[kk * 4 + lk][wc + bj * 16 + li];
+      for (int bj = 0; bj < 2; ++bj) bv[bj] = Us[kk * 4 + lk][wc + bj * 16 + li];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_16x16x4(av[bi], bv[bj], acc[bi][bj]);
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_16x16x4(av[bi], bv[bj], acc[bi][bj]);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -450,26 +533,28 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ desc, T* __restrict__ A, int k,
-                                                 const int32_t* __restrict__ prefix, int n_sub) {
-  const int j = find_sub(prefix, n_sub, blockIdx.x);
-  const SubDesc d = desc[j];
-  const int kb = min(LU_NB, d.n - k);
-  const int lo = k + kb;
-  const int ntc = (d.cols - lo + GEMM_TILE - 1) / GEMM_TILE;
-  const int tile = blockIdx.x - prefix[j];
+__global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ desc, T* __restrict__ A,
+                                                 const LuJob* __restrict__ jobs, const int32_t* __restrict__ prefix,
+                                                 int n_jobs) {
+  const int q = find_job(prefix, n_jobs, blockIdx.x);
+  const LuJob jb = jobs[q];
+  const SubDesc d = desc[jb.j];
+  const int ncol = jb.c_hi - jb.c_lo;
+  const int ntc = (ncol + GEMM_TILE - 1) / GEMM_TILE;
+  const int tile = blockIdx.x - prefix[q];
   const int tr = tile / ntc, tc = tile - (tile / ntc) * ntc;
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
-  // rows/cols relative to the trailing block origin (lo, lo)
-  tile_update<T>(a + lo * lda + lo, lda, d.rows - lo, d.cols - lo, kb, tr * GEMM_TILE, tc * GEMM_TILE,
-                 a + lo * lda + k, lda, a + (int64_t)k * lda + lo, lda);
+  // view with origin (r_lo, c_lo)
+  tile_update<T>(a + (int64_t)jb.r_lo * lda + jb.c_lo, lda, d.rows - jb.r_lo, ncol, jb.kdim, tr * GEMM_TILE,
+                 tc * GEMM_TILE, a + (int64_t)jb.r_lo * lda + jb.kstart, lda,
+                 a + (int64_t)jb.kstart * lda + jb.c_lo, lda);
 }
 
-// Self-test of the matrix-core tile: C (64x64) -= A (64xkb) B (kbx64), row-major.
+// Self-test of the matrix-core tile: C (64x64) -= A (64 x kdim) B (kdim x 64), row-major.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tile_selftest(T* C, const T* Am, const T* Bm, int kb) {
-  tile_update<T>(C, GEMM_TILE, GEMM_TILE, GEMM_TILE, kb, 0, 0, Am, LU_NB, Bm, GEMM_TILE);
+__global__ __launch_bounds__(256) void k_tile_selftest(T* C, const T* Am, const T* Bm, int kdim) {
+  tile_update<T>(C, GEMM_TILE, GEMM_TILE, GEMM_TILE, kdim, 0, 0, Am, LU_KMAX, Bm, GEMM_TILE);
 }
 
 // W_j = -(lower-right block) of the eliminated augmented matrix, row stride ldw.
