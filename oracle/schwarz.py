@@ -90,7 +90,9 @@ def _grow(band, mask):
     return mask | nb_in.any(axis=1)
 
 
-def decompose(band, part, overlap, kind, alpha=0.0, alpha_cross=0.0):
+def decompose(band, part, overlap, kind, alpha=0.0, alpha_cross=0.0, only=None):
+    """Node sets of every subdomain (or of the subdomains listed in `only`;
+    the others are left as None). Cross points always use the whole partition."""
     if kind not in (RAS, ORAS):
         raise ValueError("kind must be RAS or ORAS")
     if overlap < 0 or (kind == ORAS and overlap < 1):
@@ -103,6 +105,9 @@ def decompose(band, part, overlap, kind, alpha=0.0, alpha_cross=0.0):
     dec = Decomposition(kind=kind, overlap=overlap, alpha=float(alpha),
                         alpha_cross=float(alpha_cross), part=part, cross=cross)
     for j in range(n_sub):
+        if only is not None and j not in only:
+            dec.subs.append(None)
+            continue
         mask = part == j
         tilde = np.flatnonzero(mask)
         prev = mask
