@@ -183,6 +183,20 @@ def run_gpu(args):
                 "stencil_ms_avg": st_ms / max(st_n, 1),
                 "footprint_GB": ctx.footprint_bytes() / 1e9,
             }
+            if a_name == ALPHAS[0][0]:
+                # longer restart cycles: fewer iterations, same factors
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                its60 = []
+                for q in range(args.warmup, nrhs):
+                    info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=60)
+                    if rc != P.OK:
+                        raise RuntimeError(f"solve did not converge: {info}")
+                    its60.append(info[0]["iters"])
+                torch.cuda.synchronize()
+                w60 = time.perf_counter() - t0
+                r["restart60"] = {"solves_per_s": args.steps / w60, "ms_per_solve": 1e3 * w60 / args.steps,
+                                  "iters_mean": float(np.mean(its60))}
             res[a_name][prec_name] = r
             log(f"{a_name} {prec_name}: {json.dumps(r)}")
             if args.check:

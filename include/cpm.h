@@ -135,6 +135,13 @@ int cpm_solve(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, in
 int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs, double tol,
                      int max_iter, int restart, cpm_solve_info* info);
 
+/* (O)RAS as a stationary solver (eq. algRAS): u <- u + M^{-1}(f - A u) from
+ * u = 0 until ||f - A u|| <= tol ||f|| or max_iter updates; device pointers
+ * (N_A, float64). info->iters = updates applied, relres_true = final true
+ * relative residual. Same errors as cpm_solve; CPM_ENOTCONV at max_iter. */
+int cpm_solve_stationary(cpm_ctx* ctx, const double* f_dev, double* u_dev, double tol, int max_iter,
+                         cpm_solve_info* info);
+
 /* Single applications on device vectors, for checking and profiling.
  * y = A x (Section 2.1);  z = M^{-1} v (eq. algRAS) after cpm_factor. */
 int cpm_apply_operator(cpm_ctx* ctx, const double* x_dev, double* y_dev);

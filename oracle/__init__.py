@@ -24,3 +24,4 @@ from .operator import (  # noqa: F401
 from .partition import octant_partition, rcb_partition  # noqa: F401
 from .schwarz import Decomposition, decompose, local_matrix, Preconditioner  # noqa: F401
 from .gmres import fgmres  # noqa: F401
+from .stationary import stationary  # noqa: F401

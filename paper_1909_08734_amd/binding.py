@@ -60,6 +60,8 @@ _SIGS = {
                             C.POINTER(SolveInfo)]),
     "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
                                    C.c_int, C.POINTER(SolveInfo)]),
+    "cpm_solve_stationary": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                       C.POINTER(SolveInfo)]),
     "cpm_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cpm_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cpm_band_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -213,6 +215,14 @@ class Context:
         rc = self._check(self._L.cpm_solve_device(self._h, _dev_ptr(f), _dev_ptr(u), nrhs, float(tol),
                                                   int(max_iter), int(restart), info), "solve_device")
         return [info[q].as_dict() for q in range(nrhs)], rc
+
+    def solve_stationary(self, f, u, tol=1e-8, max_iter=1000):
+        """(O)RAS as a stationary solver on torch float64 HIP tensors f, u (N_A)."""
+        info = SolveInfo()
+        _sync_torch()
+        rc = self._check(self._L.cpm_solve_stationary(self._h, _dev_ptr(f), _dev_ptr(u), float(tol),
+                                                      int(max_iter), C.byref(info)), "solve_stationary")
+        return info.as_dict(), rc
 
     def apply_operator(self, x, y):
         _sync_torch()

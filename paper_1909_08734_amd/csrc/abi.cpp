@@ -195,6 +195,21 @@ int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs,
   return solve_common(ctx, f_dev, u_dev, nrhs, tol, max_iter, restart, info);
 }
 
+int cpm_solve_stationary(cpm_ctx* ctx, const double* f_dev, double* u_dev, double tol, int max_iter,
+                         cpm_solve_info* info) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "solve_stationary: factor first");
+  if (!f_dev || !u_dev) return fail(ctx, CPM_EINVAL, "solve_stationary: null vector");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, CPM_EINVAL, "solve_stationary: tol must be positive");
+  if (max_iter < 1) return fail(ctx, CPM_EINVAL, "solve_stationary: max_iter must be >= 1");
+  return guarded(ctx, [&]() -> int {
+    cpm_solve_info tmp{};
+    const int rc = cpm::dev_stationary(ctx, f_dev, u_dev, tol, max_iter, &tmp);
+    if (info) *info = tmp;
+    return rc;
+  });
+}
+
 int cpm_apply_operator(cpm_ctx* ctx, const double* x_dev, double* y_dev) {
   if (!ctx) return CPM_EINVAL;
   if (ctx->state < 2) return fail(ctx, CPM_ESTATE, "apply_operator: build the operator first");

@@ -134,6 +134,7 @@ int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y);
 int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);
 int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
               cpm_solve_info* info);
+int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, cpm_solve_info* info);
 int dev_export_w(cpm_ctx* ctx, int j, double* w);
 void dev_free_all(cpm_ctx* ctx);
 void dev_free_factor(cpm_ctx* ctx);

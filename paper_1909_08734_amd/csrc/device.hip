@@ -683,6 +683,97 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   return finish(status, iters, cycles, rel_true, rel_est);
 }
 
+// (O)RAS as a stationary solver: u <- u + M^{-1}(f - A u), u0 = 0. Each step
+// applies z = M^{-1} r_n, u_{n+1} = u_n + z, then computes r_{n+1} = f - A u_{n+1}
+// and its norm, which the host reads (one wait per step) for the stopping test.
+int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, cpm_solve_info* info) {
+  HIPCHK(hipSetDevice(ctx->device));
+  const int m = ctx->dev.restart > 0 ? ctx->dev.restart : 2;
+  int rc = ensure_krylov(ctx, m);
+  if (rc != CPM_OK) return rc;
+  Dev& d = ctx->dev;
+  const int64_t na = ctx->band.n_act;
+  const SmallLayout L{m};
+  double* sm = d.small;
+  hipStream_t st = ctx->stream;
+  const unsigned gv = nblk(na, 256);
+  const int rb = red_blocks(na);
+  double* r = d.V;
+  double* z = d.Z;
+  unsigned long long expect[2] = {0, 0};
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, st));
+  auto residual = [&](int slot) {
+    launch_operator(ctx, u, r, f);  // r = f - A u
+    k_dots<<<rb, RED_THREADS, 0, st>>>(na, r, 0, 1, r, d.part, -1, nullptr);
+    expect[slot] = ++d.ticket;
+    k_norm_finish<<<1, RED_THREADS, 0, st>>>(d.part, rb, L, sm, d.slots_dev + slot, expect[slot]);
+  };
+  auto wait = [&](int slot, double* out) -> int {
+    volatile unsigned long long* tk = &d.slots[slot].ticket;
+    for (long spin = 0;; ++spin) {
+      if (*tk == expect[slot]) break;
+      if ((spin & 1023) == 1023) {
+        const hipError_t q = hipStreamQuery(st);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+          ctx->err = std::string("solve_stationary: device error ") + hipGetErrorString(q);
+          return CPM_EDEVICE;
+        }
+        if (q == hipSuccess && *tk != expect[slot]) {
+          ctx->err = "solve_stationary: stream idle but the step's result never arrived";
+          return CPM_EDEVICE;
+        }
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *out = d.slots[slot].v[S_BETA];
+    return CPM_OK;
+  };
+  auto finish = [&](int code, int iters, double rel) -> int {
+    hipEventRecord(t1, st);
+    hipEventSynchronize(t1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, t0, t1);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (info) {
+      info->iters = iters;
+      info->cycles = iters;
+      info->status = code;
+      info->relres_true = rel;
+      info->relres_est = rel;
+      info->ms = ms;
+    }
+    return code;
+  };
+  k_fill<<<gv, 256, 0, st>>>(na, u, 0.0);
+  residual(0);
+  double bnorm = 0.0;
+  if ((rc = wait(0, &bnorm)) != CPM_OK) return rc;
+  if (!std::isfinite(bnorm)) {
+    finish(CPM_EINVAL, 0, NAN);
+    ctx->err = "solve_stationary: right-hand side is not finite";
+    return CPM_EINVAL;
+  }
+  if (bnorm == 0.0) return finish(CPM_OK, 0, 0.0);
+  int n = 0;
+  double rel = 1.0;
+  for (;;) {
+    // update n, then the residual of u_{n+1}
+    launch_precond(ctx, r, z, nullptr);
+    k_axpy<<<gv, 256, 0, st>>>(na, z, u);
+    ++n;
+    residual(n & 1);
+    double bn = 0.0;
+    if ((rc = wait(n & 1, &bn)) != CPM_OK) return rc;
+    rel = bn / bnorm;
+    if (rel <= tol) return finish(CPM_OK, n, rel);
+    if (n >= max_iter || !std::isfinite(rel)) return finish(CPM_ENOTCONV, n, rel);
+  }
+}
+
 template <typename T>
 static int selftest_tile(const double* a, const double* b, double* c, int kdim) {
   std::vector<T> ha(GEMM_TILE * LU_KMAX, (T)0), hb(LU_KMAX * GEMM_TILE, (T)0), hc(GEMM_TILE * GEMM_TILE);

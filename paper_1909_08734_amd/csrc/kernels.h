@@ -827,6 +827,11 @@ __global__ __launch_bounds__(256) void k_update_x(int64_t n, const double* __res
   x[i] += s;
 }
 
+__global__ __launch_bounds__(256) void k_axpy(int64_t n, const double* __restrict__ z, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += z[i];
+}
+
 __global__ __launch_bounds__(256) void k_fill(int64_t n, double* __restrict__ x, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;

@@ -238,3 +238,28 @@ def test_sphere_h0025_rcb64_oras_sampled(alpha_pow, cross):
         assert rc == P.OK
         assert np.linalg.norm(f - A @ u) / np.linalg.norm(f) <= 1.05e-10
     ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["RAS", "ORAS"])
+def test_stationary_solver_follows_oracle(direct_cfg1, kind):
+    say("stationary", kind)
+    b, A, f, u_ref = direct_cfg1
+    alpha, ax = 1 / np.sqrt(0.1), 10.0
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), 0.1, 3)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_OCTANT, 8, None, 2, getattr(P, kind), alpha, ax)
+    ctx.factor(P.FP64)
+    u = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
+    info, rc = ctx.solve_stationary(dev(f), u, tol=1e-10, max_iter=2000)
+    assert rc == P.OK and info["relres_true"] <= 1e-10
+    dec = schwarz.decompose(b, oracle.octant_partition(b), 2, kind, alpha=alpha, alpha_cross=ax)
+    uo, oinfo = oracle.stationary(lambda x: A @ x, f, schwarz.Preconditioner(b, dec, 1.0).apply, tol=1e-10,
+                                  max_iter=2000)
+    assert abs(info["iters"] - oinfo["iters"]) <= 1, (info, oinfo["iters"])
+    got = u.cpu().numpy()
+    assert np.abs(got - u_ref).max() <= 1e-8 * np.abs(u_ref).max()
+    # a capped run reports ENOTCONV with the residual reached
+    info2, rc2 = ctx.solve_stationary(dev(f), u, tol=1e-14, max_iter=3)
+    assert rc2 == P.ENOTCONV and info2["iters"] == 3
+    ctx.close()

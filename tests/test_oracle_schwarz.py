@@ -216,3 +216,29 @@ def test_transmission_node_on_the_surface_keeps_local_matrix_regular():
             assert row[m + q] == pytest.approx(1.0) and np.count_nonzero(row) == 1
         assert np.linalg.cond(Aj) < 1e8
     assert found >= 1
+
+
+def test_stationary_solver_trends_and_fixed_point():
+    # Section 2.2: u <- u + M^{-1}(f - A u) converges to A^{-1} f; with one subdomain in
+    # one step; ORAS converges in fewer steps than RAS and GMRES in fewer than either
+    # (the "Solver" vs "Preconditioner" rows of Tables 2-7)
+    b = oracle.build_band(ci.Sphere(), 0.1, 3, [-2.0] * 3, [2.0] * 3)
+    c = 1.0
+    A = oracle.stabilized_operator(b, c)
+    f = ci.rhs_sphere_y20(b.cp[: b.n_act], c)
+    u_ref = np.linalg.solve(A.toarray(), f)
+    dec1 = schwarz.decompose(b, np.zeros(b.n_act, dtype=np.int64), 1, "RAS")
+    u1, i1 = oracle.stationary(lambda x: A @ x, f, schwarz.Preconditioner(b, dec1, c).apply, tol=1e-12)
+    assert i1["iters"] == 1 and np.abs(u1 - u_ref).max() < 1e-10 * np.abs(u_ref).max()
+    part = oracle.octant_partition(b)
+    its = {}
+    for kind in ("RAS", "ORAS"):
+        dec = schwarz.decompose(b, part, 2, kind, alpha=1 / np.sqrt(0.1), alpha_cross=10.0)
+        M = schwarz.Preconditioner(b, dec, c)
+        u, info = oracle.stationary(lambda x: A @ x, f, M.apply, tol=1e-10, max_iter=2000)
+        assert info["converged"]
+        np.testing.assert_allclose(u, u_ref, rtol=0, atol=1e-8 * np.abs(u_ref).max())
+        _, ginfo = oracle.fgmres(lambda x: A @ x, f, M.apply, tol=1e-10)
+        assert ginfo["iters"] < info["iters"]
+        its[kind] = info["iters"]
+    assert its["ORAS"] < its["RAS"], its
