@@ -36,6 +36,7 @@ CASES = [
     (ci.Sphere(), 0.1, 3, "octant", 8, 2),
     (ci.Torus(1.0, 0.4), 0.05, 3, "rcb", 12, 3),
     (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08, 2, "wrcb", 6, 1),
+    (ci.bumpy_icosphere(level=3, far=0.6), 0.1, 3, "rcb", 8, 2),
 ]
 
 

@@ -49,10 +49,11 @@ def test_matrix_core_tile(prec, kb):
 
 
 SURF = {"sphere": (ci.Sphere(), 0.1), "torus": (ci.Torus(1.0, 0.4), 0.05),
-        "offsphere": (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08)}
+        "offsphere": (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08),
+        "trimesh": (ci.bumpy_icosphere(level=3, far=0.6), 0.1)}
 
 
-@pytest.mark.parametrize("name,p", [("sphere", 3), ("torus", 3), ("offsphere", 2)])
+@pytest.mark.parametrize("name,p", [("sphere", 3), ("torus", 3), ("offsphere", 2), ("trimesh", 3)])
 def test_operator_apply(name, p):
     say("operator", name, p)
     surf, h = SURF[name]
@@ -87,11 +88,13 @@ PRECOND_CASES = [
     ("sphere", 3, "rcb", 7, 2, "ORAS", 3.16, 0.0),
     ("torus", 3, "rcb", 16, 3, "ORAS", 4.47, 20.0),
     ("offsphere", 2, "rcb", 5, 1, "ORAS", 2.0, 0.0),
+    ("trimesh", 3, "rcb", 8, 2, "ORAS", 3.16, 10.0),
 ]
 
 
-@pytest.mark.parametrize("case", range(len(PRECOND_CASES)))
-@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+@pytest.mark.parametrize("case", range(len(PRECOND_CASES)),
+                         ids=[f"{c[0]}-{c[2]}{c[3]}-{c[5]}" for c in PRECOND_CASES])
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
 def test_preconditioner_apply(case, prec):
     args = PRECOND_CASES[case]
     say("precond", args, prec)
