@@ -82,6 +82,23 @@ typedef struct {
  * CPM_EDEVICE. The context creates and owns one HIP stream. */
 int cpm_create(cpm_ctx** out, int device);
 void cpm_destroy(cpm_ctx* ctx);
+
+/*
+ * New context on `device` (as cpm_create) holding a copy of src's host
+ * set-up: band, operator constant and partition (Sections 2.1, 3, 4). The
+ * copy is at src's state capped at "partitioned", so it needs cpm_factor; a
+ * different c is set with cpm_build_operator, which keeps the partition. This
+ * lets one band and partition serve factorisations for several values of c.
+ * src is only read (it may be host-only). ESTATE if src has no band; on error
+ * *out is NULL.
+ */
+int cpm_clone(const cpm_ctx* src, int device, cpm_ctx** out);
+
+/*
+ * Thread use: distinct contexts may be used concurrently from different host
+ * threads (each has its own stream and device memory); one context must not
+ * be used by two threads at once.
+ */
 const char* cpm_last_error(const cpm_ctx* ctx);
 
 /*
@@ -135,6 +152,19 @@ int cpm_solve(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, in
 int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs, double tol,
                      int max_iter, int restart, cpm_solve_info* info);
 
+/*
+ * Implicit steps with resident factors (repeated right-hand sides, e.g.
+ * backward Euler for u_t = Delta_S u with c = 1/dt, which solves
+ * (c - Delta_S) u^{n+1} = c u^n): u_0 solves A u_0 = f, and u_k solves
+ * A u_k = scale * u_{k-1} for k = 1 .. nsteps-1, each by the FGMRES of
+ * cpm_solve. Device pointers: f_dev (N_A), u_dev (N_A x nsteps,
+ * column-major, caller-owned). info may be NULL (else nsteps entries).
+ * EINVAL for nsteps < 0, a non-finite scale, or the arguments cpm_solve
+ * rejects; returns CPM_ENOTCONV if some step hit max_iter.
+ */
+int cpm_solve_steps(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nsteps, double scale,
+                    double tol, int max_iter, int restart, cpm_solve_info* info);
+
 /* (O)RAS as a stationary solver (eq. algRAS): u <- u + M^{-1}(f - A u) from
  * u = 0 until ||f - A u|| <= tol ||f|| or max_iter updates; device pointers
  * (N_A, float64). info->iters = updates applied, relres_true = final true
@@ -164,6 +194,16 @@ int cpm_subdomain_sets(const cpm_ctx* ctx, int j, int32_t* tilde, int32_t* sigma
 int cpm_factor_export(cpm_ctx* ctx, int j, double* w);
 /* Device bytes held for the band, operator, factors and Krylov workspace. */
 size_t cpm_footprint_bytes(const cpm_ctx* ctx);
+/*
+ * Device bytes a factorisation in `prec` would need, before making it
+ * (partitioned context, host-only allowed): *resident = held afterwards with
+ * a Krylov space of `restart` vectors (0: none), *peak = the most held while
+ * cpm_factor runs. For admission of work by memory footprint. Either output
+ * may be NULL. ESTATE before cpm_partition; EINVAL for an unknown prec or
+ * restart outside [0, 64].
+ */
+int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident,
+                           size_t* peak);
 
 /* Per-kernel timing with HIP events on the context stream (off by default).
  * which: 0 = preconditioner apply, 1 = extension apply, 2 = stencil apply,

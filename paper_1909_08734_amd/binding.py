@@ -49,6 +49,7 @@ _lib = None
 _SIGS = {
     "cpm_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "cpm_destroy": (None, [C.c_void_p]),
+    "cpm_clone": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "cpm_last_error": (C.c_char_p, [C.c_void_p]),
     "cpm_build_band": (C.c_int, [C.c_void_p, CP_FN, C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.c_double, C.c_int, C.c_double]),
@@ -60,6 +61,8 @@ _SIGS = {
                             C.POINTER(SolveInfo)]),
     "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
                                    C.c_int, C.POINTER(SolveInfo)]),
+    "cpm_solve_steps": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double,
+                                  C.c_int, C.c_int, C.POINTER(SolveInfo)]),
     "cpm_solve_stationary": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                        C.POINTER(SolveInfo)]),
     "cpm_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -72,6 +75,8 @@ _SIGS = {
     "cpm_subdomain_sets": (C.c_int, [C.c_void_p, C.c_int] + [C.c_void_p] * 8),
     "cpm_factor_export": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "cpm_footprint_bytes": (C.c_size_t, [C.c_void_p]),
+    "cpm_footprint_estimate": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_size_t),
+                                         C.POINTER(C.c_size_t)]),
     "cpm_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_kernel_time": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "cpm_selftest_tile": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
@@ -130,14 +135,25 @@ def selftest_tile(a, b, c, prec=FP64, device=0):
 class Context:
     """One solver context (owns device memory and a HIP stream)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, _handle=None):
         self._L = lib()
-        h = C.c_void_p()
-        rc = self._L.cpm_create(C.byref(h), int(device))
-        if rc != 0:
-            raise CpmError(rc, f"cpm_create(device={device}) failed")
-        self._h = h
+        if _handle is None:
+            h = C.c_void_p()
+            rc = self._L.cpm_create(C.byref(h), int(device))
+            if rc != 0:
+                raise CpmError(rc, f"cpm_create(device={device}) failed")
+            _handle = h
+        self._h = _handle
         self._cb = None
+        self.device = int(device)
+
+    def clone(self, device=0):
+        """New context on `device` with a copy of this one's band, c and partition."""
+        h = C.c_void_p()
+        rc = self._L.cpm_clone(self._h, int(device), C.byref(h))
+        if rc != 0:
+            raise CpmError(rc, f"cpm_clone(device={device}) failed")
+        return Context(device, _handle=h)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -207,14 +223,30 @@ class Context:
                                            int(restart), info), "solve")
         return u, [info[q].as_dict() for q in range(nrhs)], rc
 
-    def solve_device(self, f, u, tol=1e-8, max_iter=1000, restart=30):
-        """torch float64 HIP tensors f, u of N_A x nrhs (column-major = (nrhs, N_A) row-major)."""
+    def solve_device(self, f, u, tol=1e-8, max_iter=1000, restart=30, sync=True):
+        """torch float64 HIP tensors f, u of N_A x nrhs (column-major = (nrhs, N_A) row-major).
+        sync=False skips the device-wide synchronisation that makes torch's pending
+        writes to f visible (for callers that synchronised already)."""
         nrhs = 1 if f.dim() == 1 else f.shape[0]
         info = (SolveInfo * max(nrhs, 1))()
-        _sync_torch()
+        if sync:
+            _sync_torch()
         rc = self._check(self._L.cpm_solve_device(self._h, _dev_ptr(f), _dev_ptr(u), nrhs, float(tol),
                                                   int(max_iter), int(restart), info), "solve_device")
         return [info[q].as_dict() for q in range(nrhs)], rc
+
+    def solve_steps(self, f, u, scale, tol=1e-8, max_iter=1000, restart=30, sync=True):
+        """Implicit steps: u[0] = A^{-1} f, u[k] = A^{-1}(scale u[k-1]); torch float64 HIP
+        tensors f (N_A) and u (nsteps, N_A)."""
+        if u.dim() != 2 or u.shape[1] != f.shape[0]:
+            raise ValueError("u must be (nsteps, N_A)")
+        nsteps = u.shape[0]
+        info = (SolveInfo * max(nsteps, 1))()
+        if sync:
+            _sync_torch()
+        rc = self._check(self._L.cpm_solve_steps(self._h, _dev_ptr(f), _dev_ptr(u), nsteps, float(scale),
+                                                 float(tol), int(max_iter), int(restart), info), "solve_steps")
+        return [info[q].as_dict() for q in range(nsteps)], rc
 
     def solve_stationary(self, f, u, tol=1e-8, max_iter=1000):
         """(O)RAS as a stationary solver on torch float64 HIP tensors f, u (N_A)."""
@@ -280,6 +312,13 @@ class Context:
 
     def footprint_bytes(self):
         return int(self._L.cpm_footprint_bytes(self._h))
+
+    def footprint_estimate(self, prec=FP32, restart=30):
+        """(resident, peak) device bytes of a factorisation in `prec`, before making it."""
+        res, peak = C.c_size_t(), C.c_size_t()
+        self._check(self._L.cpm_footprint_estimate(self._h, int(prec), int(restart), C.byref(res),
+                                                   C.byref(peak)), "footprint_estimate")
+        return int(res.value), int(peak.value)
 
     def set_timing(self, on=True):
         self._check(self._L.cpm_set_timing(self._h, 1 if on else 0), "set_timing")

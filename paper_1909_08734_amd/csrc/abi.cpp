@@ -1,5 +1,6 @@
 // C ABI of the CPM Schwarz solver: argument checks, call-order state machine,
 // error reporting and host queries. Device work lives in device.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -89,6 +90,29 @@ int cpm_build_band(cpm_ctx* ctx, cpm_cp_fn fn, void* user, const double lo[3], c
     }
     return CPM_OK;
   });
+}
+
+int cpm_clone(const cpm_ctx* src, int device, cpm_ctx** out) {
+  if (!out) return CPM_EINVAL;
+  *out = nullptr;
+  if (!src) return CPM_EINVAL;
+  if (src->state < 1) return CPM_ESTATE;
+  cpm_ctx* ctx = nullptr;
+  int rc = cpm_create(&ctx, device);
+  if (rc != CPM_OK) return rc;
+  rc = guarded(ctx, [&]() -> int {
+    ctx->band = src->band;
+    ctx->dec = src->dec;
+    ctx->c = src->c;
+    ctx->state = std::min(src->state, 3);
+    return ctx->host_only ? CPM_OK : cpm::dev_upload_operator(ctx);
+  });
+  if (rc != CPM_OK) {
+    cpm_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return CPM_OK;
 }
 
 int cpm_build_operator(cpm_ctx* ctx, double c) {
@@ -193,6 +217,21 @@ int cpm_solve(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, in
 int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs, double tol, int max_iter,
                      int restart, cpm_solve_info* info) {
   return solve_common(ctx, f_dev, u_dev, nrhs, tol, max_iter, restart, info);
+}
+
+int cpm_solve_steps(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nsteps, double scale, double tol,
+                    int max_iter, int restart, cpm_solve_info* info) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "solve_steps: factor first");
+  if (!f_dev || !u_dev) return fail(ctx, CPM_EINVAL, "solve_steps: null vector");
+  if (nsteps < 0) return fail(ctx, CPM_EINVAL, "solve_steps: nsteps < 0");
+  if (!std::isfinite(scale)) return fail(ctx, CPM_EINVAL, "solve_steps: scale must be finite");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, CPM_EINVAL, "solve_steps: tol must be positive");
+  if (max_iter < 1) return fail(ctx, CPM_EINVAL, "solve_steps: max_iter must be >= 1");
+  if (restart < 1 || restart > 64) return fail(ctx, CPM_EINVAL, "solve_steps: restart must be in [1, 64]");
+  return guarded(ctx, [&]() -> int {
+    return cpm::dev_solve_steps(ctx, f_dev, u_dev, nsteps, scale, tol, max_iter, restart, info);
+  });
 }
 
 int cpm_solve_stationary(cpm_ctx* ctx, const double* f_dev, double* u_dev, double tol, int max_iter,
@@ -301,6 +340,15 @@ int cpm_factor_export(cpm_ctx* ctx, int j, double* w) {
 size_t cpm_footprint_bytes(const cpm_ctx* ctx) {
   if (!ctx) return 0;
   return ctx->dev.op_bytes + ctx->dev.w_bytes + ctx->dev.krylov_bytes;
+}
+
+int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, size_t* peak) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 3) return CPM_ESTATE;
+  if (prec != CPM_FP64 && prec != CPM_FP32) return CPM_EINVAL;
+  if (restart < 0 || restart > 64) return CPM_EINVAL;
+  cpm::dev_estimate(ctx, prec, restart, resident, peak);
+  return CPM_OK;
 }
 
 int cpm_set_timing(cpm_ctx* ctx, int on) {

@@ -102,6 +102,7 @@ struct Dev {
   int64_t ld = 0;               // padded vector length
   double* V = nullptr;          // (restart+1) x ld
   double* Z = nullptr;          // restart x ld
+  double* F = nullptr;          // right-hand side of the current implicit step (ld)
   double* part = nullptr;       // partial sums
   double* small = nullptr;      // H, cs, sn, g, y, h1, h2, scalars
   struct HostSlot* slots = nullptr;  // mapped pinned scalars, one slot per step (host view)
@@ -135,7 +136,10 @@ int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);
 int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
               cpm_solve_info* info);
 int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, cpm_solve_info* info);
+int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double scale, double tol, int max_iter,
+                    int restart, cpm_solve_info* info);
 int dev_export_w(cpm_ctx* ctx, int j, double* w);
+void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, size_t* peak);
 void dev_free_all(cpm_ctx* ctx);
 void dev_free_factor(cpm_ctx* ctx);
 void timer_harvest(cpm_ctx* ctx);

@@ -99,6 +99,7 @@ static void free_krylov(cpm_ctx* ctx) {
   Dev& d = ctx->dev;
   dfree(d.V);
   dfree(d.Z);
+  dfree(d.F);
   dfree(d.part);
   dfree(d.small);
   if (d.slots) hipHostFree(d.slots);
@@ -534,6 +535,11 @@ int dev_export_w(cpm_ctx* ctx, int j, double* w) {
 // ---------------------------------------------------------------------------
 // FGMRES(m), right preconditioned, CGS2 Arnoldi, x0 = 0.
 // ---------------------------------------------------------------------------
+static size_t krylov_bytes(int64_t na, int m) {
+  const SmallLayout L{m};
+  return ((size_t)(2 * m + 2) * round_up(na, 64) + RED_MAX_BLOCKS * PART_LD + L.size()) * sizeof(double);
+}
+
 static int ensure_krylov(cpm_ctx* ctx, int m) {
   Dev& d = ctx->dev;
   if (d.restart == m && d.V) return CPM_OK;
@@ -543,6 +549,7 @@ static int ensure_krylov(cpm_ctx* ctx, int m) {
   SmallLayout L{m};
   HIPCHK(hipMalloc((void**)&d.V, (size_t)(m + 1) * d.ld * sizeof(double)));
   HIPCHK(hipMalloc((void**)&d.Z, (size_t)m * d.ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.F, (size_t)d.ld * sizeof(double)));
   HIPCHK(hipMalloc((void**)&d.part, (size_t)RED_MAX_BLOCKS * PART_LD * sizeof(double)));
   HIPCHK(hipMalloc((void**)&d.small, (size_t)L.size() * sizeof(double)));
   HIPCHK(hipHostMalloc((void**)&d.slots, (size_t)(m + 2) * sizeof(HostSlot),
@@ -551,7 +558,7 @@ static int ensure_krylov(cpm_ctx* ctx, int m) {
   HIPCHK(hipHostGetDevicePointer((void**)&d.slots_dev, d.slots, 0));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   d.restart = m;
-  d.krylov_bytes = ((size_t)(2 * m + 1) * d.ld + RED_MAX_BLOCKS * PART_LD + L.size()) * sizeof(double);
+  d.krylov_bytes = krylov_bytes(na, m);
   return CPM_OK;
 }
 
@@ -772,6 +779,61 @@ int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max
     if (rel <= tol) return finish(CPM_OK, n, rel);
     if (n >= max_iter || !std::isfinite(rel)) return finish(CPM_ENOTCONV, n, rel);
   }
+}
+
+// Device bytes of a factorisation before it is made: resident afterwards
+// (operator arrays, W arena and its index lists, Krylov space of `restart`)
+// and the peak while factoring (plus the bordered matrices, panel scratch and
+// assembly lists). Mirrors the allocations of dev_upload_operator, make_plan,
+// run_factor and ensure_krylov; the apply-block table is bounded by one entry
+// per W row.
+void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, size_t* peak) {
+  const Band& b = ctx->band;
+  const Decomp& D = ctx->dec;
+  const bool oras = D.kind == CPM_ORAS;
+  const size_t esz = prec == CPM_FP64 ? 8 : 4;
+  const size_t op = b.lines.size() * 4 + b.wts.size() * 8 + (size_t)b.n_act * 6 * 4 + (size_t)b.total() * 8;
+  int64_t a_elems = 0, w_elems = 0, scr = 0, u_total = 0, t_total = 0;
+  for (const Sub& s : D.subs) {
+    const int64_t m = (int64_t)s.sigma.size();
+    const int64_t n = m + (oras ? (int64_t)s.bnd.size() : 0);
+    const int64_t t = (int64_t)s.tilde.size();
+    a_elems += (n + t) * round_up(n + m, 16);
+    w_elems += t * round_up(m, 8);
+    scr += (int64_t)LU_NB * (n + t);
+    u_total += n;
+    t_total += t;
+  }
+  const size_t lists = (size_t)D.n_sub * sizeof(SubDesc) + (size_t)(u_total + 2 * t_total) * 4;
+  const size_t res = op + (size_t)w_elems * esz + lists + (restart > 0 ? krylov_bytes(b.n_act, restart) : 0);
+  const size_t work = (size_t)(a_elems + scr) * esz + (size_t)u_total * (5 * 4 + 2 * 8) + (size_t)t_total * 4 +
+                      (size_t)D.n_sub * (4 + 8);
+  if (resident) *resident = res;
+  if (peak) *peak = res + work;
+}
+
+// Implicit steps with resident factors: u_0 = A^{-1} f, u_k = A^{-1}(scale u_{k-1}).
+int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double scale, double tol, int max_iter,
+                    int m, cpm_solve_info* info) {
+  HIPCHK(hipSetDevice(ctx->device));
+  int rc = ensure_krylov(ctx, m);
+  if (rc != CPM_OK) return rc;
+  const int64_t na = ctx->band.n_act;
+  int worst = CPM_OK;
+  for (int k = 0; k < nsteps; ++k) {
+    const double* rhs = f;
+    if (k > 0) {
+      k_scale<<<nblk(na, 256), 256, 0, ctx->stream>>>(na, scale, u + (size_t)(k - 1) * na, ctx->dev.F);
+      HIPCHK(hipGetLastError());
+      rhs = ctx->dev.F;
+    }
+    cpm_solve_info tmp{};
+    rc = dev_solve(ctx, rhs, u + (size_t)k * na, tol, max_iter, m, &tmp);
+    if (info) info[k] = tmp;
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
 }
 
 template <typename T>

@@ -832,6 +832,12 @@ __global__ __launch_bounds__(256) void k_axpy(int64_t n, const double* __restric
   if (i < n) x[i] += z[i];
 }
 
+__global__ __launch_bounds__(256) void k_scale(int64_t n, double a, const double* __restrict__ x,
+                                               double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
 __global__ __launch_bounds__(256) void k_fill(int64_t n, double* __restrict__ x, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;

@@ -1,0 +1,359 @@
+"""Request loop for many closest point method solves on one GPU.
+
+Requests name a surface, a grid spacing h, a value of c and a number of
+sequential right-hand sides (implicit steps u^{n+1} = A^{-1}(c u^n)). The
+server
+
+* batches continuously: `slots` worker threads each drive one request at a
+  time on its own context (own HIP stream), so requests that arrive while
+  others run start as soon as a slot and device memory are free, and their
+  kernels overlap on the device;
+* keeps factorisations resident: one context per (surface, h, c level) holds
+  its restricted local solution operators until evicted (least recently used
+  first, never while in use); c is quantised to `c_levels` log-spaced levels
+  so that repeated requests hit the cache;
+* admits work by device memory: before factoring, the peak footprint of the
+  factorisation (cpm_footprint_estimate) plus the request's vectors must fit in
+  the budget, else idle cached factors are evicted, else the request waits;
+* shares host set-up: the band and partition of a (surface, h) are built once
+  on a host-only context and cloned onto the device for each c level;
+* records per-request arrival, start, finish, iteration counts and cache hits,
+  from which `summary()` gives p50/p99 latency and solves/s.
+
+Every computation runs in libcpm; this module only schedules calls to it.
+"""
+
+from __future__ import annotations
+
+import math
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import binding as B
+
+
+@dataclass
+class Request:
+    rid: int
+    surface: str
+    h: float
+    c: float
+    nsteps: int
+    seed: int
+    arrival: float = 0.0  # seconds after the server's start
+
+
+@dataclass
+class Result:
+    rid: int
+    key: tuple
+    c_used: float
+    arrival: float
+    start: float = math.nan
+    finish: float = math.nan
+    hit: bool = False
+    iters: list = field(default_factory=list)
+    relres: list = field(default_factory=list)
+    status: int = 0
+    error: str = ""
+    u: np.ndarray | None = None
+
+    @property
+    def latency(self):
+        return self.finish - self.arrival
+
+
+class _Entry:
+    def __init__(self, ctx, resident):
+        self.ctx = ctx
+        self.resident = resident
+        self.busy = False
+        self.last_used = 0.0
+
+
+class Server:
+    """Continuous-batching solve server on one device (see the module docstring).
+
+    surfaces: name -> (surface object with .cp(x), rhs(cp_actives, seed) -> f).
+    """
+
+    def __init__(self, surfaces, device=0, slots=4, budget_bytes=None, prec=B.FP32, restart=30, tol=1e-8,
+                 max_iter=3000, degree=3, overlap=3, nodes_per_sub=2200, c_range=(0.1, 10.0), c_levels=16,
+                 keep_solutions=False):
+        import torch
+
+        self.torch = torch
+        self.surfaces = dict(surfaces)
+        self.device = int(device)
+        self.slots = int(slots)
+        self.prec, self.restart, self.tol, self.max_iter = prec, int(restart), float(tol), int(max_iter)
+        self.degree, self.overlap, self.nodes_per_sub = int(degree), int(overlap), int(nodes_per_sub)
+        lo, hi = c_range
+        self.c_grid = np.exp(np.linspace(math.log(lo), math.log(hi), int(c_levels)))
+        self.keep = bool(keep_solutions)
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            budget_bytes = int(0.85 * free)
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.peak_used = 0
+        self._lock = threading.Condition()
+        self._bases = {}          # (surface, h) -> (host ctx, cp of actives, n_act)
+        self._base_locks = {}
+        self._cache = {}          # key -> _Entry
+        self._building = set()    # keys being factored
+        self._claimed = set()     # keys of requests taken by a slot
+        self.evictions = 0
+        self.factor_s = 0.0
+        self.n_factor = 0
+
+    # ---- keys and host set-up --------------------------------------------------------
+    def quantise(self, c):
+        """Nearest of the log-spaced c levels (in log distance)."""
+        k = int(np.argmin(np.abs(np.log(self.c_grid) - math.log(c))))
+        return float(self.c_grid[k])
+
+    def key(self, req):
+        return (req.surface, float(req.h), self.quantise(req.c))
+
+    def _base(self, surface, h):
+        k = (surface, float(h))
+        with self._lock:
+            lk = self._base_locks.setdefault(k, threading.Lock())
+        with lk:
+            if k not in self._bases:
+                surf, _ = self.surfaces[surface]
+                ctx = B.Context(-1)
+                ctx.build_band(surf, h, self.degree)
+                na = ctx.band_sizes()[0]
+                cp = ctx.band_arrays(self.degree)["cp"][:na].copy()
+                ctx.build_operator(1.0)
+                n_sub = max(1, int(round(na / self.nodes_per_sub)))
+                ctx.partition(B.PART_RCB, n_sub, None, self.overlap, B.ORAS, h ** -0.5, 1.0 / h)
+                self._bases[k] = (ctx, cp, na)
+            return self._bases[k]
+
+    # ---- device memory ledger -----------------------------------------------------------
+    def _reserve(self, nbytes, evictable=True):
+        """Block until nbytes fit in the budget (evicting idle factors). Caller holds the lock."""
+        if nbytes > self.budget:
+            raise MemoryError(f"request needs {nbytes} bytes, budget {self.budget}")
+        while self.used + nbytes > self.budget:
+            idle = [(e.last_used, k) for k, e in self._cache.items() if not e.busy]
+            if evictable and idle:
+                _, k = min(idle)
+                e = self._cache.pop(k)
+                e.ctx.close()
+                self.used -= e.resident
+                self.evictions += 1
+                continue
+            self._lock.wait(0.05)
+        self.used += nbytes
+        self.peak_used = max(self.peak_used, self.used)
+
+    def _release(self, nbytes):
+        self.used -= nbytes
+        self._lock.notify_all()
+
+    # ---- one request ----------------------------------------------------------------------
+    def _acquire_entry(self, req, res):
+        k = res.key
+        with self._lock:
+            while True:
+                e = self._cache.get(k)
+                if e is not None and not e.busy:
+                    e.busy = True
+                    res.hit = True
+                    return e
+                if e is None and k not in self._building:
+                    self._building.add(k)
+                    break
+                self._lock.wait(0.05)
+        try:
+            base, _, _ = self._base(req.surface, req.h)
+            resident, peak = base.footprint_estimate(self.prec, self.restart)
+            with self._lock:
+                self._reserve(peak)
+            t0 = time.perf_counter()
+            ctx = None
+            try:
+                ctx = base.clone(self.device)
+                ctx.build_operator(k[2])
+                ctx.factor(self.prec)
+            except Exception:
+                with self._lock:
+                    self._release(peak)
+                if ctx is not None:
+                    ctx.close()
+                raise
+            dt = time.perf_counter() - t0
+            e = _Entry(ctx, resident)
+            e.busy = True
+            with self._lock:
+                self.factor_s += dt
+                self.n_factor += 1
+                self._release(peak - resident)
+                self._cache[k] = e
+            return e
+        finally:
+            with self._lock:
+                self._building.discard(k)
+                self._lock.notify_all()
+
+    def _run(self, req, res, stream):
+        torch = self.torch
+        _, cp, na = self._base(req.surface, req.h)
+        _, rhs = self.surfaces[req.surface]
+        f = np.ascontiguousarray(rhs(cp, req.seed), dtype=np.float64)
+        vec_bytes = (req.nsteps + 1) * na * 8
+        with self._lock:
+            self._reserve(vec_bytes)
+        try:
+            e = self._acquire_entry(req, res)
+            try:
+                with torch.cuda.stream(stream):
+                    f_dev = torch.from_numpy(f).to(f"cuda:{self.device}")
+                    u_dev = torch.empty((req.nsteps, na), dtype=torch.float64, device=f"cuda:{self.device}")
+                stream.synchronize()
+                info, rc = e.ctx.solve_steps(f_dev, u_dev, res.c_used, tol=self.tol, max_iter=self.max_iter,
+                                             restart=self.restart, sync=False)
+                res.iters = [q["iters"] for q in info]
+                res.relres = [q["relres_true"] for q in info]
+                res.status = rc
+                if self.keep:
+                    res.u = u_dev.cpu().numpy()
+                del f_dev, u_dev
+            finally:
+                with self._lock:
+                    e.busy = False
+                    e.last_used = time.perf_counter()
+                    self._lock.notify_all()
+        finally:
+            with self._lock:
+                self._release(vec_bytes)
+
+    # ---- the loop ----------------------------------------------------------------------------
+    def run(self, requests, realtime=True):
+        """Serve `requests` (arrival times in seconds from now). With realtime=False
+        every request is available at once. Returns a list of Result (request order)."""
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        results = {r.rid: Result(r.rid, self.key(r), self.key(r)[2], r.arrival if realtime else 0.0) for r in reqs}
+        pending = []
+        state = {"next": 0, "done": 0, "error": None}
+        t_start = time.perf_counter()
+        self._t0 = t_start
+
+        def now():
+            return time.perf_counter() - t_start
+
+        def pick():
+            # earliest-arrived request whose factors no other slot is using
+            for q, r in enumerate(pending):
+                if results[r.rid].key not in self._claimed:
+                    self._claimed.add(results[r.rid].key)
+                    return pending.pop(q)
+            return None
+
+        def worker(wid):
+            stream = torch.cuda.Stream(device=self.device)
+            while True:
+                with self._lock:
+                    while True:
+                        if state["error"] is not None:
+                            return
+                        r = pick()
+                        if r is not None:
+                            break
+                        if state["next"] >= len(reqs) and not pending:
+                            return
+                        self._lock.wait(0.01)
+                res = results[r.rid]
+                res.start = now()
+                try:
+                    self._run(r, res, stream)
+                except Exception as exc:  # recorded; the loop stops admitting new work
+                    res.error = f"{type(exc).__name__}: {exc}"
+                    with self._lock:
+                        state["error"] = res.error
+                        self._lock.notify_all()
+                res.finish = now()
+                with self._lock:
+                    self._claimed.discard(res.key)
+                    state["done"] += 1
+                    self._lock.notify_all()
+
+        threads = [threading.Thread(target=worker, args=(w,), daemon=True) for w in range(self.slots)]
+        for t in threads:
+            t.start()
+        # arrivals
+        for i, r in enumerate(reqs):
+            if realtime:
+                delay = r.arrival - now()
+                if delay > 0:
+                    time.sleep(delay)
+            if state["error"] is not None:
+                break
+            with self._lock:
+                pending.append(r)
+                state["next"] = i + 1
+                self._lock.notify_all()
+        for t in threads:
+            t.join()
+        self.makespan = now()
+        if state["error"] is not None:
+            raise RuntimeError(f"serving stopped: {state['error']}")
+        return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+    def close(self):
+        with self._lock:
+            for e in self._cache.values():
+                e.ctx.close()
+            self._cache.clear()
+            self.used = 0
+            for ctx, _, _ in self._bases.values():
+                ctx.close()
+            self._bases.clear()
+
+
+def summary(results, makespan):
+    """Latency percentiles (ms, arrival to last right-hand side) and throughput."""
+    lat = np.array([r.latency for r in results]) * 1e3
+    solves = sum(len(r.iters) for r in results)
+    return {
+        "requests": len(results),
+        "solves": int(solves),
+        "solves_per_s": solves / makespan if makespan > 0 else math.nan,
+        "requests_per_s": len(results) / makespan if makespan > 0 else math.nan,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "max_ms": float(lat.max()),
+        "hit_rate": float(np.mean([r.hit for r in results])),
+        "mean_iters": float(np.mean([np.mean(r.iters) for r in results if r.iters])),
+        "worst_relres": float(max(max(r.relres) for r in results if r.relres)),
+        "makespan_s": makespan,
+    }
+
+
+def poisson_requests(n, rate, surfaces, hs, seed, c_range=(0.1, 10.0), steps=(1, 32), c_sigma=1.0):
+    """n requests with exponential inter-arrival times (rate per second), surfaces
+    and h uniform, c log-normal (median sqrt(lo hi)) truncated to c_range by
+    redrawing, steps uniform on the inclusive range, RHS seeds from the stream."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n)) if rate > 0 else np.zeros(n)
+    lo, hi = c_range
+    mu = 0.5 * (math.log(lo) + math.log(hi))
+    out = []
+    for i in range(n):
+        while True:
+            c = float(math.exp(rng.normal(mu, c_sigma)))
+            if lo <= c <= hi:
+                break
+        out.append(Request(rid=i, surface=surfaces[int(rng.integers(len(surfaces)))],
+                           h=float(hs[int(rng.integers(len(hs)))]), c=c,
+                           nsteps=int(rng.integers(steps[0], steps[1] + 1)), seed=int(rng.integers(1 << 31)),
+                           arrival=float(t[i])))
+    return out
