@@ -12,6 +12,14 @@ resident in HBM; factorisation is timed separately. Both local-factor
 precisions are measured: `value` is the plain FP64 form, the FP32-factor form
 (FP64 Krylov) is reported beside it.
 
+A serving leg follows (`serving` in the output): a request loop over a mix of
+surfaces (unit sphere, torus R = 1, r = 0.4, bumpy icosphere with 20480
+triangles) and grid spacings h in {0.05, 0.025}, Poisson arrivals at 80% of the
+solve capacity with cached factors measured just before, c log-normal on [0.1, 10] quantised to 16
+levels, 1-32 implicit steps per request, cached FP32 factors, admission by
+device-memory footprint; it reports p50/p99 latency (arrival to last step) and
+solves/s.
+
 Prints one JSON line.
 """
 
@@ -210,6 +218,63 @@ def run_gpu(args):
     return res, na
 
 
+SERVE_HS = (0.05, 0.025)
+SERVE_SLOTS = 4
+
+
+def serve_surfaces():
+    import cpm_inputs as ci
+    return {
+        "sphere": (ci.Sphere(), lambda cp, seed: ci.rhs_surface_bumps(cp, seed)),
+        "torus": (ci.Torus(1.0, 0.4), lambda cp, seed: ci.rhs_torus_bumps(cp, 1.0, 0.4, seed)),
+        # closest points are searched out to 6 h, beyond every band node
+        "bumpy_icosphere": (lambda h: ci.bumpy_icosphere(level=5, amplitude=0.05, lmax=6, seed=4, far=6 * h),
+                            lambda cp, seed: ci.rhs_surface_bumps(cp, seed)),
+    }
+
+
+def run_serving(n_requests):
+    """Serving leg: prepare the host set-up of every (surface, h), calibrate the
+    solve capacity with one cached factorisation per (surface, h), then serve
+    Poisson arrivals at 80% of it."""
+    import torch
+    import paper_1909_08734_amd as P
+    from paper_1909_08734_amd import serve
+
+    surfaces = serve_surfaces()
+    srv = serve.Server(surfaces, slots=SERVE_SLOTS, prec=P.FP32, restart=RESTART, tol=TOL)
+    names = sorted(surfaces)
+    t0 = time.time()
+    pairs = [(name, h) for name in names for h in SERVE_HS]
+    for name, h in pairs:
+        srv._base(name, h)
+    log(f"serving: host set-up of {len(pairs)} (surface, h) pairs {time.time() - t0:.1f}s")
+    # capacity: two steps per (surface, h) near c = 1, run once to factor and
+    # once more with the factors cached (the second run is the one measured)
+    calib = [serve.Request(rid=q, surface=n, h=h, c=1.0, nsteps=2, seed=100 + q, arrival=0.0)
+             for q, (n, h) in enumerate(pairs)]
+    srv.run(calib, realtime=False)
+    srv.run(calib, realtime=False)
+    mean_step = srv.makespan / (2 * len(calib))  # device time per step with all slots busy
+    mean_service = mean_step * 16.5  # mean of 1..32 steps
+    rate = 0.8 / mean_service
+    reqs = serve.poisson_requests(n_requests, rate, names, list(SERVE_HS), seed=6)
+    log(f"serving: step {mean_step * 1e3:.1f} ms mean -> rate {rate:.2f}/s, {n_requests} requests")
+    torch.cuda.synchronize()
+    out = srv.run(reqs, realtime=True)
+    st = serve.summary(out, srv.makespan)
+    st.update({
+        "workload": "mix: sphere, torus(1,0.4), bumpy icosphere (20480 triangles) x h {0.05, 0.025}",
+        "arrival_rate_per_s": rate, "slots": SERVE_SLOTS, "c_levels": 16, "steps_per_request": "1-32",
+        "factors": "fp32 (fp64 krylov)", "budget_GB": srv.budget / 1e9, "peak_reserved_GB": srv.peak_used / 1e9,
+        "evictions": srv.evictions, "factorisations": srv.n_factor - len(calib),
+        "factor_s_total": srv.factor_s, "calibration_step_ms": mean_step * 1e3,
+        "failed": int(sum(1 for r in out if r.status != P.OK)),
+    })
+    srv.close()
+    return st
+
+
 def cpu_baseline(gpu_iters):
     """The oracle as it stands, timed on a bounded sample of the same workload:
     local LU solves of 4 of the 64 subdomains (scaled by 16), one CSR operator
@@ -264,6 +329,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="check the last solve with the oracle")
+    ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "
@@ -312,6 +378,9 @@ def main():
             "kernel_source_hash": src,
         },
     }
+    if args.serve_requests > 0:
+        out["serving"] = run_serving(args.serve_requests)
+        log(f"serving: {json.dumps(out['serving'])}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r64["iters_mean"])
     print(json.dumps(out), flush=True)

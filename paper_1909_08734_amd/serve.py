@@ -77,7 +77,9 @@ class _Entry:
 class Server:
     """Continuous-batching solve server on one device (see the module docstring).
 
-    surfaces: name -> (surface object with .cp(x), rhs(cp_actives, seed) -> f).
+    surfaces: name -> (surface, rhs) with rhs(cp_actives, seed) -> f, and surface
+    either an object with .cp(x) or a callable h -> such an object (e.g. a mesh
+    whose closest-point search radius depends on the band width).
     """
 
     def __init__(self, surfaces, device=0, slots=4, budget_bytes=None, prec=B.FP32, restart=30, tol=1e-8,
@@ -126,6 +128,8 @@ class Server:
         with lk:
             if k not in self._bases:
                 surf, _ = self.surfaces[surface]
+                if not hasattr(surf, "cp"):
+                    surf = surf(h)
                 ctx = B.Context(-1)
                 ctx.build_band(surf, h, self.degree)
                 na = ctx.band_sizes()[0]
