@@ -44,6 +44,38 @@ OVERLAP = 3
 ALPHAS = (("alpha_1/h", 1.0 / H, 0.0), ("alpha_h^-1/2_cross_1/h", H ** -0.5, 1.0 / H))
 TOL = 1e-8
 RESTART = 30
+
+
+def workloads():
+    """The benchmark configurations (the first is the default line)."""
+    import cpm_inputs as ci
+    return {
+        "sphere_h0.025_rcb64_oras": dict(
+            surface=lambda: ci.Sphere(), h=H, c=C_SHIFT, method="rcb", n_sub=N_SUB, weights=None,
+            overlap=OVERLAP, kind="ORAS", alphas=ALPHAS, tol=TOL, precs=("fp64", "fp32"),
+            rhs=lambda cp, q: ci.rhs_sphere_random_sh(cp, C_SHIFT, seed=1 + q)[0],
+            rhs_name="seeded random spherical harmonics l<=4", surface_name="unit sphere"),
+        "sphere_h0.1_octant8_ras": dict(
+            surface=lambda: ci.Sphere(), h=0.1, c=1.0, method="octant", n_sub=8, weights=None, overlap=2,
+            kind="RAS", alphas=(("ras", 0.0, 0.0),), tol=1e-10, precs=("fp64", "fp32"),
+            rhs=lambda cp, q: ci.rhs_sphere_y20(cp, 1.0), rhs_name="(c+6) Y_2^0", surface_name="unit sphere"),
+        "torus_h0.0125_wrcb256_oras": dict(
+            surface=lambda: ci.Torus(1.0, 0.4), h=0.0125, c=0.5, method="rcb", n_sub=256,
+            weights=lambda: ci.wrcb_weights(256, seed=2), overlap=3, kind="ORAS",
+            alphas=(("alpha_h^-1/2_cross_1/h", 0.0125 ** -0.5, 1.0 / 0.0125),), tol=TOL, precs=("fp32", "fp64"),
+            rhs=lambda cp, q: ci.rhs_torus_bumps(cp, 1.0, 0.4, seed=3 + q),
+            rhs_name="16 seeded Gaussian bumps (sigma 0.2)", surface_name="torus R=1 r=0.4"),
+        "bumpy_icosphere_h0.02_rcb128_oras": dict(
+            surface=lambda: ci.bumpy_icosphere(level=5, amplitude=0.05, lmax=6, seed=4, far=0.12), h=0.02, c=1.0,
+            method="rcb", n_sub=128, weights=None, overlap=3, kind="ORAS",
+            alphas=(("alpha_h^-1/2_cross_1/h", 0.02 ** -0.5, 1.0 / 0.02),), tol=TOL, precs=("fp64", "fp32"),
+            rhs=lambda cp, q: ci.rhs_surface_bumps(cp, seed=5 + q),
+            rhs_name="16 seeded Gaussian bumps (sigma 0.2)",
+            surface_name="icosphere, 20480 triangles, seeded l<=6 radial bumps (amplitude 0.05)"),
+    }
+
+
+DEFAULT_WORKLOAD = "sphere_h0.025_rcb64_oras"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
@@ -116,30 +148,35 @@ def pmc_traffic(kind, source_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_gpu(args):
+def run_gpu(args, wl):
     import torch
-    import cpm_inputs as ci
     import paper_1909_08734_amd as P
 
     ctx = P.Context(0)
     t0 = time.time()
-    ctx.build_band(ci.Sphere(), H, 3)
-    ctx.build_operator(C_SHIFT)
+    surf = wl["surface"]()
+    ctx.build_band(surf, wl["h"], 3)
+    ctx.build_operator(wl["c"])
     na, ng, _ = ctx.band_sizes()
     cp = ctx.band_arrays(3)["cp"][:na]
     log(f"band {time.time() - t0:.1f}s  N_A={na} N_G={ng}")
     nrhs = args.warmup + args.steps
-    F = np.stack([ci.rhs_sphere_random_sh(cp, C_SHIFT, seed=1 + q)[0] for q in range(nrhs)])
+    F = np.stack([wl["rhs"](cp, q) for q in range(nrhs)])
     f_dev = torch.from_numpy(F).cuda()
     u_dev = torch.zeros_like(f_dev)
     torch.cuda.synchronize()
+    kind = P.ORAS if wl["kind"] == "ORAS" else P.RAS
+    method = P.PART_OCTANT if wl["method"] == "octant" else P.PART_RCB
+    weights = wl["weights"]() if wl["weights"] else None
+    n_sub, tol = wl["n_sub"], wl["tol"]
     res = {}
-    for a_name, alpha, alpha_x in ALPHAS:
+    for a_name, alpha, alpha_x in wl["alphas"]:
         t0 = time.time()
-        ctx.partition(P.PART_RCB, N_SUB, None, OVERLAP, P.ORAS, alpha, alpha_x)
+        ctx.partition(method, n_sub, weights, wl["overlap"], kind, alpha, alpha_x)
         log(f"{a_name}: partition {time.time() - t0:.1f}s")
         res[a_name] = {}
-        for prec_name, prec, esz in (("fp64", P.FP64, 8), ("fp32", P.FP32, 4)):
+        for prec_name in wl["precs"]:
+            prec, esz = (P.FP64, 8) if prec_name == "fp64" else (P.FP32, 4)
             ctx.set_timing(True)
             t0 = time.time()
             ctx.factor(prec)
@@ -147,13 +184,13 @@ def run_gpu(args):
             gemm_ms, gemm_n = ctx.kernel_time(P.TIMER_LU_GEMM)
             ctx.set_timing(False)
             for q in range(args.warmup):
-                ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
+                ctx.solve_device(f_dev[q], u_dev[q], tol=tol, max_iter=3000, restart=RESTART)
             # timed region: K solves, nothing else on the stream
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             infos = []
             for q in range(args.warmup, nrhs):
-                info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
+                info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=tol, max_iter=3000, restart=RESTART)
                 if rc != P.OK:
                     raise RuntimeError(f"solve did not converge: {info}")
                 infos.append(info[0])
@@ -163,16 +200,16 @@ def run_gpu(args):
             # stamped by HIP events on the context stream (per-kernel durations)
             ctx.set_timing(True)
             for q in range(args.warmup, nrhs):
-                ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=RESTART)
+                ctx.solve_device(f_dev[q], u_dev[q], tol=tol, max_iter=3000, restart=RESTART)
             pre_ms, pre_n = ctx.kernel_time(P.TIMER_PRECOND)
             ext_ms, ext_n = ctx.kernel_time(P.TIMER_EXTEND)
             st_ms, st_n = ctx.kernel_time(P.TIMER_STENCIL)
             ctx.set_timing(False)
             lat = np.array([i["ms"] for i in infos])
             its = np.array([i["iters"] for i in infos])
-            bytes_apply, _ = precond_bytes(ctx, N_SUB, esz)
+            bytes_apply, _ = precond_bytes(ctx, n_sub, esz)
             avg_pre = pre_ms / max(pre_n, 1)
-            flops = lu_flops(ctx, N_SUB, True)
+            flops = lu_flops(ctx, n_sub, kind == P.ORAS)
             r = {
                 "solves_per_s": args.steps / wall,
                 "ms_per_solve": 1e3 * wall / args.steps,
@@ -191,13 +228,13 @@ def run_gpu(args):
                 "stencil_ms_avg": st_ms / max(st_n, 1),
                 "footprint_GB": ctx.footprint_bytes() / 1e9,
             }
-            if a_name == ALPHAS[0][0]:
+            if a_name == wl["alphas"][0][0] and args.restart60:
                 # longer restart cycles: fewer iterations, same factors
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 its60 = []
                 for q in range(args.warmup, nrhs):
-                    info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=TOL, max_iter=1000, restart=60)
+                    info, rc = ctx.solve_device(f_dev[q], u_dev[q], tol=tol, max_iter=3000, restart=60)
                     if rc != P.OK:
                         raise RuntimeError(f"solve did not converge: {info}")
                     its60.append(info[0]["iters"])
@@ -209,8 +246,8 @@ def run_gpu(args):
             log(f"{a_name} {prec_name}: {json.dumps(r)}")
             if args.check:
                 import oracle
-                b = oracle.build_band(ci.Sphere(), H, 3, [-2.0] * 3, [2.0] * 3)
-                A = oracle.stabilized_operator(b, C_SHIFT)
+                b = oracle.build_band(surf, wl["h"], 3, [-2.0] * 3, [2.0] * 3)
+                A = oracle.stabilized_operator(b, wl["c"])
                 u = u_dev[nrhs - 1].cpu().numpy()
                 rr = np.linalg.norm(F[nrhs - 1] - A @ u) / np.linalg.norm(F[nrhs - 1])
                 log(f"{a_name} {prec_name}: oracle residual of the last solve {rr:.3e}")
@@ -275,12 +312,11 @@ def run_serving(n_requests):
     return st
 
 
-def cpu_baseline(gpu_iters):
+def cpu_baseline(wl, gpu_iters):
     """The oracle as it stands, timed on a bounded sample of the same workload:
-    local LU solves of 4 of the 64 subdomains (scaled by 16), one CSR operator
+    local LU solves of 4 subdomains (scaled to all of them), one CSR operator
     apply and one modified Gram-Schmidt pass at the mean Krylov depth; solves/s
     = 1 / (iterations x per-iteration time), iterations taken from the GPU run."""
-    import cpm_inputs as ci
     import oracle
     from oracle import schwarz
     try:
@@ -288,21 +324,26 @@ def cpu_baseline(gpu_iters):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    b = oracle.build_band(ci.Sphere(), H, 3, [-2.0] * 3, [2.0] * 3)
-    A = oracle.stabilized_operator(b, C_SHIFT)
-    _, alpha, alpha_x = ALPHAS[0]
-    dec = schwarz.decompose(b, oracle.rcb_partition(b, N_SUB), OVERLAP, "ORAS", alpha=alpha,
-                            alpha_cross=alpha_x)
-    sample = [0, 21, 42, 63]
+    h, c, n_sub = wl["h"], wl["c"], wl["n_sub"]
+    b = oracle.build_band(wl["surface"](), h, 3, [-2.0] * 3, [2.0] * 3)
+    A = oracle.stabilized_operator(b, c)
+    _, alpha, alpha_x = wl["alphas"][0]
+    if wl["method"] == "octant":
+        part = oracle.octant_partition(b)
+    else:
+        part = oracle.rcb_partition(b, n_sub, weights=wl["weights"]() if wl["weights"] else None)
+    sample = sorted({0, n_sub // 3, (2 * n_sub) // 3, n_sub - 1})
+    dec = schwarz.decompose(b, part, wl["overlap"], wl["kind"], alpha=alpha, alpha_cross=alpha_x,
+                            only=set(sample))
     t0 = time.perf_counter()
-    M = schwarz.Preconditioner(b, dec, C_SHIFT, subs=sample)
+    M = schwarz.Preconditioner(b, dec, c, subs=sample)
     factor_s = time.perf_counter() - t0
     v = np.random.default_rng(0).standard_normal(b.n_act)
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
         M.apply(v)
-    t_pre = (time.perf_counter() - t0) / reps * (N_SUB / len(sample))
+    t_pre = (time.perf_counter() - t0) / reps * (n_sub / len(sample))
     t0 = time.perf_counter()
     for _ in range(reps):
         A @ v
@@ -316,10 +357,10 @@ def cpu_baseline(gpu_iters):
     t_mgs = time.perf_counter() - t0
     per_iter = t_pre + t_op + t_mgs
     return {"value": 1.0 / (gpu_iters * per_iter), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"oracle dense-LU local solves of 4/64 subdomains scaled x16 "
-                       f"({t_pre * 1e3:.0f} ms/apply), CSR A.v ({t_op * 1e3:.1f} ms), one MGS pass "
-                       f"at depth {k} ({t_mgs * 1e3:.1f} ms), x {gpu_iters:.1f} iterations; "
-                       f"oracle factor of the 4 sampled subdomains {factor_s:.1f}s (excluded)")}
+            "sample": (f"oracle dense-LU local solves of {len(sample)}/{n_sub} subdomains scaled "
+                       f"x{n_sub / len(sample):g} ({t_pre * 1e3:.0f} ms/apply), CSR A.v ({t_op * 1e3:.1f} ms), "
+                       f"one MGS pass at depth {k} ({t_mgs * 1e3:.1f} ms), x {gpu_iters:.1f} iterations; "
+                       f"oracle factor of the {len(sample)} sampled subdomains {factor_s:.1f}s (excluded)")}
 
 
 def main():
@@ -330,14 +371,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="check the last solve with the oracle")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads()),
+                    help="benchmark configuration (default: the headline one)")
+    ap.add_argument("--no-restart60", dest="restart60", action="store_false",
+                    help="skip the FGMRES(60) comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "
               "design, not a build", file=sys.stderr)
         sys.exit(2)
-    res, na = run_gpu(args)
+    wl = workloads()[args.workload]
+    default = args.workload == DEFAULT_WORKLOAD
+    res, na = run_gpu(args, wl)
     src = kernel_source_hash()
-    head = ALPHAS[0][0]
+    head = wl["alphas"][0][0]
     r64 = res[head]["fp64"]
     r32 = res[head]["fp32"]
     sweep = {a: {p: {k: v[k] for k in ("solves_per_s", "p50_ms", "p99_ms", "iters_mean", "factor_s",
@@ -356,10 +403,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "sphere_h0.025_rcb64_oras", "surface": "unit sphere", "h": H, "N_A": na,
-                   "degree": 3, "c": C_SHIFT, "n_sub": N_SUB, "overlap": OVERLAP, "alpha": ALPHAS[0][1],
-                   "alpha_cross": ALPHAS[0][2], "restart": RESTART, "tol": TOL,
-                   "rhs": "seeded random spherical harmonics l<=4"},
+        "config": {"workload": args.workload, "surface": wl["surface_name"], "h": wl["h"], "N_A": na,
+                   "degree": 3, "c": wl["c"], "partition": wl["method"] + (" weighted" if wl["weights"] else ""),
+                   "n_sub": wl["n_sub"], "overlap": wl["overlap"], "kind": wl["kind"],
+                   "alpha": wl["alphas"][0][1], "alpha_cross": wl["alphas"][0][2], "restart": RESTART,
+                   "tol": wl["tol"], "rhs": wl["rhs_name"]},
         "p50_ms": r64["p50_ms"],
         "p99_ms": r64["p99_ms"],
         "fp64_factors": r64,
@@ -372,17 +420,17 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r64["precond_GBs"] / HBM_PEAK_GBS,
-            "traffic": pmc_traffic("fp64", src),
+            "traffic": pmc_traffic("fp64", src) if default else None,
             "algorithmic_bytes_per_launch": r64["precond_bytes"],
             "avg_launch_ms": r64["precond_ms_avg"],
             "kernel_source_hash": src,
         },
     }
-    if args.serve_requests > 0:
+    if args.serve_requests > 0 and default:
         out["serving"] = run_serving(args.serve_requests)
         log(f"serving: {json.dumps(out['serving'])}")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(r64["iters_mean"])
+        out["cpu_baseline"] = cpu_baseline(wl, r64["iters_mean"])
     print(json.dumps(out), flush=True)
 
 
