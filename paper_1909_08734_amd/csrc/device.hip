@@ -137,19 +137,27 @@ int dev_upload_operator(cpm_ctx* ctx) {
   return CPM_OK;
 }
 
+// e = E x over the whole band (active and ghost rows)
+static void launch_extend(cpm_ctx* ctx, const double* x) {
+  const Band& b = ctx->band;
+  Dev& d = ctx->dev;
+  const int64_t nt = b.total();
+  if (b.p == 3)
+    launch(ctx, TIMER_EXTEND, k_extend<3>, dim3(nblk(nt * 4, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
+           (const double*)d.wts, x, d.e);
+  else
+    launch(ctx, TIMER_EXTEND, k_extend<2>, dim3(nblk(nt * 4, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
+           (const double*)d.wts, x, d.e);
+}
+
 // e = E x, y = A x (or y = f - A x when f != nullptr)
 static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const double* f) {
   const Band& b = ctx->band;
   Dev& d = ctx->dev;
   const double ih2 = 1.0 / (b.h * b.h);
   const double diag = ctx->c + 6.0 * ih2;
-  const int64_t nt = b.total(), na = b.n_act;
-  if (b.p == 3)
-    launch(ctx, TIMER_EXTEND, k_extend<3>, dim3(nblk(nt * 16, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
-           (const double*)d.wts, x, d.e);
-  else
-    launch(ctx, TIMER_EXTEND, k_extend<2>, dim3(nblk(nt * 16, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
-           (const double*)d.wts, x, d.e);
+  const int64_t na = b.n_act;
+  launch_extend(ctx, x);
   launch(ctx, TIMER_STENCIL, k_stencil, dim3(nblk(na, 256)), dim3(256), 0, na, diag, ih2, (const int32_t*)d.nbr, x,
          (const double*)d.e, f, y);
 }
@@ -573,14 +581,16 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   double* scal = sm + L.scal();
   hipStream_t st = ctx->stream;
   const unsigned gv = nblk(na, 256);
+  const double ih2 = 1.0 / (ctx->band.h * ctx->band.h);
+  const double diag = ctx->c + 6.0 * ih2;
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, st));
 
-  // The last block of k_cgs3 / k_norm_init writes the scalars of a step into
-  // mapped pinned memory and then the step's ticket; the host polls for it
-  // (and checks the stream for errors while it waits).
+  // k_arnoldi / k_norm_finish write the scalars of a step into mapped pinned
+  // memory and then the step's ticket; the host polls for it (and checks the
+  // stream for errors while it waits).
   HostSlot* slots = d.slots;
   HostSlot* slots_dev = d.slots_dev;
   std::vector<unsigned long long> expect(m + 2, 0);
@@ -650,9 +660,11 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
     double* w = d.V + (size_t)(k + 1) * d.ld;
     double* zk = d.Z + (size_t)k * d.ld;
     launch_precond(ctx, vk, zk, scal + S_INV);  // z_k = M^{-1} (V[k] / ||V[k]||)
-    launch_operator(ctx, zk, w, nullptr);       // w = A z_k
-    // CGS pass 1 (normalising V[k] in place), pass 2, then ||w|| and the Givens update
-    k_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k + 1, w, d.part, k, scal + S_INV);
+    launch_extend(ctx, zk);                     // e = E z_k
+    // w = A z_k fused with CGS pass 1 (normalising V[k] in place), then pass 2,
+    // ||w|| and the Givens update
+    k_stencil_dots<<<rb, RED_THREADS, 0, st>>>(na, diag, ih2, d.nbr, zk, d.e, w, d.V, d.ld, k + 1, d.part, k,
+                                               scal + S_INV);
     k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h1());
     k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0);
     k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h2());

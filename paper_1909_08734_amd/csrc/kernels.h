@@ -32,37 +32,48 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
 // ---------------------------------------------------------------------------
 // Operator apply (Section 2.1): e = E x over all band rows, then
 // y = (c + 6/h^2) x - (1/h^2) sum_{6 neighbours} e.
-// Extension: 16 lanes per row, one lane per stencil z-line (a, b); the lane
-// interpolates along z, weights by w_x[a] w_y[b], the 16 lanes reduce.
+// Extension: 4 lanes per row; lane a takes the stencil plane x = base_x + a,
+// interpolates each of its p+1 z-lines (p+1 consecutive band entries) with
+// w_z, combines them with w_y, scales by w_x[a]; the 4 lanes then reduce.
+// (Fewer, longer lanes per row keep more independent gathers in flight per
+// lane than one lane per z-line.)
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
                                                 const double* __restrict__ wts,
                                                 const double* __restrict__ x, double* __restrict__ e) {
   constexpr int P1 = P + 1, NL = P1 * P1, NW = 3 * P1;
-  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  const int q = threadIdx.x & 15;
-  const bool live = row < n_rows;
-  // lane q holds weight q of the row (w_x[0..p], w_y[0..p], w_z[0..p]); the
-  // 16-lane group shares them by shuffles
-  const double wq = (live && q < NW) ? wts[row * NW + q] : 0.0;
-  const int a = q / P1, b = q - (q / P1) * P1;
-  const double wxa = __shfl(wq, a, 16);
-  const double wyb = __shfl(wq, P1 + b, 16);
-  double wz[P1];
-#pragma unroll
-  for (int c = 0; c < P1; ++c) wz[c] = __shfl(wq, 2 * P1 + c, 16);
+  static_assert(P1 <= 4, "at most 4 lanes per row");
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  const int a = threadIdx.x & 3;
   double acc = 0.0;
-  if (live && q < NL) {
-    const int32_t s = lines[row * NL + q];
-    double lz = 0.0;
+  if (row < n_rows && a < P1) {
+    const double* w = wts + row * NW;
+    int32_t s[P1];
+    if constexpr (P1 == 4) {
+      typedef int32_t i4v __attribute__((ext_vector_type(4)));
+      const i4v v = *reinterpret_cast<const i4v*>(lines + row * NL + a * P1);
 #pragma unroll
-    for (int c = 0; c < P1; ++c) lz += wz[c] * x[s + c];
-    acc = (wxa * wyb) * lz;
+      for (int b = 0; b < P1; ++b) s[b] = v[b];
+    } else {
+#pragma unroll
+      for (int b = 0; b < P1; ++b) s[b] = lines[row * NL + a * P1 + b];
+    }
+    double wz[P1];
+#pragma unroll
+    for (int c = 0; c < P1; ++c) wz[c] = w[2 * P1 + c];
+#pragma unroll
+    for (int b = 0; b < P1; ++b) {
+      double lz = 0.0;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) lz += wz[c] * x[s[b] + c];
+      acc += w[P1 + b] * lz;
+    }
+    acc *= w[a];
   }
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-  if (live && q == 0) e[row] = acc;
+  acc += __shfl_xor(acc, 1, 4);
+  acc += __shfl_xor(acc, 2, 4);
+  if (row < n_rows && a == 0) e[row] = acc;
 }
 
 // y = diag x - ih2 * sum_nb e[nb]           (f == nullptr)
@@ -642,6 +653,54 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NC], int j0, 
   __syncthreads();
 }
 
+// Wave sums of 32 per-lane values by recursive halving: at each of five steps
+// a lane keeps half of its live values and adds the partner lane's copy of
+// that half (lane bit 5 picks column bit 4, ..., lane bit 1 picks column bit
+// 0), then the pair (lane, lane ^ 1) is added. Lanes with bit 0 clear end up
+// holding the wave sum of column transpose_col(lane): 32 shuffles instead of
+// 6 per column.
+__device__ __forceinline__ double transpose_sum32(double (&a)[32], int lane) {
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int half = 16 >> s;
+    const int off = 32 >> s;
+    const bool hi = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < half) {
+        const double lo_v = a[i], hi_v = a[i + half];
+        const double send = hi ? lo_v : hi_v;
+        const double keep = hi ? hi_v : lo_v;
+        a[i] = keep + __shfl_xor(send, off, 64);
+      }
+    }
+  }
+  return a[0] + __shfl_xor(a[0], 1, 64);
+}
+
+__device__ __forceinline__ int transpose_col(int lane) {
+  return (((lane >> 5) & 1) << 4) | (((lane >> 4) & 1) << 3) | (((lane >> 3) & 1) << 2) |
+         (((lane >> 2) & 1) << 1) | ((lane >> 1) & 1);
+}
+
+// block_partials for 32 accumulators per thread (acc is consumed).
+__device__ __forceinline__ void block_partials32(double (&acc)[32], int j0, int nc, double* __restrict__ part) {
+  if (nc <= 2) {
+    block_partials<2>(reinterpret_cast<const double(&)[2]>(acc), j0, nc, part);
+    return;
+  }
+  __shared__ double red[RED_THREADS / 64][32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double t = transpose_sum32(acc, lane);
+  if ((lane & 1) == 0) red[wave][transpose_col(lane)] = t;
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    const int u = threadIdx.x;
+    part[(int64_t)blockIdx.x * PART_LD + j0 + u] = (red[0][u] + red[1][u]) + (red[2][u] + red[3][u]);
+  }
+  __syncthreads();
+}
+
 // part[blk][j] = sum over the block's rows of X_j[r] w[r], j < ncols. With
 // `scale_col` >= 0 that column of X is first scaled in place by *scale.
 __global__ __launch_bounds__(RED_THREADS) void k_dots(int64_t n, double* __restrict__ X, int64_t ldx, int ncols,
@@ -668,7 +727,49 @@ __global__ __launch_bounds__(RED_THREADS) void k_dots(int64_t n, double* __restr
         }
       }
     }
-    block_partials<NC>(acc, j0, nc, part);
+    block_partials32(acc, j0, nc, part);
+  }
+}
+
+// Operator apply fused with the first Gram-Schmidt pass: w = diag z - ih2 sum_nb e[nb]
+// (the stencil of k_stencil, same arithmetic), then part = X^T w as in k_dots.
+__global__ __launch_bounds__(RED_THREADS) void k_stencil_dots(int64_t n, double diag, double ih2,
+                                                              const int32_t* __restrict__ nbr,
+                                                              const double* __restrict__ z,
+                                                              const double* __restrict__ e, double* __restrict__ w,
+                                                              double* __restrict__ X, int64_t ldx, int ncols,
+                                                              double* __restrict__ part, int scale_col,
+                                                              const double* __restrict__ scale) {
+  constexpr int NC = 32;
+  const double sc = scale_col >= 0 ? *scale : 1.0;
+  for (int j0 = 0; j0 < ncols; j0 += NC) {
+    const int nc = min(NC, ncols - j0);
+    double acc[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) acc[u] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
+      double wr;
+      if (j0 == 0) {
+        const double s = (e[nbr[r]] + e[nbr[n + r]]) + (e[nbr[2 * n + r]] + e[nbr[3 * n + r]]) +
+                         (e[nbr[4 * n + r]] + e[nbr[5 * n + r]]);
+        wr = diag * z[r] - ih2 * s;
+        w[r] = wr;
+      } else {
+        wr = w[r];
+      }
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        if (u < nc) {
+          double x = X[(int64_t)(j0 + u) * ldx + r];
+          if (j0 + u == scale_col) {
+            x *= sc;
+            X[(int64_t)(j0 + u) * ldx + r] = x;
+          }
+          acc[u] += x * wr;
+        }
+      }
+    }
+    block_partials32(acc, j0, nc, part);
   }
 }
 
@@ -702,7 +803,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const doub
         acc[0] += wn * wn;
       }
     }
-    block_partials<NC>(acc, 0, mode == 0 ? ncols : 1, part);
+    block_partials32(acc, 0, mode == 0 ? ncols : 1, part);
     return;
   }
   // long bases: two sweeps over V
@@ -724,7 +825,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const doub
         for (int u = 0; u < NC; ++u)
           if (u < nc) acc[u] += V[(int64_t)(j0 + u) * ld + r] * wr;
       }
-      block_partials<NC>(acc, j0, nc, part);
+      block_partials32(acc, j0, nc, part);
     }
   } else {
     double acc[1] = {0.0};
@@ -771,37 +872,50 @@ __global__ __launch_bounds__(RED_THREADS) void k_norm_finish(const double* __res
 
 // Arnoldi column k: H[:,k] = h1 + h2, H[k+1,k] = ||w|| (from partials), the
 // Givens update of the least-squares problem and the residual estimate
-// |g[k+1]|; published to the host.
+// |g[k+1]|; published to the host. The column and the rotations are staged in
+// LDS so that the serial rotation sweep does not wait on device memory.
 __global__ __launch_bounds__(RED_THREADS) void k_arnoldi(const double* __restrict__ part, int nblocks, int k,
                                                          SmallLayout L, double* __restrict__ sm, HostSlot* slot,
                                                          unsigned long long ticket) {
+  __shared__ double hc[MAX_BASIS + 2], csl[MAX_BASIS], snl[MAX_BASIS];
   const double tot = column_total(part, nblocks, 0);
-  if (threadIdx.x != 0) return;
   const int ldh = L.m + 1;
   double* H = sm + L.H() + (int64_t)k * ldh;
   double* cs = sm + L.cs();
   double* sn = sm + L.sn();
   double* g = sm + L.g();
   double* scal = sm + L.scal();
-  const double hk1 = sqrt(tot);
-  for (int i = 0; i <= k; ++i) H[i] = sm[L.h1() + i] + sm[L.h2() + i];
-  H[k + 1] = hk1;
-  for (int i = 0; i < k; ++i) {
-    const double a = H[i], b = H[i + 1];
-    H[i] = cs[i] * a + sn[i] * b;
-    H[i + 1] = -sn[i] * a + cs[i] * b;
+  for (int i = threadIdx.x; i <= k; i += RED_THREADS) hc[i] = sm[L.h1() + i] + sm[L.h2() + i];
+  for (int i = threadIdx.x; i < k; i += RED_THREADS) {
+    csl[i] = cs[i];
+    snl[i] = sn[i];
   }
-  const double den = hypot(H[k], H[k + 1]);
-  cs[k] = H[k] / den;
-  sn[k] = H[k + 1] / den;
-  H[k] = den;
-  H[k + 1] = 0.0;
-  g[k + 1] = -sn[k] * g[k];
-  g[k] = cs[k] * g[k];
-  scal[S_EST] = fabs(g[k + 1]);
-  scal[S_HK1] = hk1;
-  scal[S_INV] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
-  publish(slot, ticket, scal);
+  __syncthreads();
+  const double hk1 = sqrt(tot);
+  if (threadIdx.x == 0) {
+    double a = hc[0];  // rotated H[i] carried down the column
+    for (int i = 0; i < k; ++i) {
+      const double b = hc[i + 1];
+      hc[i] = csl[i] * a + snl[i] * b;
+      a = -snl[i] * a + csl[i] * b;
+    }
+    const double den = hypot(a, hk1);
+    const double c = a / den, sr = hk1 / den;
+    cs[k] = c;
+    sn[k] = sr;
+    hc[k] = den;
+    hc[k + 1] = 0.0;
+    const double gk = g[k];
+    g[k + 1] = -sr * gk;
+    g[k] = c * gk;
+    scal[S_EST] = fabs(-sr * gk);
+    scal[S_HK1] = hk1;
+    scal[S_INV] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= k + 1; i += RED_THREADS) H[i] = hc[i];
+  __syncthreads();
+  if (threadIdx.x == 0) publish(slot, ticket, scal);
 }
 
 // y = H[0:kk, 0:kk]^{-1} g[0:kk] (upper triangular after the rotations)
