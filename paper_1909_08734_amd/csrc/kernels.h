@@ -507,17 +507,37 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
         const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
         acc[bi][bj][i] = (rr < rows && cc < cols) ? a[(int64_t)rr * lda + cc] : (T)0;
       }
+  // K in chunks of LU_NB, staged through LDS; the next chunk's loads are issued
+  // into registers before the current chunk's matrix-core steps, so their
+  // latency overlaps the arithmetic.
+  constexpr int PER = GEMM_TILE * LU_NB / 256;
+  T lreg[PER], ureg[PER];
+  auto fetch = [&](int kc) {
+    const int kb = min(LU_NB, kdim - kc);
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int idx = threadIdx.x + t * 256;
+      const int i = idx / LU_NB, qq = idx - (idx / LU_NB) * LU_NB;
+      lreg[t] = (r0 + i < rows && qq < kb) ? lsrc[(int64_t)(r0 + i) * lld + kc + qq] : (T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int idx = threadIdx.x + t * 256;
+      const int qq = idx / GEMM_TILE, jx = idx - (idx / GEMM_TILE) * GEMM_TILE;
+      ureg[t] = (qq < kb && c0 + jx < cols) ? usrc[(int64_t)(kc + qq) * uld + c0 + jx] : (T)0;
+    }
+  };
+  if (kdim > 0) fetch(0);
   for (int kc = 0; kc < kdim; kc += LU_NB) {
     const int kb = min(LU_NB, kdim - kc);
-    for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
-      const int i = idx / LU_NB, qq = idx - (idx / LU_NB) * LU_NB;
-      Ls[i][qq] = (r0 + i < rows && qq < kb) ? lsrc[(int64_t)(r0 + i) * lld + kc + qq] : (T)0;
-    }
-    for (int idx = threadIdx.x; idx < GEMM_TILE * LU_NB; idx += 256) {
-      const int qq = idx / GEMM_TILE, jx = idx - (idx / GEMM_TILE) * GEMM_TILE;
-      Us[qq][jx] = (qq < kb && c0 + jx < cols) ? usrc[(int64_t)(kc + qq) * uld + c0 + jx] : (T)0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int idx = threadIdx.x + t * 256;
+      Ls[idx / LU_NB][idx - (idx / LU_NB) * LU_NB] = lreg[t];
+      Us[idx / GEMM_TILE][idx - (idx / GEMM_TILE) * GEMM_TILE] = ureg[t];
     }
     __syncthreads();
+    if (kc + LU_NB < kdim) fetch(kc + LU_NB);
     const int ksteps = (kb + 3) >> 2;
     for (int kk = 0; kk < ksteps; ++kk) {
       T av[2], bv[2];
