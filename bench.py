@@ -148,6 +148,37 @@ def pmc_traffic(kind, source_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
+def operator_roofline(ctx, torch, P, na, ng, reps=50, degree=3):
+    """Operator apply (extension + stencil) timed by HIP events: warm (repeated
+    applies, band data resident in the 256 MB last-level cache) and cold (a
+    1 GiB copy between applies evicts it, as the preconditioner's stream does
+    inside a solve). Algorithmic bytes: N_A (x 8 + y 8 + neighbour indices 24)
+    + N_T (weights 24(p+1) + z-line starts 4(p+1)^2)."""
+    nt = na + ng
+    p1 = degree + 1
+    nbytes = na * (8 + 8 + 24) + nt * (8 * 3 * p1 + 4 * p1 * p1)
+    x = torch.randn(na, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    big = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    big2 = torch.empty_like(big)
+    out = {"bytes_per_apply": nbytes}
+    for mode in ("warm", "cold"):
+        ctx.apply_operator(x, y)
+        ctx.set_timing(True)
+        for _ in range(reps):
+            if mode == "cold":
+                big2.copy_(big)
+            ctx.apply_operator(x, y)
+        ext_ms, ext_n = ctx.kernel_time(P.TIMER_EXTEND)
+        st_ms, st_n = ctx.kernel_time(P.TIMER_STENCIL)
+        ctx.set_timing(False)
+        t = ext_ms / ext_n + st_ms / st_n
+        out[mode] = {"extend_us": 1e3 * ext_ms / ext_n, "stencil_us": 1e3 * st_ms / st_n,
+                     "GBs": nbytes / (t * 1e-3) / 1e9, "frac_of_8TBs": nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del big, big2
+    return out
+
+
 def run_gpu(args, wl):
     import torch
     import paper_1909_08734_amd as P
@@ -165,6 +196,8 @@ def run_gpu(args, wl):
     f_dev = torch.from_numpy(F).cuda()
     u_dev = torch.zeros_like(f_dev)
     torch.cuda.synchronize()
+    op = operator_roofline(ctx, torch, P, na, ng)
+    log(f"operator apply: {json.dumps(op)}")
     kind = P.ORAS if wl["kind"] == "ORAS" else P.RAS
     method = P.PART_OCTANT if wl["method"] == "octant" else P.PART_RCB
     weights = wl["weights"]() if wl["weights"] else None
@@ -252,7 +285,7 @@ def run_gpu(args, wl):
                 rr = np.linalg.norm(F[nrhs - 1] - A @ u) / np.linalg.norm(F[nrhs - 1])
                 log(f"{a_name} {prec_name}: oracle residual of the last solve {rr:.3e}")
     ctx.close()
-    return res, na
+    return res, na, op
 
 
 SERVE_HS = (0.05, 0.025)
@@ -382,7 +415,7 @@ def main():
         sys.exit(2)
     wl = workloads()[args.workload]
     default = args.workload == DEFAULT_WORKLOAD
-    res, na = run_gpu(args, wl)
+    res, na, op = run_gpu(args, wl)
     src = kernel_source_hash()
     head = wl["alphas"][0][0]
     r64 = res[head]["fp64"]
@@ -413,6 +446,7 @@ def main():
         "fp64_factors": r64,
         "fp32_factors": dict(r32, speedup_vs_fp64=r32["solves_per_s"] / r64["solves_per_s"]),
         "alpha_sweep": sweep,
+        "operator_apply": op,
         "roofline": {
             "kernel": "k_precond<double> (restricted local solves, eq. algRAS)",
             "bound": "hbm",

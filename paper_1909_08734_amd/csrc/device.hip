@@ -143,10 +143,10 @@ static void launch_extend(cpm_ctx* ctx, const double* x) {
   Dev& d = ctx->dev;
   const int64_t nt = b.total();
   if (b.p == 3)
-    launch(ctx, TIMER_EXTEND, k_extend<3>, dim3(nblk(nt * 4, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
+    launch(ctx, TIMER_EXTEND, k_extend<3>, dim3(nblk(nt * 2, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
            (const double*)d.wts, x, d.e);
   else
-    launch(ctx, TIMER_EXTEND, k_extend<2>, dim3(nblk(nt * 4, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
+    launch(ctx, TIMER_EXTEND, k_extend<2>, dim3(nblk(nt * 2, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
            (const double*)d.wts, x, d.e);
 }
 

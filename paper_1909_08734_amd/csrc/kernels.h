@@ -32,48 +32,57 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
 // ---------------------------------------------------------------------------
 // Operator apply (Section 2.1): e = E x over all band rows, then
 // y = (c + 6/h^2) x - (1/h^2) sum_{6 neighbours} e.
-// Extension: 4 lanes per row; lane a takes the stencil plane x = base_x + a,
-// interpolates each of its p+1 z-lines (p+1 consecutive band entries) with
-// w_z, combines them with w_y, scales by w_x[a]; the 4 lanes then reduce.
-// (Fewer, longer lanes per row keep more independent gathers in flight per
-// lane than one lane per z-line.)
+// Extension: 2 lanes per row; lane h takes the stencil planes x = base_x + a
+// for a = 2h, 2h + 1 (a <= p), interpolates each of their p+1 z-lines (p+1
+// consecutive band entries) with w_z, combines them with w_y and w_x[a]; the
+// two lanes then add. (Few lanes per row keep many independent gathers in
+// flight per lane and need a single shuffle.)
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
                                                 const double* __restrict__ wts,
                                                 const double* __restrict__ x, double* __restrict__ e) {
   constexpr int P1 = P + 1, NL = P1 * P1, NW = 3 * P1;
-  static_assert(P1 <= 4, "at most 4 lanes per row");
-  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  const int a = threadIdx.x & 3;
+  static_assert(P1 <= 4, "two planes per lane");
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
+  const int hl = threadIdx.x & 1;
   double acc = 0.0;
-  if (row < n_rows && a < P1) {
+  if (row < n_rows) {
     const double* w = wts + row * NW;
-    int32_t s[P1];
-    if constexpr (P1 == 4) {
-      typedef int32_t i4v __attribute__((ext_vector_type(4)));
-      const i4v v = *reinterpret_cast<const i4v*>(lines + row * NL + a * P1);
+    double wy[P1], wz[P1];
 #pragma unroll
-      for (int b = 0; b < P1; ++b) s[b] = v[b];
-    } else {
-#pragma unroll
-      for (int b = 0; b < P1; ++b) s[b] = lines[row * NL + a * P1 + b];
+    for (int c = 0; c < P1; ++c) {
+      wy[c] = w[P1 + c];
+      wz[c] = w[2 * P1 + c];
     }
-    double wz[P1];
 #pragma unroll
-    for (int c = 0; c < P1; ++c) wz[c] = w[2 * P1 + c];
+    for (int q = 0; q < 2; ++q) {
+      const int a = 2 * hl + q;
+      if (a < P1) {
+        int32_t s[P1];
+        if constexpr (P1 == 4) {
+          typedef int32_t i4v __attribute__((ext_vector_type(4)));
+          const i4v v = *reinterpret_cast<const i4v*>(lines + row * NL + a * P1);
 #pragma unroll
-    for (int b = 0; b < P1; ++b) {
-      double lz = 0.0;
+          for (int b = 0; b < P1; ++b) s[b] = v[b];
+        } else {
 #pragma unroll
-      for (int c = 0; c < P1; ++c) lz += wz[c] * x[s[b] + c];
-      acc += w[P1 + b] * lz;
+          for (int b = 0; b < P1; ++b) s[b] = lines[row * NL + a * P1 + b];
+        }
+        double pa = 0.0;
+#pragma unroll
+        for (int b = 0; b < P1; ++b) {
+          double lz = 0.0;
+#pragma unroll
+          for (int c = 0; c < P1; ++c) lz += wz[c] * x[s[b] + c];
+          pa += wy[b] * lz;
+        }
+        acc += w[a] * pa;
+      }
     }
-    acc *= w[a];
   }
-  acc += __shfl_xor(acc, 1, 4);
-  acc += __shfl_xor(acc, 2, 4);
-  if (row < n_rows && a == 0) e[row] = acc;
+  acc += __shfl_xor(acc, 1, 2);
+  if (row < n_rows && hl == 0) e[row] = acc;
 }
 
 // y = diag x - ih2 * sum_nb e[nb]           (f == nullptr)
