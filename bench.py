@@ -93,7 +93,7 @@ def kernel_source_hash():
         k = fh.read()
     with open(os.path.join(csrc, "device.hip")) as fh:
         d = fh.read()
-    kern = k[k.index("constexpr int PRECOND_THREADS"):k.index("// Local operator assembly")]
+    kern = k[k.index("constexpr int PRECOND_THREADS"):k.index("// Chunked form, for subdomains")]
     plan = d[d.index("std::vector<int> apportion_blocks("):d.index("template <typename T>\nint run_factor(")]
     h = hashlib.sha256()
     h.update(kern.encode())

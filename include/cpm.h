@@ -131,6 +131,28 @@ int cpm_partition(cpm_ctx* ctx, int method, int n_sub, const double* weights, in
                   int kind, double alpha, double alpha_cross);
 
 /*
+ * Device memory for the factorisation's work arrays (the bordered local
+ * matrices and panel scratch): subdomains are factored in consecutive groups
+ * whose work arrays fit in `bytes` together (one subdomain larger than that is
+ * a group of its own); only W_j stays resident. The result does not depend on
+ * the grouping. 0 restores the default, 64 GiB. Takes effect at the next
+ * cpm_factor; also used by cpm_footprint_estimate.
+ */
+int cpm_set_factor_workspace(cpm_ctx* ctx, size_t bytes);
+/* Number of subdomain groups the last cpm_factor used (0 before any). */
+int cpm_factor_groups(const cpm_ctx* ctx);
+/*
+ * Preconditioner apply layout. By default v|Sigma_j is staged whole in LDS
+ * (160 KB per CU: |Sigma_j| <= 20480); larger subdomains use the chunked form
+ * (v staged `columns` at a time, partial row sums kept in LDS). columns > 0
+ * forces the chunked form with that width (a multiple of 8, at most 16384);
+ * 0 restores the default. Takes effect at the next cpm_factor. EINVAL for
+ * other values. cpm_precond_chunk reports the width in use (0: unchunked).
+ */
+int cpm_set_precond_chunk(cpm_ctx* ctx, int columns);
+int cpm_precond_chunk(const cpm_ctx* ctx);
+
+/*
  * Local operators A_j (eq. localOP) assembled on the device and factored by
  * batched dense LU with partial pivoting (Section 5) in `prec`; the factors
  * are reduced to the restricted local solution operators

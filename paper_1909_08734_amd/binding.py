@@ -57,6 +57,10 @@ _SIGS = {
     "cpm_partition": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int,
                                 C.c_double, C.c_double]),
     "cpm_factor": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_set_factor_workspace": (C.c_int, [C.c_void_p, C.c_size_t]),
+    "cpm_factor_groups": (C.c_int, [C.c_void_p]),
+    "cpm_set_precond_chunk": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_precond_chunk": (C.c_int, [C.c_void_p]),
     "cpm_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int,
                             C.POINTER(SolveInfo)]),
     "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
@@ -212,6 +216,20 @@ class Context:
 
     def factor(self, prec=FP64):
         self._check(self._L.cpm_factor(self._h, int(prec)), "factor")
+
+    def set_factor_workspace(self, nbytes=0):
+        """Bound the factorisation's work arrays per group of subdomains (0: default)."""
+        self._check(self._L.cpm_set_factor_workspace(self._h, int(nbytes)), "set_factor_workspace")
+
+    def factor_groups(self):
+        return int(self._L.cpm_factor_groups(self._h))
+
+    def set_precond_chunk(self, columns=0):
+        """Force the chunked preconditioner apply with `columns` per pass (0: automatic)."""
+        self._check(self._L.cpm_set_precond_chunk(self._h, int(columns)), "set_precond_chunk")
+
+    def precond_chunk(self):
+        return int(self._L.cpm_precond_chunk(self._h))
 
     def solve(self, f, tol=1e-8, max_iter=1000, restart=30):
         """Host arrays: f (N_A,) or (nrhs, N_A). Returns (u, [info dicts])."""

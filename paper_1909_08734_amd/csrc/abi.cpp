@@ -351,6 +351,24 @@ int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* re
   return CPM_OK;
 }
 
+int cpm_set_factor_workspace(cpm_ctx* ctx, size_t bytes) {
+  if (!ctx) return CPM_EINVAL;
+  ctx->dev.ws_limit = bytes ? bytes : (size_t(64) << 30);
+  return CPM_OK;
+}
+
+int cpm_factor_groups(const cpm_ctx* ctx) { return ctx ? ctx->dev.n_groups : 0; }
+
+int cpm_set_precond_chunk(cpm_ctx* ctx, int columns) {
+  if (!ctx) return CPM_EINVAL;
+  if (columns < 0 || columns > 16384 || columns % 8 != 0)
+    return fail(ctx, CPM_EINVAL, "set_precond_chunk: columns must be 0 or a multiple of 8 up to 16384");
+  ctx->dev.chunk_req = columns;
+  return CPM_OK;
+}
+
+int cpm_precond_chunk(const cpm_ctx* ctx) { return ctx ? ctx->dev.chunk : 0; }
+
 int cpm_set_timing(cpm_ctx* ctx, int on) {
   if (!ctx) return CPM_EINVAL;
   if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "set_timing: host-only context");

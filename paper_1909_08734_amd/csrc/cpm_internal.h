@@ -96,6 +96,10 @@ struct Dev {
   int prec = -1;
   int n_blocks = 0;
   int max_m = 0;
+  int n_groups = 0;             // subdomain groups of the last factorisation
+  int chunk = 0;                // 0: v|Sigma_j staged whole; else columns per pass (chunked apply)
+  int chunk_req = 0;            // requested chunk (0: only when v|Sigma_j exceeds LDS)
+  size_t ws_limit = size_t(64) << 30;  // factor workspace per group, bytes
   size_t w_bytes = 0;
   // Krylov workspace
   int restart = 0;

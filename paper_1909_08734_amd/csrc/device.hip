@@ -165,6 +165,18 @@ static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const doub
 // z = scale * M^{-1} v (scale: device scalar or nullptr for 1)
 static void launch_precond(cpm_ctx* ctx, const double* v, double* z, const double* scale = nullptr) {
   Dev& d = ctx->dev;
+  if (d.chunk > 0) {
+    const size_t lds = (size_t)(d.chunk + PRECOND_RPB_MAX) * sizeof(double);
+    if (d.prec == CPM_FP64)
+      launch(ctx, TIMER_PRECOND, k_precond_chunked<double>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
+             (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
+             (const int32_t*)d.tilde_idx, (const double*)d.W, v, scale, z, d.chunk);
+    else
+      launch(ctx, TIMER_PRECOND, k_precond_chunked<float>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
+             (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
+             (const int32_t*)d.tilde_idx, (const float*)d.W, v, scale, z, d.chunk);
+    return;
+  }
   const size_t lds = (size_t)d.max_m * sizeof(double);
   if (d.prec == CPM_FP64)
     launch(ctx, TIMER_PRECOND, k_precond<double>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
@@ -229,10 +241,13 @@ std::vector<int> apportion_blocks(const Decomp& D, int slots) {
   return want;
 }
 
-void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots) {
+void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) {
   const Decomp& D = ctx->dec;
   const bool oras = D.kind == CPM_ORAS;
-  const std::vector<int> want_blocks = apportion_blocks(D, block_slots);
+  std::vector<int> want_blocks = apportion_blocks(D, block_slots);
+  if (rpb_max > 0)  // chunked apply: at most rpb_max rows per block
+    for (int j = 0; j < D.n_sub; ++j)
+      want_blocks[j] = std::max(want_blocks[j], (int)((D.subs[j].tilde.size() + rpb_max - 1) / rpb_max));
   int32_t u_off = 0, t_off = 0, blk = 0;
   int64_t a_off = 0, w_off = 0;
   for (int j = 0; j < D.n_sub; ++j) {
@@ -292,6 +307,28 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots) {
   P.n_blocks = blk;
 }
 
+// Factor workspace of one subdomain (bordered matrix + column-major panel scratch), elements.
+inline int64_t factor_ws_elems(const SubDesc& d) { return (int64_t)d.rows * d.lda + (int64_t)LU_NB * d.rows; }
+
+// Consecutive groups of subdomains whose factor workspaces fit in `limit` bytes
+// together (a subdomain larger than the limit forms a group of its own).
+std::vector<std::pair<int, int>> factor_groups(const std::vector<SubDesc>& desc, size_t esz, size_t limit) {
+  std::vector<std::pair<int, int>> g;
+  int g0 = 0;
+  size_t acc = 0;
+  for (int j = 0; j < (int)desc.size(); ++j) {
+    const size_t wj = (size_t)factor_ws_elems(desc[j]) * esz;
+    if (j > g0 && acc + wj > limit) {
+      g.push_back({g0, j});
+      g0 = j;
+      acc = 0;
+    }
+    acc += wj;
+  }
+  if (!desc.empty()) g.push_back({g0, (int)desc.size()});
+  return g;
+}
+
 template <typename T>
 int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   const Band& b = ctx->band;
@@ -301,7 +338,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   const double ih2 = 1.0 / (b.h * b.h);
   const double diag = ctx->c + 6.0 * ih2;
 
-  SubDesc* ddesc = nullptr;
+  SubDesc *ddesc = nullptr, *gdesc = nullptr;
   int32_t *dU = nullptr, *dsrt = nullptr, *dpos = nullptr, *dbx = nullptr, *dtpos = nullptr, *dtidx = nullptr,
           *dblk = nullptr, *dipiv = nullptr, *dinfo = nullptr, *dpre = nullptr;
   double *dbs = nullptr, *dba = nullptr;
@@ -311,10 +348,14 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   T* dW = nullptr;
   T* dscr = nullptr;
   int rc = CPM_OK;
-  auto cleanup = [&]() {
+  auto free_group = [&]() {
     hipStreamSynchronize(ctx->stream);
+    dfree(gdesc); dfree(dA); dfree(dscr); dfree(dscr_off); dfree(jobs_buf); dfree(dpre);
+  };
+  auto cleanup = [&]() {
+    free_group();
     dfree(dsrt); dfree(dpos); dfree(dbx); dfree(dtpos); dfree(dipiv); dfree(dinfo);
-    dfree(dpre); dfree(dbs); dfree(dba); dfree(dA); dfree(dscr); dfree(dscr_off); dfree(jobs_buf);
+    dfree(dbs); dfree(dba);
   };
   auto bail = [&](int code) {
     cleanup();
@@ -348,126 +389,157 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   FHIP(hipMalloc((void**)&dipiv, P.u_total * sizeof(int32_t)));
   FHIP(hipMalloc((void**)&dinfo, ns * sizeof(int32_t)));
   FHIP(hipMemsetAsync(dinfo, 0, ns * sizeof(int32_t), ctx->stream));
-  FHIP(hipMalloc((void**)&dA, P.a_elems * sizeof(T)));
-  FHIP(hipMemsetAsync(dA, 0, P.a_elems * sizeof(T), ctx->stream));
-
-  // Assembly of the augmented local matrices.
-  {
-    dim3 grid(nblk(P.max_rows, 256), ns);
-    if (b.p == 3)
-      k_assemble<T, 3><<<grid, 256, 0, ctx->stream>>>(ddesc, b.n_act, dv.lines, dv.wts, dv.nbr, dU, dsrt, dpos,
-                                                      dbx, dbs, dba, dtpos, diag, ih2, D.kind == CPM_ORAS, dA);
-    else
-      k_assemble<T, 2><<<grid, 256, 0, ctx->stream>>>(ddesc, b.n_act, dv.lines, dv.wts, dv.nbr, dU, dsrt, dpos,
-                                                      dbx, dbs, dba, dtpos, diag, ih2, D.kind == CPM_ORAS, dA);
-    FHIP(hipGetLastError());
-  }
-
-  // Two-level blocked LU. Outer blocks of LU_KMAX columns; inside one, each
-  // LU_NB-wide panel is first brought up to date left-looking (row
-  // interchanges + unit-lower solve + MFMA update from the block's earlier
-  // panels), then factored; its interchanges are applied to the block's
-  // earlier L columns. After the outer block, the trailing matrix gets the
-  // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
-  // and one MFMA update with K = LU_KMAX.
-  enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3 };
-  struct Launch {
-    int kind, k, job_off, n_jobs, units;
-  };
-  std::vector<LuJob> jobs;
-  std::vector<int32_t> prefix;  // per launch: n_jobs entries (job_off-aligned)
-  std::vector<Launch> lplan;
-  auto add = [&](int kind, int k, const std::vector<std::pair<LuJob, int>>& list) {
-    Launch L{kind, k, (int)jobs.size(), 0, 0};
-    for (const auto& e : list) {
-      if (e.second <= 0) continue;
-      jobs.push_back(e.first);
-      prefix.push_back(L.units);
-      L.units += e.second;
-      L.n_jobs++;
-    }
-    if (L.n_jobs > 0) lplan.push_back(L);
-  };
-  auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
-  for (int K0 = 0; K0 < P.max_n; K0 += LU_KMAX) {
-    for (int p = 0; p < LU_KMAX / LU_NB; ++p) {
-      const int k = K0 + p * LU_NB;
-      if (k >= P.max_n) break;
-      if (p > 0) {
-        std::vector<std::pair<LuJob, int>> ts, gm;
-        for (int j = 0; j < ns; ++j) {
-          const SubDesc& d = P.desc[j];
-          if (k >= d.n) continue;
-          const int kb = std::min(LU_NB, d.n - k);
-          const LuJob jb{j, K0, k - K0, k, k, k + kb};
-          ts.push_back({jb, 1});
-          gm.push_back({jb, cdiv(d.rows - k, GEMM_TILE)});
-        }
-        add(L_SWAP_TRSM, k, ts);
-        add(L_GEMM, k, gm);
-      }
-      lplan.push_back(Launch{L_PANEL, k, 0, 0, ns});
-      if (p > 0) {
-        std::vector<std::pair<LuJob, int>> sw;
-        for (int j = 0; j < ns; ++j) {
-          const SubDesc& d = P.desc[j];
-          if (k >= d.n) continue;
-          sw.push_back({LuJob{j, k, std::min(LU_NB, d.n - k), 0, K0, k}, cdiv(k - K0, TRSM_COLS)});
-        }
-        add(L_SWAP, k, sw);
-      }
-    }
-    std::vector<std::pair<LuJob, int>> ts, gm;
-    for (int j = 0; j < ns; ++j) {
-      const SubDesc& d = P.desc[j];
-      if (K0 >= d.n) continue;
-      const int K1 = std::min(K0 + LU_KMAX, d.n);
-      const LuJob jb{j, K0, K1 - K0, K1, K1, d.cols};
-      ts.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
-      gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE) * cdiv(d.cols - K1, GEMM_TILE)});
-    }
-    add(L_SWAP_TRSM, K0, ts);
-    add(L_GEMM, K0, gm);
-  }
-  LuJob* djobs = nullptr;
-  FCHK(upload(ctx, &djobs, jobs));
-  FCHK(upload(ctx, &dpre, prefix));
-  jobs_buf = djobs;
-  // column-major panel scratch, LU_NB x rows_j per subdomain
-  std::vector<int64_t> scr_off(ns);
-  int64_t scr_total = 0;
-  for (int j = 0; j < ns; ++j) {
-    scr_off[j] = scr_total;
-    scr_total += (int64_t)LU_NB * P.desc[j].rows;
-  }
-  FCHK(upload(ctx, &dscr_off, scr_off));
-  FHIP(hipMalloc((void**)&dscr, scr_total * sizeof(T)));
-  for (const Launch& L : lplan) {
-    const LuJob* jb = djobs + L.job_off;
-    const int32_t* pre = dpre + L.job_off;
-    switch (L.kind) {
-      case L_PANEL:
-        k_lu_panel<T><<<ns, PANEL_THREADS, 0, ctx->stream>>>(ddesc, dA, L.k, dipiv, dinfo, dscr, dscr_off);
-        break;
-      case L_SWAP_TRSM:
-      case L_SWAP:
-        k_lu_swap_trsm<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(ddesc, dA, dipiv, jb, pre, L.n_jobs,
-                                                                   L.kind == L_SWAP_TRSM ? 1 : 0);
-        break;
-      case L_GEMM:
-        launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(L.units), dim3(256), 0, (const SubDesc*)ddesc, dA, jb, pre,
-               L.n_jobs);
-        break;
-    }
-  }
-  FHIP(hipGetLastError());
   FHIP(hipMalloc((void**)&dW, P.w_elems * sizeof(T)));
-  {
-    int tmax = 0;
-    for (const SubDesc& d : P.desc) tmax = std::max(tmax, (int)d.t);
-    dim3 grid(tmax, ns);
-    k_extract_w<T><<<grid, 256, 0, ctx->stream>>>(ddesc, dA, dW);
+
+  // Subdomains are factored group by group so that the bordered matrices of a
+  // group fit in the workspace limit; every subdomain's arithmetic is the same
+  // whatever group it is in. Within a group the arrays are addressed through
+  // rebased descriptors (a_off, u_off, t_off relative to the group; w_off
+  // global, into the resident W arena).
+  const std::vector<std::pair<int, int>> groups = factor_groups(P.desc, sizeof(T), dv.ws_limit);
+  for (const auto& gr : groups) {
+    const int g0 = gr.first, gn = gr.second - gr.first;
+    std::vector<SubDesc> gd(P.desc.begin() + g0, P.desc.begin() + gr.second);
+    const int64_t a0 = gd[0].a_off;
+    const int32_t u0 = gd[0].u_off, t0 = gd[0].t_off;
+    int64_t a_elems = 0;
+    int max_n = 0, max_rows = 0, tmax = 0;
+    for (SubDesc& d : gd) {
+      d.a_off -= a0;
+      d.u_off -= u0;
+      d.t_off -= t0;
+      a_elems = std::max(a_elems, d.a_off + (int64_t)d.rows * d.lda);
+      max_n = std::max(max_n, (int)d.n);
+      max_rows = std::max(max_rows, (int)d.rows);
+      tmax = std::max(tmax, (int)d.t);
+    }
+    int32_t* gU = dU + u0;
+    int32_t* gsrt = dsrt + u0;
+    int32_t* gpos = dpos + u0;
+    int32_t* gbx = dbx + u0;
+    double* gbs = dbs + u0;
+    double* gba = dba + u0;
+    int32_t* gtpos = dtpos + t0;
+    int32_t* gipiv = dipiv + u0;
+    int32_t* ginfo = dinfo + g0;
+    FCHK(upload(ctx, &gdesc, gd));
+    FHIP(hipMalloc((void**)&dA, a_elems * sizeof(T)));
+    FHIP(hipMemsetAsync(dA, 0, a_elems * sizeof(T), ctx->stream));
+
+    // Assembly of the augmented local matrices.
+    {
+      dim3 grid(nblk(max_rows, 256), gn);
+      if (b.p == 3)
+        k_assemble<T, 3><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
+                                                        gbx, gbs, gba, gtpos, diag, ih2, D.kind == CPM_ORAS, dA);
+      else
+        k_assemble<T, 2><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
+                                                        gbx, gbs, gba, gtpos, diag, ih2, D.kind == CPM_ORAS, dA);
+      FHIP(hipGetLastError());
+    }
+
+    // Two-level blocked LU. Outer blocks of LU_KMAX columns; inside one, each
+    // LU_NB-wide panel is first brought up to date left-looking (row
+    // interchanges + unit-lower solve + MFMA update from the block's earlier
+    // panels), then factored; its interchanges are applied to the block's
+    // earlier L columns. After the outer block, the trailing matrix gets the
+    // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
+    // and one MFMA update with K = LU_KMAX.
+    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3 };
+    struct Launch {
+      int kind, k, job_off, n_jobs, units;
+    };
+    std::vector<LuJob> jobs;
+    std::vector<int32_t> prefix;  // per launch: n_jobs entries (job_off-aligned)
+    std::vector<Launch> lplan;
+    auto add = [&](int kind, int k, const std::vector<std::pair<LuJob, int>>& list) {
+      Launch L{kind, k, (int)jobs.size(), 0, 0};
+      for (const auto& e : list) {
+        if (e.second <= 0) continue;
+        jobs.push_back(e.first);
+        prefix.push_back(L.units);
+        L.units += e.second;
+        L.n_jobs++;
+      }
+      if (L.n_jobs > 0) lplan.push_back(L);
+    };
+    auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
+    for (int K0 = 0; K0 < max_n; K0 += LU_KMAX) {
+      for (int p = 0; p < LU_KMAX / LU_NB; ++p) {
+        const int k = K0 + p * LU_NB;
+        if (k >= max_n) break;
+        if (p > 0) {
+          std::vector<std::pair<LuJob, int>> ts, gm;
+          for (int j = 0; j < gn; ++j) {
+            const SubDesc& d = gd[j];
+            if (k >= d.n) continue;
+            const int kb = std::min(LU_NB, d.n - k);
+            const LuJob jb{j, K0, k - K0, k, k, k + kb};
+            ts.push_back({jb, 1});
+            gm.push_back({jb, cdiv(d.rows - k, GEMM_TILE)});
+          }
+          add(L_SWAP_TRSM, k, ts);
+          add(L_GEMM, k, gm);
+        }
+        lplan.push_back(Launch{L_PANEL, k, 0, 0, gn});
+        if (p > 0) {
+          std::vector<std::pair<LuJob, int>> sw;
+          for (int j = 0; j < gn; ++j) {
+            const SubDesc& d = gd[j];
+            if (k >= d.n) continue;
+            sw.push_back({LuJob{j, k, std::min(LU_NB, d.n - k), 0, K0, k}, cdiv(k - K0, TRSM_COLS)});
+          }
+          add(L_SWAP, k, sw);
+        }
+      }
+      std::vector<std::pair<LuJob, int>> ts, gm;
+      for (int j = 0; j < gn; ++j) {
+        const SubDesc& d = gd[j];
+        if (K0 >= d.n) continue;
+        const int K1 = std::min(K0 + LU_KMAX, d.n);
+        const LuJob jb{j, K0, K1 - K0, K1, K1, d.cols};
+        ts.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
+        gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE) * cdiv(d.cols - K1, GEMM_TILE)});
+      }
+      add(L_SWAP_TRSM, K0, ts);
+      add(L_GEMM, K0, gm);
+    }
+    FCHK(upload(ctx, &jobs_buf, jobs));
+    FCHK(upload(ctx, &dpre, prefix));
+    // column-major panel scratch, LU_NB x rows_j per subdomain
+    std::vector<int64_t> scr_off(gn);
+    int64_t scr_total = 0;
+    for (int j = 0; j < gn; ++j) {
+      scr_off[j] = scr_total;
+      scr_total += (int64_t)LU_NB * gd[j].rows;
+    }
+    FCHK(upload(ctx, &dscr_off, scr_off));
+    FHIP(hipMalloc((void**)&dscr, scr_total * sizeof(T)));
+    for (const Launch& L : lplan) {
+      const LuJob* jb = jobs_buf + L.job_off;
+      const int32_t* pre = dpre + L.job_off;
+      switch (L.kind) {
+        case L_PANEL:
+          k_lu_panel<T><<<gn, PANEL_THREADS, 0, ctx->stream>>>(gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off);
+          break;
+        case L_SWAP_TRSM:
+        case L_SWAP:
+          k_lu_swap_trsm<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, gipiv, jb, pre, L.n_jobs,
+                                                                     L.kind == L_SWAP_TRSM ? 1 : 0);
+          break;
+        case L_GEMM:
+          launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(L.units), dim3(256), 0, (const SubDesc*)gdesc, dA, jb, pre,
+                 L.n_jobs);
+          break;
+      }
+    }
     FHIP(hipGetLastError());
+    {
+      dim3 grid(tmax, gn);
+      k_extract_w<T><<<grid, 256, 0, ctx->stream>>>(gdesc, dA, dW);
+      FHIP(hipGetLastError());
+    }
+    free_group();
   }
   std::vector<int32_t> info(ns);
   FHIP(hipMemcpyAsync(info.data(), dinfo, ns * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -486,6 +558,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   dv.prec = prec;
   dv.n_blocks = P.n_blocks;
   dv.max_m = P.max_m;
+  dv.n_groups = (int)groups.size();
   dv.w_bytes = P.w_elems * sizeof(T) + P.desc.size() * sizeof(SubDesc) + (P.U.size() + P.tilde_idx.size() +
                P.blk_sub.size()) * sizeof(int32_t);
   return rc;
@@ -504,23 +577,38 @@ int dev_factor(cpm_ctx* ctx, int prec) {
   HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
   int64_t max_m = 0;
   for (const Sub& s : ctx->dec.subs) max_m = std::max<int64_t>(max_m, round_up(s.sigma.size(), 8));
-  const size_t lds = (size_t)max_m * sizeof(double);
-  if (lds > 160 * 1024) {
-    ctx->err = "factor: a subdomain is too large for the preconditioner apply (|Sigma_j| > 20480)";
-    return CPM_EINVAL;
-  }
-  if (lds > 64 * 1024) {
-    hipFuncSetAttribute((const void*)k_precond<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute((const void*)k_precond<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // v|Sigma_j is staged whole in LDS when it fits, else in chunks (or when a
+  // chunk width is requested).
+  Dev& dv = ctx->dev;
+  dv.chunk = 0;
+  size_t lds = (size_t)max_m * sizeof(double);
+  if (dv.chunk_req > 0 || lds > 160 * 1024) {
+    dv.chunk = dv.chunk_req > 0 ? dv.chunk_req : PRECOND_CHUNK;
+    lds = (size_t)(dv.chunk + PRECOND_RPB_MAX) * sizeof(double);
   }
   int per_cu = 0;
-  if (prec == CPM_FP64)
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<double>, PRECOND_THREADS, lds));
-  else
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<float>, PRECOND_THREADS, lds));
+  if (dv.chunk > 0) {
+    if (lds > 64 * 1024) {
+      hipFuncSetAttribute((const void*)k_precond_chunked<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipFuncSetAttribute((const void*)k_precond_chunked<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    if (prec == CPM_FP64)
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond_chunked<double>, PRECOND_THREADS, lds));
+    else
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond_chunked<float>, PRECOND_THREADS, lds));
+  } else {
+    if (lds > 64 * 1024) {
+      hipFuncSetAttribute((const void*)k_precond<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipFuncSetAttribute((const void*)k_precond<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    if (prec == CPM_FP64)
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<double>, PRECOND_THREADS, lds));
+    else
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<float>, PRECOND_THREADS, lds));
+  }
   per_cu = std::max(1, per_cu);
   FactorPlan P;
-  make_plan(ctx, P, n_cu * per_cu);
+  make_plan(ctx, P, n_cu * per_cu, dv.chunk > 0 ? PRECOND_RPB_MAX : 0);
   return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec) : run_factor<float>(ctx, P, prec);
 }
 
@@ -805,20 +893,29 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
   const bool oras = D.kind == CPM_ORAS;
   const size_t esz = prec == CPM_FP64 ? 8 : 4;
   const size_t op = b.lines.size() * 4 + b.wts.size() * 8 + (size_t)b.n_act * 6 * 4 + (size_t)b.total() * 8;
-  int64_t a_elems = 0, w_elems = 0, scr = 0, u_total = 0, t_total = 0;
-  for (const Sub& s : D.subs) {
-    const int64_t m = (int64_t)s.sigma.size();
-    const int64_t n = m + (oras ? (int64_t)s.bnd.size() : 0);
-    const int64_t t = (int64_t)s.tilde.size();
-    a_elems += (n + t) * round_up(n + m, 16);
-    w_elems += t * round_up(m, 8);
-    scr += (int64_t)LU_NB * (n + t);
-    u_total += n;
-    t_total += t;
+  int64_t w_elems = 0, u_total = 0, t_total = 0;
+  std::vector<SubDesc> desc(D.n_sub);
+  for (int j = 0; j < D.n_sub; ++j) {
+    const Sub& s = D.subs[j];
+    SubDesc& d = desc[j];
+    d.m = (int32_t)s.sigma.size();
+    d.n = d.m + (oras ? (int32_t)s.bnd.size() : 0);
+    d.t = (int32_t)s.tilde.size();
+    d.rows = d.n + d.t;
+    d.lda = (int32_t)round_up(d.n + d.m, 16);
+    w_elems += (int64_t)d.t * round_up(d.m, 8);
+    u_total += d.n;
+    t_total += d.t;
+  }
+  int64_t ws = 0;  // largest group workspace
+  for (const auto& g : factor_groups(desc, esz, ctx->dev.ws_limit)) {
+    int64_t e = 0;
+    for (int j = g.first; j < g.second; ++j) e += factor_ws_elems(desc[j]);
+    ws = std::max(ws, e);
   }
   const size_t lists = (size_t)D.n_sub * sizeof(SubDesc) + (size_t)(u_total + 2 * t_total) * 4;
   const size_t res = op + (size_t)w_elems * esz + lists + (restart > 0 ? krylov_bytes(b.n_act, restart) : 0);
-  const size_t work = (size_t)(a_elems + scr) * esz + (size_t)u_total * (5 * 4 + 2 * 8) + (size_t)t_total * 4 +
+  const size_t work = (size_t)ws * esz + (size_t)u_total * (5 * 4 + 2 * 8) + (size_t)t_total * 4 +
                       (size_t)D.n_sub * (4 + 8);
   if (resident) *resident = res;
   if (peak) *peak = res + work;

@@ -195,6 +195,71 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* _
   }
 }
 
+// Chunked form, for subdomains whose v|Sigma_j does not fit in LDS: v is
+// staged `chunk` columns at a time and each row's partial sums are kept in LDS
+// (at most PRECOND_RPB_MAX rows per block), then the rows are written once.
+constexpr int PRECOND_CHUNK = 4096;     // columns of v per pass (default)
+constexpr int PRECOND_RPB_MAX = 1024;   // rows per block in the chunked form
+
+template <typename T>
+__global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const SubDesc* __restrict__ desc,
+                                                                     const int32_t* __restrict__ blk_sub,
+                                                                     const int32_t* __restrict__ sig_idx,
+                                                                     const int32_t* __restrict__ tilde_idx,
+                                                                     const T* __restrict__ W,
+                                                                     const double* __restrict__ v,
+                                                                     const double* __restrict__ scale,
+                                                                     double* __restrict__ z, int chunk) {
+  extern __shared__ double lds[];
+  double* vs = lds;          // chunk columns of v|Sigma_j
+  double* ps = lds + chunk;  // partial sums of the block's rows
+  typedef typename VecOf<T>::type VT;
+  constexpr int VN = VecOf<T>::n;
+  constexpr int NWAVE = PRECOND_THREADS / 64;
+  const int blk = blockIdx.x;
+  const int j = blk_sub[blk];
+  const SubDesc d = desc[j];
+  const double sc = scale ? *scale : 1.0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r_begin = (blk - d.blk_off) * d.rpb;
+  const int r_end = min(r_begin + d.rpb, d.t);
+  for (int q = threadIdx.x; q < r_end - r_begin; q += PRECOND_THREADS) ps[q] = 0.0;
+  for (int c0 = 0; c0 < d.ldw; c0 += chunk) {
+    const int cw = min(chunk, d.ldw - c0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int c = threadIdx.x; c < cw; c += PRECOND_THREADS)
+      vs[c] = c0 + c < d.m ? sc * v[sig_idx[d.u_off + c0 + c]] : 0.0;
+    __syncthreads();
+    for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += NWAVE * PRECOND_RPW) {
+      const T* wr[PRECOND_RPW];
+      double acc[PRECOND_RPW];
+#pragma unroll
+      for (int i = 0; i < PRECOND_RPW; ++i) {
+        wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw + c0;
+        acc[i] = 0.0;
+      }
+      for (int c = lane * VN; c < cw; c += 64 * VN) {
+        VT wv[PRECOND_RPW];
+#pragma unroll
+        for (int i = 0; i < PRECOND_RPW; ++i) wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          const double xv = vs[c + e];
+#pragma unroll
+          for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[i][e] * xv;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PRECOND_RPW; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0 && r0 + i < r_end) ps[r0 + i - r_begin] += s;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < r_end - r_begin; q += PRECOND_THREADS) z[tilde_idx[d.t_off + r_begin + q]] = ps[q];
+}
+
 // ---------------------------------------------------------------------------
 // Local operator assembly (Section 5, eq. localOP) into the augmented matrix
 //   [ A_j        E_Sigma ]      E_Sigma: identity on the Sigma_j rows

@@ -266,3 +266,83 @@ def test_stationary_solver_follows_oracle(direct_cfg1, kind):
     info2, rc2 = ctx.solve_stationary(dev(f), u, tol=1e-14, max_iter=3)
     assert rc2 == P.ENOTCONV and info2["iters"] == 3
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
+def test_grouped_factorisation_is_identical(prec):
+    """Factoring the subdomains in workspace-bounded groups gives bit-identical
+    local solution operators and preconditioner applies."""
+    say("grouped factor", prec)
+    surf, h = SURF["torus"]
+    ctxs = []
+    for limit in (0, 1):  # default (one group) / 1 byte (one subdomain per group)
+        ctx = P.Context(0)
+        ctx.build_band(surf, h, 3)
+        ctx.build_operator(0.8)
+        ctx.partition(P.PART_RCB, 11, None, 3, P.ORAS, 4.47, 20.0)
+        ctx.set_factor_workspace(limit)
+        ctx.factor(prec)
+        ctxs.append(ctx)
+    assert ctxs[0].factor_groups() == 1 and ctxs[1].factor_groups() == 11
+    for j in (0, 4, 10):
+        np.testing.assert_array_equal(ctxs[1].factor_export(j), ctxs[0].factor_export(j))
+    na = ctxs[0].band_sizes()[0]
+    v = dev(np.random.default_rng(5).standard_normal(na))
+    zs = []
+    for ctx in ctxs:
+        z = torch.zeros(na, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(v, z)
+        zs.append(z.cpu().numpy())
+    np.testing.assert_array_equal(zs[0], zs[1])
+    r1, p1 = ctxs[1].footprint_estimate(prec, 30)
+    r0, p0 = ctxs[0].footprint_estimate(prec, 30)
+    assert r1 == r0 and p1 < p0
+    for ctx in ctxs:
+        ctx.close()
+
+
+@pytest.mark.parametrize("chunk", [8, 264, 1024])
+def test_chunked_preconditioner_apply(chunk):
+    """The chunked apply (v|Sigma_j staged a chunk at a time) against the oracle
+    and the unchunked apply, with chunk widths that leave ragged last chunks."""
+    say("chunked precond", chunk)
+    b, dec, ctx = _setup("torus", 3, "rcb", 16, 3, "ORAS", 4.47, 20.0)
+    ctx.factor(P.FP64)
+    assert ctx.precond_chunk() == 0
+    na = b.n_act
+    v = np.random.default_rng(8).standard_normal(na)
+    z0 = torch.zeros(na, dtype=torch.float64, device="cuda")
+    ctx.apply_precond(dev(v), z0)
+    ctx.set_precond_chunk(chunk)
+    ctx.factor(P.FP64)
+    assert ctx.precond_chunk() == chunk
+    z1 = torch.zeros(na, dtype=torch.float64, device="cuda")
+    ctx.apply_precond(dev(v), z1)
+    assert rel(z1.cpu().numpy(), z0.cpu().numpy()) < 1e-13
+    M = schwarz.Preconditioner(b, dec, 1.0)
+    assert rel(z1.cpu().numpy(), M.apply(v)) < 1e-9
+    with pytest.raises(P.CpmError):
+        ctx.set_precond_chunk(12)
+    ctx.close()
+
+
+def test_one_large_subdomain_uses_chunked_apply_and_is_a_direct_solve():
+    """One subdomain of 35k nodes (v|Sigma does not fit in LDS): the chunked
+    apply is chosen by itself, and with M^{-1} = A^{-1} FGMRES stops after one
+    iteration (up to rounding)."""
+    h, c = 0.05, 1.0
+    say("one large subdomain")
+    b = oracle.build_band(ci.Sphere(), h, 3, [-2.0] * 3, [2.0] * 3)
+    assert b.n_act > 20480
+    A = oracle.stabilized_operator(b, c)
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), h, 3)
+    ctx.build_operator(c)
+    ctx.partition(P.PART_RCB, 1, None, 2, P.RAS, 0.0, 0.0)
+    ctx.factor(P.FP64)
+    assert ctx.precond_chunk() > 0
+    f = ci.rhs_sphere_random_sh(b.cp[: b.n_act], c, seed=4)[0]
+    u, info, rc = ctx.solve(f, tol=1e-10, max_iter=20, restart=30)
+    assert rc == P.OK and info[0]["iters"] <= 2, info
+    assert np.linalg.norm(f - A @ u) / np.linalg.norm(f) <= 1.05e-10
+    ctx.close()

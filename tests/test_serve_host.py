@@ -105,6 +105,12 @@ def test_clone_and_footprint_estimate_host_only():
     np.testing.assert_array_equal(part0, part1)
     np.testing.assert_array_equal(cross0, cross1)
     assert cl.footprint_estimate(P.FP32, 30) == (r32, p32)
+    # a smaller factor workspace lowers the peak, not what stays resident
+    cl.set_factor_workspace(1)
+    r1, p1 = cl.footprint_estimate(P.FP32, 30)
+    assert r1 == r32 and r32 < p1 < p32
+    cl.set_factor_workspace(0)
+    assert cl.footprint_estimate(P.FP32, 30) == (r32, p32)
     cl.build_operator(2.5)  # a new c keeps the partition
     assert cl.partition_info()[0] == 8
     cl.close()
