@@ -55,7 +55,8 @@ enum {
 
 enum { CPM_RAS = 0, CPM_ORAS = 1 };                 /* transmission condition */
 enum { CPM_FP64 = 0, CPM_FP32 = 1 };                /* local factor precision */
-enum { CPM_PART_OCTANT = 0, CPM_PART_RCB = 1 };     /* disjoint partition */
+enum { CPM_PART_OCTANT = 0, CPM_PART_RCB = 1, CPM_PART_GRAPH = 2 };  /* disjoint partition */
+enum { CPM_PART_ALIGN = 16 };  /* flag: align interfaces with the surface normals (Section 3.2) */
 
 /*
  * Closest-point callback (the surface representation CP_S of Section 2.1).
@@ -119,9 +120,14 @@ int cpm_build_operator(cpm_ctx* ctx, double c);
 
 /*
  * Overlapping decomposition (Sections 3, 4, 5).
- * method: CPM_PART_OCTANT (n_sub must be 8) or CPM_PART_RCB (recursive
+ * method: CPM_PART_OCTANT (n_sub must be 8), CPM_PART_RCB (recursive
  *   coordinate bisection into n_sub parts; weights = n_sub target weights for
- *   weighted bisection, or NULL).
+ *   weighted bisection, or NULL) or CPM_PART_GRAPH (recursive bisection of the
+ *   6-neighbour graph of the active nodes by breadth-first distance from a
+ *   pseudo-peripheral node, Section 3.1's graph view; weights as for RCB),
+ *   optionally OR'ed with CPM_PART_ALIGN: degree + 1 passes in which every
+ *   node with a neighbour in another part moves to the part of the grid node
+ *   nearest to its closest point (Section 3.2). EINVAL if a part ends empty.
  * overlap: N_O >= 0 layers (>= 1 for ORAS).
  * kind: CPM_RAS or CPM_ORAS; alpha: Robin weight (ORAS, > 0);
  * alpha_cross: weight for boundary nodes within 2 N_O h of a cross point

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libcpm.so")
 OK, ENOTCONV, EINVAL, ESTATE, ENOMEM, ESINGULAR, EDEVICE, ECALLBACK = 0, 1, -1, -2, -3, -4, -5, -6
 RAS, ORAS = 0, 1
 FP64, FP32 = 0, 1
-PART_OCTANT, PART_RCB = 0, 1
+PART_OCTANT, PART_RCB, PART_GRAPH = 0, 1, 2
+PART_ALIGN = 16
 TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM = 0, 1, 2, 3
 
 _NAMES = {OK: "OK", ENOTCONV: "ENOTCONV", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM",

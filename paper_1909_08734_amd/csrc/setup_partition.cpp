@@ -52,6 +52,150 @@ void rcb(const Band& b, std::vector<int32_t>& idx, int first, int n, const doubl
   rcb(b, right, first + nl, n - nl, w, part);
 }
 
+// Recursive graph bisection of the 6-neighbour graph of the actives: as rcb,
+// but nodes are ordered by breadth-first distance inside the subgraph induced
+// by the current set, from a pseudo-peripheral node (a sweep from the lowest
+// band index finds the farthest node, lowest index on ties; a second sweep
+// starts there), ties by band index; unreachable nodes come last. idx is
+// sorted by band index on entry; pos is a scratch map band index -> position
+// (-1 outside the set).
+void bfs_dist(const Band& b, const std::vector<int32_t>& idx, const std::vector<int32_t>& pos, int start,
+              std::vector<int32_t>& dist) {
+  const int64_t na = b.n_act;
+  dist.assign(idx.size(), -1);
+  std::vector<int32_t> queue;
+  queue.reserve(idx.size());
+  dist[start] = 0;
+  queue.push_back(start);
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int32_t u = queue[h];
+    const int32_t q = idx[u];
+    for (int e = 0; e < 6; ++e) {
+      const int32_t y = b.nbr[(size_t)q * 6 + e];
+      if (y >= na) continue;
+      const int32_t v = pos[y];
+      if (v < 0 || dist[v] >= 0) continue;
+      dist[v] = dist[u] + 1;
+      queue.push_back(v);
+    }
+  }
+}
+
+void graph_bisect(const Band& b, std::vector<int32_t>& idx, int first, int n, const double* w,
+                  std::vector<int32_t>& pos, std::vector<int32_t>& part) {
+  if (n == 1) {
+    for (int32_t q : idx) part[q] = first;
+    return;
+  }
+  for (size_t u = 0; u < idx.size(); ++u) pos[idx[u]] = (int32_t)u;
+  std::vector<int32_t> dist;
+  bfs_dist(b, idx, pos, 0, dist);
+  int far = 0;
+  for (size_t u = 1; u < idx.size(); ++u)
+    if (dist[u] > dist[far]) far = (int)u;
+  bfs_dist(b, idx, pos, far, dist);
+  for (int32_t q : idx) pos[q] = -1;
+  const int32_t unreached = (int32_t)b.n_act + 1;
+  std::vector<int32_t> order(idx.size());
+  for (size_t u = 0; u < idx.size(); ++u) order[u] = (int32_t)u;
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const int32_t dx = dist[x] < 0 ? unreached : dist[x], dy = dist[y] < 0 ? unreached : dist[y];
+    if (dx != dy) return dx < dy;
+    return idx[x] < idx[y];
+  });
+  const int nl = n / 2;
+  size_t cut;
+  if (!w) {
+    cut = (idx.size() * (size_t)nl) / (size_t)n;
+  } else {
+    double wl = 0.0, wt = 0.0;
+    for (int q = first; q < first + nl; ++q) wl += w[q];
+    for (int q = first; q < first + n; ++q) wt += w[q];
+    cut = (size_t)std::floor((double)idx.size() * wl / wt);
+  }
+  std::vector<int32_t> left, right;
+  left.reserve(cut);
+  right.reserve(idx.size() - cut);
+  for (size_t u = 0; u < idx.size(); ++u) (u < cut ? left : right).push_back(idx[order[u]]);
+  idx.clear();
+  idx.shrink_to_fit();
+  std::sort(left.begin(), left.end());
+  std::sort(right.begin(), right.end());
+  // Pieces of the right group cut off from its largest connected piece (ties:
+  // the piece holding the lowest band index) join the left group.
+  if (!right.empty()) {
+    for (size_t u = 0; u < right.size(); ++u) pos[right[u]] = (int32_t)u;
+    std::vector<int32_t> comp(right.size(), -1), csize;
+    int ncomp = 0;
+    std::vector<int32_t> queue;
+    for (size_t s0 = 0; s0 < right.size(); ++s0) {
+      if (comp[s0] >= 0) continue;
+      comp[s0] = ncomp;
+      queue.assign(1, (int32_t)s0);
+      for (size_t hq = 0; hq < queue.size(); ++hq) {
+        const int32_t q = right[queue[hq]];
+        for (int e = 0; e < 6; ++e) {
+          const int32_t y = b.nbr[(size_t)q * 6 + e];
+          if (y >= b.n_act) continue;
+          const int32_t v = pos[y];
+          if (v < 0 || comp[v] >= 0) continue;
+          comp[v] = ncomp;
+          queue.push_back(v);
+        }
+      }
+      csize.push_back((int32_t)queue.size());
+      ++ncomp;
+    }
+    for (int32_t q : right) pos[q] = -1;
+    if (ncomp > 1) {
+      int keep = 0;  // components are numbered in order of their lowest member
+      for (int c = 1; c < ncomp; ++c)
+        if (csize[c] > csize[keep]) keep = c;
+      std::vector<int32_t> r2;
+      for (size_t u = 0; u < right.size(); ++u) (comp[u] == keep ? r2 : left).push_back(right[u]);
+      right.swap(r2);
+      std::sort(left.begin(), left.end());
+    }
+  }
+  graph_bisect(b, left, first, nl, w, pos, part);
+  graph_bisect(b, right, first + nl, n - nl, w, pos, part);
+}
+
+// Interface alignment (Section 3.2): `passes` rounds in which every node with
+// an active FD neighbour in another part moves, all at once, to the part of
+// the grid node nearest to its closest point.
+int align_interfaces(const Band& b, std::vector<int32_t>& part, int passes, std::string& err) {
+  const int64_t na = b.n_act;
+  std::vector<int32_t> xbar(na);
+  for (int64_t q = 0; q < na; ++q) {
+    int64_t g[3];
+    for (int a = 0; a < 3; ++a) {
+      const double t = (b.cp[q * 3 + a] - b.lo[a]) / b.h;
+      g[a] = (int64_t)std::floor(t + 0.5);
+    }
+    const int64_t L = (g[0] * b.n[1] + g[1]) * b.n[2] + g[2];
+    const auto it = std::lower_bound(b.lin.begin(), b.lin.begin() + na, L);
+    if (it == b.lin.begin() + na || *it != L) {
+      err = "partition: a closest point's nearest grid node is not active";
+      return CPM_EINVAL;
+    }
+    xbar[q] = (int32_t)(it - b.lin.begin());
+  }
+  std::vector<int32_t> next(na);
+  for (int pass = 0; pass < passes; ++pass) {
+    for (int64_t q = 0; q < na; ++q) {
+      bool iface = false;
+      for (int e = 0; e < 6; ++e) {
+        const int32_t y = b.nbr[q * 6 + e];
+        if (y < na && part[y] != part[q]) iface = true;
+      }
+      next[q] = iface ? part[xbar[q]] : part[q];
+    }
+    part.swap(next);
+  }
+  return CPM_OK;
+}
+
 void sort_unique(std::vector<int32_t>& v) {
   std::sort(v.begin(), v.end());
   v.erase(std::unique(v.begin(), v.end()), v.end());
@@ -68,8 +212,13 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
   if (kind == CPM_ORAS && !(alpha > 0 && std::isfinite(alpha))) { err = "partition: ORAS needs a positive finite alpha"; return CPM_EINVAL; }
   if (!(alpha_cross >= 0) || !std::isfinite(alpha_cross)) { err = "partition: alpha_cross must be >= 0"; return CPM_EINVAL; }
   if (n_sub < 1 || n_sub > na) { err = "partition: n_sub out of range"; return CPM_EINVAL; }
+  const bool align = (method & CPM_PART_ALIGN) != 0;
+  method &= ~CPM_PART_ALIGN;
   if (method == CPM_PART_OCTANT && n_sub != 8) { err = "partition: octant partition has 8 parts"; return CPM_EINVAL; }
-  if (method != CPM_PART_OCTANT && method != CPM_PART_RCB) { err = "partition: unknown method"; return CPM_EINVAL; }
+  if (method != CPM_PART_OCTANT && method != CPM_PART_RCB && method != CPM_PART_GRAPH) {
+    err = "partition: unknown method";
+    return CPM_EINVAL;
+  }
   if (weights)
     for (int q = 0; q < n_sub; ++q)
       if (!(weights[q] > 0) || !std::isfinite(weights[q])) { err = "partition: weights must be positive"; return CPM_EINVAL; }
@@ -86,10 +235,18 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
       const int32_t* x = &b.ijk[q * 3];
       nd.part[q] = 4 * (x[0] >= b.n[0] / 2) + 2 * (x[1] >= b.n[1] / 2) + (x[2] >= b.n[2] / 2);
     }
-  } else {
+  } else if (method == CPM_PART_RCB) {
     std::vector<int32_t> idx(na);
     for (int64_t q = 0; q < na; ++q) idx[q] = (int32_t)q;
     rcb(b, idx, 0, n_sub, weights, nd.part);
+  } else {
+    std::vector<int32_t> idx(na), pos(na, -1);
+    for (int64_t q = 0; q < na; ++q) idx[q] = (int32_t)q;
+    graph_bisect(b, idx, 0, n_sub, weights, pos, nd.part);
+  }
+  if (align) {
+    const int rc = align_interfaces(b, nd.part, b.p + 1, err);
+    if (rc != CPM_OK) return rc;
   }
   std::vector<int64_t> count(n_sub, 0);
   for (int32_t q : nd.part) count[q]++;

@@ -5,7 +5,8 @@ Settings follow Section 6: tri-quadratic extension (p = 2) with the tube radius
 2.6067 h (which reproduces the paper's band sizes, e.g. N_A = 654,630 for the
 unit sphere at h = 1/100), torus R = 2/3, r = 1/3, convergence when the
 residual 2-norm has dropped by 10^6. Differences: recursive coordinate
-bisection instead of METIS, right-preconditioned FGMRES(30) on the true
+bisection (or the graph bisection, optionally with the interface alignment of
+Section 3.2: --partition) instead of METIS, right-preconditioned FGMRES(30) on the true
 residual instead of left-preconditioned GMRES, seeded synthetic right-hand
 sides (the paper does not state its own), c = 1, FP64 local factors.
 
@@ -31,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BAND_FACTOR = 2.6067
+METHOD = "rcb"  # partitioner: rcb or graph, optionally +align
 DEGREE = 2
 TOL = 1e-6
 
@@ -68,7 +70,10 @@ class Problem:
         P, torch = self.P, self.torch
         prec = P.FP64 if prec is None else prec
         t0 = time.time()
-        self.ctx.partition(P.PART_RCB, n_sub, None, overlap, P.ORAS if kind == "ORAS" else P.RAS, alpha, alpha_x)
+        code = {"rcb": P.PART_RCB, "graph": P.PART_GRAPH}[METHOD.split("+")[0]]
+        if METHOD.endswith("+align"):
+            code |= P.PART_ALIGN
+        self.ctx.partition(code, n_sub, None, overlap, P.ORAS if kind == "ORAS" else P.RAS, alpha, alpha_x)
         self.ctx.factor(prec)
         factor_s = time.time() - t0
         u = torch.zeros_like(self.f)
@@ -83,7 +88,7 @@ class Problem:
                 "solver_relres": info_s["relres_true"],
                 "precond_iters": info_g["iters"] if rc_g == P.OK else None,
                 "precond_relres": info_g["relres_true"], "factor_s": round(factor_s, 2),
-                "groups": self.ctx.factor_groups(), "chunk": self.ctx.precond_chunk()}
+                "groups": self.ctx.factor_groups(), "chunk": self.ctx.precond_chunk(), "partition": METHOD}
 
     def close(self):
         self.ctx.close()
@@ -131,7 +136,10 @@ def main():
     ap.add_argument("--hs", type=float, nargs="+", default=[1 / 15, 1 / 20])
     ap.add_argument("--n-sub", type=int, nargs="+", default=[32, 64, 96])
     ap.add_argument("--overlaps", type=int, nargs="+", default=[4, 8, 12])
+    ap.add_argument("--partition", default="rcb", choices=["rcb", "rcb+align", "graph", "graph+align"])
     args = ap.parse_args()
+    global METHOD
+    METHOD = args.partition
     {"table8": table8, "table6": table6, "table2": table2}[args.table](args)
 
 

@@ -37,6 +37,10 @@ CASES = [
     (ci.Torus(1.0, 0.4), 0.05, 3, "rcb", 12, 3),
     (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08, 2, "wrcb", 6, 1),
     (ci.bumpy_icosphere(level=3, far=0.6), 0.1, 3, "rcb", 8, 2),
+    (ci.Torus(1.0, 0.4), 0.05, 3, "graph", 12, 3),
+    (ci.Sphere(), 0.1, 2, "graph+align", 7, 2),
+    (ci.Torus(1.0, 0.4), 0.05, 3, "rcb+align", 16, 2),
+    (ci.Sphere(1.0, (0.013, 0.027, 0.031)), 0.08, 3, "wgraph+align", 6, 1),
 ]
 
 
@@ -56,13 +60,21 @@ def test_host_setup_matches_oracle(case, kind):
     np.testing.assert_array_equal(arr["cp"], b.cp)
     np.testing.assert_allclose(arr["wts"], b.wts, rtol=0, atol=1e-15)
     ctx.build_operator(1.0)
-    weights = ci.wrcb_weights(n, seed=2) if method == "wrcb" else None
-    if method == "octant":
+    weights = ci.wrcb_weights(n, seed=2) if method.startswith("w") else None
+    base = method.split("+")[0].lstrip("w")
+    if base == "octant":
         opart = oracle.octant_partition(b)
-        ctx.partition(P.PART_OCTANT, 8, None, no, getattr(P, kind), 3.0, 30.0)
-    else:
+        code = P.PART_OCTANT
+    elif base == "rcb":
         opart = oracle.rcb_partition(b, n, weights=weights)
-        ctx.partition(P.PART_RCB, n, weights, no, getattr(P, kind), 3.0, 30.0)
+        code = P.PART_RCB
+    else:
+        opart = oracle.graph_partition(b, n, weights=weights)
+        code = P.PART_GRAPH
+    if method.endswith("+align"):
+        opart = oracle.align_interfaces(b, opart, p + 1)
+        code |= P.PART_ALIGN
+    ctx.partition(code, n, weights, no, getattr(P, kind), 3.0, 30.0)
     nsub, part, cross = ctx.partition_info()
     dec = schwarz.decompose(b, opart, no, kind, alpha=3.0, alpha_cross=30.0)
     assert nsub == len(dec.subs)

@@ -73,13 +73,20 @@ def test_operator_apply(name, p):
 def _setup(name, p, method, n, no, kind, alpha, alpha_cross, c=1.0):
     surf, h = SURF[name]
     b = oracle.build_band(surf, h, p, [-2.0] * 3, [2.0] * 3)
-    part = oracle.octant_partition(b) if method == "octant" else oracle.rcb_partition(b, n)
+    base = method.split("+")[0]
+    if base == "octant":
+        part, code = oracle.octant_partition(b), P.PART_OCTANT
+    elif base == "rcb":
+        part, code = oracle.rcb_partition(b, n), P.PART_RCB
+    else:
+        part, code = oracle.graph_partition(b, n), P.PART_GRAPH
+    if method.endswith("+align"):
+        part, code = oracle.align_interfaces(b, part, p + 1), code | P.PART_ALIGN
     dec = schwarz.decompose(b, part, no, kind, alpha=alpha, alpha_cross=alpha_cross)
     ctx = P.Context(0)
     ctx.build_band(surf, h, p)
     ctx.build_operator(c)
-    ctx.partition(P.PART_OCTANT if method == "octant" else P.PART_RCB, n, None, no, getattr(P, kind),
-                  alpha, alpha_cross)
+    ctx.partition(code, n, None, no, getattr(P, kind), alpha, alpha_cross)
     return b, dec, ctx
 
 
@@ -89,6 +96,7 @@ PRECOND_CASES = [
     ("torus", 3, "rcb", 16, 3, "ORAS", 4.47, 20.0),
     ("offsphere", 2, "rcb", 5, 1, "ORAS", 2.0, 0.0),
     ("trimesh", 3, "rcb", 8, 2, "ORAS", 3.16, 10.0),
+    ("torus", 3, "graph+align", 12, 2, "ORAS", 4.47, 20.0),
 ]
 
 
