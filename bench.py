@@ -261,6 +261,23 @@ def run_gpu(args, wl):
                 "stencil_ms_avg": st_ms / max(st_n, 1),
                 "footprint_GB": ctx.footprint_bytes() / 1e9,
             }
+            if a_name == wl["alphas"][0][0] and args.steps >= 2:
+                # the same K right-hand sides solved in lockstep batches that share
+                # each pass over the factors (results equal the separate solves)
+                nb = 4 if args.steps >= 4 else 2
+                ctx.solve_device(f_dev[args.warmup:args.warmup + nb], u_dev[args.warmup:args.warmup + nb],
+                                 tol=tol, max_iter=3000, restart=RESTART)  # warm-up (workspace)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                binfo, brc = ctx.solve_device(f_dev[args.warmup:nrhs], u_dev[args.warmup:nrhs], tol=tol,
+                                              max_iter=3000, restart=RESTART)
+                torch.cuda.synchronize()
+                wb = time.perf_counter() - t0
+                if brc != P.OK:
+                    raise RuntimeError(f"batched solve did not converge: {binfo}")
+                r["batched"] = {"rhs_per_call": args.steps, "solves_per_s": args.steps / wb,
+                                "ms_per_solve": 1e3 * wb / args.steps,
+                                "iters_mean": float(np.mean([i["iters"] for i in binfo]))}
             if a_name == wl["alphas"][0][0] and args.restart60:
                 # longer restart cycles: fewer iterations, same factors
                 torch.cuda.synchronize()

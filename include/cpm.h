@@ -176,7 +176,13 @@ int cpm_factor(cpm_ctx* ctx, int prec);
  */
 int cpm_solve(cpm_ctx* ctx, const double* f, double* u, int nrhs, double tol, int max_iter,
               int restart, cpm_solve_info* info);
-/* Same with device pointers (inputs resident in HBM). */
+/*
+ * Same with device pointers (inputs resident in HBM). With nrhs >= 2 the
+ * right-hand sides are solved in lockstep batches of up to 4 that share each
+ * pass over the factors (when v|Sigma_j of all of them fits in LDS); every
+ * right-hand side follows the single-solve sequence, so results, iteration
+ * counts and statuses equal separate solves; info[q].ms is the batch's time.
+ */
 int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs, double tol,
                      int max_iter, int restart, cpm_solve_info* info);
 

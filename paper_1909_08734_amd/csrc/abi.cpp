@@ -166,12 +166,22 @@ static int solve_common(cpm_ctx* ctx, const double* f, double* u, int nrhs, doub
   return guarded(ctx, [&]() -> int {
     const int64_t na = ctx->band.n_act;
     int worst = CPM_OK;
-    for (int q = 0; q < nrhs; ++q) {
-      cpm_solve_info tmp{};
-      int rc = cpm::dev_solve(ctx, f + (size_t)q * na, u + (size_t)q * na, tol, max_iter, restart, &tmp);
-      if (info) info[q] = tmp;
+    for (int q = 0; q < nrhs;) {
+      // several right-hand sides share each pass over the factors when they fit
+      const int nb = cpm::dev_batch_width(ctx, nrhs - q);
+      cpm_solve_info tmp[4] = {};
+      int rc;
+      if (nb >= 2) {
+        rc = cpm::dev_solve_batch(ctx, f + (size_t)q * na, u + (size_t)q * na, nb, tol, max_iter, restart, tmp);
+      } else {
+        rc = cpm::dev_solve(ctx, f + (size_t)q * na, u + (size_t)q * na, tol, max_iter, restart, tmp);
+      }
+      const int took = nb >= 2 ? nb : 1;
+      if (info)
+        for (int r = 0; r < took; ++r) info[q + r] = tmp[r];
       if (rc < 0) return rc;
       if (rc > worst) worst = rc;
+      q += took;
     }
     return worst;
   });

@@ -113,6 +113,16 @@ struct Dev {
   struct HostSlot* slots_dev = nullptr;  // the same memory, device view
   unsigned long long ticket = 0;     // last ticket handed out
   size_t krylov_bytes = 0;
+  // Krylov workspace of a batch of right-hand sides solved in lockstep
+  int b_restart = 0, b_n = 0;
+  double* bV = nullptr;         // b_n x (restart+1) x ld
+  double* bZ = nullptr;         // b_n x restart x ld
+  double* bE = nullptr;         // b_n x N_T extension scratch
+  double* bpart = nullptr;      // b_n x partial sums
+  double* bsmall = nullptr;     // b_n x small buffer
+  struct HostSlot* bslots = nullptr;      // b_n x (restart+2), host view
+  struct HostSlot* bslots_dev = nullptr;  // device view
+  size_t batch_bytes = 0;
   size_t op_bytes = 0;
 };
 
@@ -140,6 +150,9 @@ int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);
 int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
               cpm_solve_info* info);
 int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, cpm_solve_info* info);
+int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol, int max_iter, int restart,
+                    cpm_solve_info* info);
+int dev_batch_width(cpm_ctx* ctx, int nrhs);
 int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double scale, double tol, int max_iter,
                     int restart, cpm_solve_info* info);
 int dev_export_w(cpm_ctx* ctx, int j, double* w);

@@ -105,6 +105,16 @@ static void free_krylov(cpm_ctx* ctx) {
   if (d.slots) hipHostFree(d.slots);
   d.slots = nullptr;
   d.slots_dev = nullptr;
+  dfree(d.bV);
+  dfree(d.bZ);
+  dfree(d.bE);
+  dfree(d.bpart);
+  dfree(d.bsmall);
+  if (d.bslots) hipHostFree(d.bslots);
+  d.bslots = nullptr;
+  d.bslots_dev = nullptr;
+  d.b_restart = d.b_n = 0;
+  d.batch_bytes = 0;
   d.restart = 0;
   d.krylov_bytes = 0;
 }
@@ -137,17 +147,20 @@ int dev_upload_operator(cpm_ctx* ctx) {
   return CPM_OK;
 }
 
-// e = E x over the whole band (active and ghost rows)
-static void launch_extend(cpm_ctx* ctx, const double* x) {
+// e = E x over the whole band (active and ghost rows); nb right-hand sides
+// x + q x_stride -> e + q e_stride
+static void launch_extend(cpm_ctx* ctx, const double* x, double* e, int nb = 1, int64_t x_stride = 0,
+                          int64_t e_stride = 0) {
   const Band& b = ctx->band;
   Dev& d = ctx->dev;
   const int64_t nt = b.total();
+  const dim3 grid(nblk(nt * 2, 256), nb);
   if (b.p == 3)
-    launch(ctx, TIMER_EXTEND, k_extend<3>, dim3(nblk(nt * 2, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
-           (const double*)d.wts, x, d.e);
+    launch(ctx, TIMER_EXTEND, k_extend<3>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts, x,
+           e, x_stride, e_stride);
   else
-    launch(ctx, TIMER_EXTEND, k_extend<2>, dim3(nblk(nt * 2, 256)), dim3(256), 0, nt, (const int32_t*)d.lines,
-           (const double*)d.wts, x, d.e);
+    launch(ctx, TIMER_EXTEND, k_extend<2>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts, x,
+           e, x_stride, e_stride);
 }
 
 // e = E x, y = A x (or y = f - A x when f != nullptr)
@@ -157,7 +170,7 @@ static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const doub
   const double ih2 = 1.0 / (b.h * b.h);
   const double diag = ctx->c + 6.0 * ih2;
   const int64_t na = b.n_act;
-  launch_extend(ctx, x);
+  launch_extend(ctx, x, d.e);
   launch(ctx, TIMER_STENCIL, k_stencil, dim3(nblk(na, 256)), dim3(256), 0, na, diag, ih2, (const int32_t*)d.nbr, x,
          (const double*)d.e, f, y);
 }
@@ -748,16 +761,17 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
     double* w = d.V + (size_t)(k + 1) * d.ld;
     double* zk = d.Z + (size_t)k * d.ld;
     launch_precond(ctx, vk, zk, scal + S_INV);  // z_k = M^{-1} (V[k] / ||V[k]||)
-    launch_extend(ctx, zk);                     // e = E z_k
+    launch_extend(ctx, zk, d.e);                // e = E z_k
     // w = A z_k fused with CGS pass 1 (normalising V[k] in place), then pass 2,
     // ||w|| and the Givens update
+    const BatchStrides one{};
     k_stencil_dots<<<rb, RED_THREADS, 0, st>>>(na, diag, ih2, d.nbr, zk, d.e, w, d.V, d.ld, k + 1, d.part, k,
-                                               scal + S_INV);
-    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h1());
-    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0);
-    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h2());
-    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h2(), w, d.part, 1);
-    k_arnoldi<<<1, RED_THREADS, 0, st>>>(d.part, rb, k, L, sm, slots_dev + k, ticket_for(k));
+                                               scal + S_INV, one);
+    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h1(), one);
+    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0, one);
+    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h2(), one);
+    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h2(), w, d.part, 1, one);
+    k_arnoldi<<<1, RED_THREADS, 0, st>>>(d.part, rb, k, L, sm, slots_dev + k, ticket_for(k), one);
     return CPM_OK;
   };
   for (;;) {
@@ -788,6 +802,264 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   }
   HIPCHK(hipGetLastError());
   return finish(status, iters, cycles, rel_true, rel_est);
+}
+
+// ---------------------------------------------------------------------------
+// Several right-hand sides in lockstep: the per-iteration kernels run for the
+// whole batch in one launch each (blockIdx.y = right-hand side) and the
+// preconditioner streams W once for all of them. Each right-hand side follows
+// exactly the single-solve sequence (same kernels, same sums, same restarts;
+// one that has stopped within a cycle idles until the cycle ends), so the
+// results equal separate solves bit for bit.
+// ---------------------------------------------------------------------------
+static int ensure_krylov_batch(cpm_ctx* ctx, int m, int nb) {
+  Dev& d = ctx->dev;
+  if (d.b_restart == m && d.b_n >= nb && d.bV) return CPM_OK;
+  dfree(d.bV);
+  dfree(d.bZ);
+  dfree(d.bE);
+  dfree(d.bpart);
+  dfree(d.bsmall);
+  if (d.bslots) hipHostFree(d.bslots);
+  d.bslots = d.bslots_dev = nullptr;
+  d.b_restart = d.b_n = 0;
+  const int64_t na = ctx->band.n_act, nt = ctx->band.total();
+  const int64_t ld = round_up(na, 64);
+  const SmallLayout L{m};
+  HIPCHK(hipMalloc((void**)&d.bV, (size_t)nb * (m + 1) * ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.bZ, (size_t)nb * m * ld * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.bE, (size_t)nb * round_up(nt, 64) * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.bpart, (size_t)nb * RED_MAX_BLOCKS * PART_LD * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d.bsmall, (size_t)nb * L.size() * sizeof(double)));
+  HIPCHK(hipHostMalloc((void**)&d.bslots, (size_t)nb * (m + 2) * sizeof(HostSlot),
+                       hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset((void*)d.bslots, 0, (size_t)nb * (m + 2) * sizeof(HostSlot));
+  HIPCHK(hipHostGetDevicePointer((void**)&d.bslots_dev, d.bslots, 0));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  d.b_restart = m;
+  d.b_n = nb;
+  d.batch_bytes = ((size_t)nb * ((2 * m + 1) * ld + round_up(nt, 64) + RED_MAX_BLOCKS * PART_LD + L.size())) *
+                  sizeof(double);
+  return CPM_OK;
+}
+
+// Right-hand sides one pass over W can serve: v_q|Sigma_j for all of them must
+// fit in LDS next to each other (0: batching not available).
+int dev_batch_width(cpm_ctx* ctx, int nrhs) {
+  const Dev& d = ctx->dev;
+  if (nrhs < 2 || d.chunk > 0 || d.prec < 0) return 0;
+  const size_t per = (size_t)d.max_m * sizeof(double);
+  for (int nb : {4, 2})
+    if (nb <= nrhs && nb * per <= 160 * 1024) return nb;
+  return 0;
+}
+
+template <int NB>
+static void launch_precond_multi(cpm_ctx* ctx, const double* v, int64_t v_stride, const double* scale,
+                                 int64_t scale_stride, double* z, int64_t z_stride) {
+  Dev& d = ctx->dev;
+  const size_t lds = (size_t)NB * d.max_m * sizeof(double);
+  if (d.prec == CPM_FP64) {
+    if (lds > 64 * 1024)
+      hipFuncSetAttribute((const void*)k_precond_multi<double, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+    launch(ctx, TIMER_PRECOND, k_precond_multi<double, NB>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
+           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
+           (const int32_t*)d.tilde_idx, (const double*)d.W, v, v_stride, scale, scale_stride, z, z_stride);
+  } else {
+    if (lds > 64 * 1024)
+      hipFuncSetAttribute((const void*)k_precond_multi<float, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+    launch(ctx, TIMER_PRECOND, k_precond_multi<float, NB>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
+           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
+           (const int32_t*)d.tilde_idx, (const float*)d.W, v, v_stride, scale, scale_stride, z, z_stride);
+  }
+}
+
+int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol, int max_iter, int m,
+                    cpm_solve_info* info) {
+  HIPCHK(hipSetDevice(ctx->device));
+  int rc = ensure_krylov_batch(ctx, m, nb);
+  if (rc != CPM_OK) return rc;
+  Dev& d = ctx->dev;
+  const int64_t na = ctx->band.n_act;
+  const int64_t ld = round_up(na, 64);
+  const SmallLayout L{m};
+  BatchStrides bs;
+  bs.v = (int64_t)(m + 1) * ld;
+  bs.z = (int64_t)m * ld;
+  bs.e = round_up(ctx->band.total(), 64);
+  bs.part = (int64_t)RED_MAX_BLOCKS * PART_LD;
+  bs.small = L.size();
+  bs.slot = m + 2;
+  hipStream_t st = ctx->stream;
+  const unsigned gv = nblk(na, 256);
+  const int rb = red_blocks(na);
+  const double ih2 = 1.0 / (ctx->band.h * ctx->band.h);
+  const double diag = ctx->c + 6.0 * ih2;
+  auto Vp = [&](int r, int k) { return d.bV + r * bs.v + (int64_t)k * ld; };
+  auto Zp = [&](int r, int k) { return d.bZ + r * bs.z + (int64_t)k * ld; };
+  auto SM = [&](int r) { return d.bsmall + r * bs.small; };
+  auto PART = [&](int r) { return d.bpart + r * bs.part; };
+  const double* fr[8];
+  double* ur[8];
+  for (int r = 0; r < nb; ++r) {
+    fr[r] = f + (size_t)r * na;
+    ur[r] = u + (size_t)r * na;
+  }
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, st));
+  std::vector<unsigned long long> expect(m + 2, 0);
+  auto ticket_for = [&](int slot) -> unsigned long long {
+    expect[slot] = ++d.ticket;
+    return expect[slot];
+  };
+  auto wait = [&](int r, int slot, const double** out) -> int {
+    HostSlot* hs = d.bslots + r * bs.slot + slot;
+    volatile unsigned long long* tk = &hs->ticket;
+    for (long spin = 0;; ++spin) {
+      if (*tk == expect[slot]) break;
+      if ((spin & 1023) == 1023) {
+        const hipError_t q = hipStreamQuery(st);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+          ctx->err = std::string("solve: device error ") + hipGetErrorString(q);
+          return CPM_EDEVICE;
+        }
+        if (q == hipSuccess && *tk != expect[slot]) {
+          ctx->err = "solve: stream idle but the step's result never arrived";
+          return CPM_EDEVICE;
+        }
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *out = (const double*)hs->v;
+    return CPM_OK;
+  };
+  std::vector<int> iters(nb, 0), cycles(nb, 0), kk(nb, 0), status(nb, CPM_ENOTCONV);
+  std::vector<double> bnorm(nb, 0.0), rel_true(nb, 1.0), rel_est(nb, 1.0);
+  std::vector<char> done(nb, 0), stopped(nb, 0);
+  auto finish = [&](int code) -> int {
+    hipEventRecord(t1, st);
+    hipEventSynchronize(t1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, t0, t1);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (info)
+      for (int r = 0; r < nb; ++r) {
+        info[r].iters = iters[r];
+        info[r].cycles = cycles[r];
+        info[r].status = status[r];
+        info[r].relres_true = rel_true[r];
+        info[r].relres_est = rel_est[r];
+        info[r].ms = ms;
+      }
+    return code;
+  };
+  // ||f_r||, with V_r[0] = f_r (x0 = 0) as the first residual
+  for (int r = 0; r < nb; ++r) {
+    k_copy<<<gv, 256, 0, st>>>(na, fr[r], Vp(r, 0));
+    k_fill<<<gv, 256, 0, st>>>(na, ur[r], 0.0);
+    k_dots<<<rb, RED_THREADS, 0, st>>>(na, Vp(r, 0), 0, 1, Vp(r, 0), PART(r), -1, nullptr);
+  }
+  {
+    const unsigned long long tk = ticket_for(m + 1);
+    for (int r = 0; r < nb; ++r)
+      k_norm_finish<<<1, RED_THREADS, 0, st>>>(PART(r), rb, L, SM(r), d.bslots_dev + r * bs.slot + (m + 1), tk);
+  }
+  for (int r = 0; r < nb; ++r) {
+    const double* hv = nullptr;
+    if ((rc = wait(r, m + 1, &hv)) != CPM_OK) return rc;
+    bnorm[r] = hv[S_BETA];
+    if (!std::isfinite(bnorm[r])) {
+      finish(CPM_EINVAL);
+      ctx->err = "solve: right-hand side is not finite";
+      return CPM_EINVAL;
+    }
+    if (bnorm[r] == 0.0) {
+      done[r] = 1;
+      status[r] = CPM_OK;
+      rel_true[r] = rel_est[r] = 0.0;
+    }
+  }
+  auto enqueue_iteration = [&](int k) {
+    double* scal_inv = d.bsmall + L.scal() + S_INV;
+    if (nb == 4)
+      launch_precond_multi<4>(ctx, Vp(0, k), bs.v, scal_inv, bs.small, Zp(0, k), bs.z);
+    else
+      launch_precond_multi<2>(ctx, Vp(0, k), bs.v, scal_inv, bs.small, Zp(0, k), bs.z);
+    launch_extend(ctx, Zp(0, k), d.bE, nb, bs.z, bs.e);
+    k_stencil_dots<<<dim3(rb, nb), RED_THREADS, 0, st>>>(na, diag, ih2, d.nbr, Zp(0, k), d.bE, Vp(0, k + 1), d.bV,
+                                                         ld, k + 1, d.bpart, k, scal_inv, bs);
+    k_reduce_cols<<<dim3(k + 1, nb), RED_THREADS, 0, st>>>(d.bpart, rb, d.bsmall + L.h1(), bs);
+    k_axpy_dots<<<dim3(rb, nb), RED_THREADS, 0, st>>>(na, d.bV, ld, k, d.bsmall + L.h1(), Vp(0, k + 1), d.bpart, 0,
+                                                      bs);
+    k_reduce_cols<<<dim3(k + 1, nb), RED_THREADS, 0, st>>>(d.bpart, rb, d.bsmall + L.h2(), bs);
+    k_axpy_dots<<<dim3(rb, nb), RED_THREADS, 0, st>>>(na, d.bV, ld, k, d.bsmall + L.h2(), Vp(0, k + 1), d.bpart, 1,
+                                                      bs);
+    k_arnoldi<<<dim3(1, nb), RED_THREADS, 0, st>>>(d.bpart, rb, k, L, d.bsmall, d.bslots_dev + k, ticket_for(k), bs);
+  };
+  for (;;) {
+    bool any = false;
+    for (int r = 0; r < nb; ++r) {
+      stopped[r] = done[r];
+      kk[r] = 0;
+      any |= !done[r];
+    }
+    if (!any) break;
+    enqueue_iteration(0);
+    for (int k = 0; k < m; ++k) {
+      // iteration k+1 is queued before iteration k is checked (as in a single solve)
+      bool more = false;
+      for (int r = 0; r < nb; ++r)
+        if (!stopped[r] && k + 1 < m && iters[r] + 1 < max_iter) more = true;
+      if (more) enqueue_iteration(k + 1);
+      bool all_stopped = true;
+      for (int r = 0; r < nb; ++r) {
+        if (stopped[r]) continue;
+        const double* hs = nullptr;
+        if ((rc = wait(r, k, &hs)) != CPM_OK) return rc;
+        ++iters[r];
+        kk[r] = k + 1;
+        rel_est[r] = hs[S_EST] / bnorm[r];
+        const bool more_r = k + 1 < m && iters[r] < max_iter;
+        if (!(hs[S_EST] > tol * bnorm[r]) || hs[S_HK1] == 0.0 || !more_r) stopped[r] = 1;
+        all_stopped &= (bool)stopped[r];
+      }
+      if (all_stopped || !more) break;
+    }
+    // cycle end: update, true residual and its norm for every right-hand side still running
+    for (int r = 0; r < nb; ++r) {
+      if (done[r]) continue;
+      k_backsolve<<<1, 64, 0, st>>>(kk[r], L, SM(r));
+      k_update_x<<<gv, 256, 0, st>>>(na, Zp(r, 0), ld, kk[r], SM(r) + L.y(), ur[r]);
+      launch_operator(ctx, ur[r], Vp(r, 0), fr[r]);
+      k_dots<<<rb, RED_THREADS, 0, st>>>(na, Vp(r, 0), 0, 1, Vp(r, 0), PART(r), -1, nullptr);
+    }
+    const unsigned long long tk = ticket_for(m + 1);
+    for (int r = 0; r < nb; ++r)
+      if (!done[r])
+        k_norm_finish<<<1, RED_THREADS, 0, st>>>(PART(r), rb, L, SM(r), d.bslots_dev + r * bs.slot + (m + 1), tk);
+    for (int r = 0; r < nb; ++r) {
+      if (done[r]) continue;
+      const double* hv = nullptr;
+      if ((rc = wait(r, m + 1, &hv)) != CPM_OK) return rc;
+      ++cycles[r];
+      rel_true[r] = hv[S_BETA] / bnorm[r];
+      if (rel_true[r] <= tol) {
+        status[r] = CPM_OK;
+        done[r] = 1;
+      } else if (iters[r] >= max_iter || !std::isfinite(rel_true[r])) {
+        done[r] = 1;
+      }
+    }
+  }
+  HIPCHK(hipGetLastError());
+  int worst = CPM_OK;
+  for (int r = 0; r < nb; ++r) worst = std::max(worst, status[r]);
+  return finish(worst);
 }
 
 // (O)RAS as a stationary solver: u <- u + M^{-1}(f - A u), u0 = 0. Each step

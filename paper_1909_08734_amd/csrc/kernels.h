@@ -41,8 +41,11 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
 template <int P>
 __global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
                                                 const double* __restrict__ wts,
-                                                const double* __restrict__ x, double* __restrict__ e) {
+                                                const double* __restrict__ x, double* __restrict__ e,
+                                                int64_t x_stride, int64_t e_stride) {
   constexpr int P1 = P + 1, NL = P1 * P1, NW = 3 * P1;
+  x += blockIdx.y * x_stride;  // right-hand side blockIdx.y of a batch
+  e += blockIdx.y * e_stride;
   static_assert(P1 <= 4, "two planes per lane");
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
   const int hl = threadIdx.x & 1;
@@ -258,6 +261,93 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
   }
   __syncthreads();
   for (int q = threadIdx.x; q < r_end - r_begin; q += PRECOND_THREADS) z[tilde_idx[d.t_off + r_begin + q]] = ps[q];
+}
+
+// Several right-hand sides per pass over W: v_q|Sigma_j (q < NB) staged in LDS
+// one after the other (each read like the single apply's, without extra bank
+// conflicts), each W element multiplied by all of them. For every
+// right-hand side the sums are formed in the order of k_precond, so a batched
+// apply equals NB single applies bit for bit.
+template <typename T, int NB>
+__global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_multi(const SubDesc* __restrict__ desc,
+                                                                   const int32_t* __restrict__ blk_sub,
+                                                                   const int32_t* __restrict__ sig_idx,
+                                                                   const int32_t* __restrict__ tilde_idx,
+                                                                   const T* __restrict__ W,
+                                                                   const double* __restrict__ v, int64_t v_stride,
+                                                                   const double* __restrict__ scale,
+                                                                   int64_t scale_stride, double* __restrict__ z,
+                                                                   int64_t z_stride) {
+  extern __shared__ double vs[];  // vs[q * ldw + c]
+  typedef typename VecOf<T>::type VT;
+  constexpr int VN = VecOf<T>::n;
+  constexpr int PRECOND_UNROLL = VecOf<T>::unroll;
+  constexpr int NWAVE = PRECOND_THREADS / 64;
+  const int blk = blockIdx.x;
+  const int j = blk_sub[blk];
+  const SubDesc d = desc[j];
+  double sc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) sc[q] = scale ? scale[q * scale_stride] : 1.0;
+  for (int c = threadIdx.x; c < d.ldw; c += PRECOND_THREADS) {
+    const int32_t g = c < d.m ? sig_idx[d.u_off + c] : 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) vs[q * d.ldw + c] = c < d.m ? sc[q] * v[q * v_stride + g] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r_begin = (blk - d.blk_off) * d.rpb;
+  const int r_end = min(r_begin + d.rpb, d.t);
+  for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += NWAVE * PRECOND_RPW) {
+    const T* wr[PRECOND_RPW];
+    double acc[PRECOND_RPW][NB];
+#pragma unroll
+    for (int i = 0; i < PRECOND_RPW; ++i) {
+      wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc[i][q] = 0.0;
+    }
+    int c = lane * VN;
+    for (; c + (PRECOND_UNROLL - 1) * 64 * VN < d.ldw; c += PRECOND_UNROLL * 64 * VN) {
+      VT wv[PRECOND_UNROLL][PRECOND_RPW];
+#pragma unroll
+      for (int u = 0; u < PRECOND_UNROLL; ++u)
+#pragma unroll
+        for (int i = 0; i < PRECOND_RPW; ++i)
+          wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c + u * 64 * VN));
+#pragma unroll
+      for (int u = 0; u < PRECOND_UNROLL; ++u)
+#pragma unroll
+        for (int e = 0; e < VN; ++e)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            const double xv = vs[q * d.ldw + c + u * 64 * VN + e];
+#pragma unroll
+            for (int i = 0; i < PRECOND_RPW; ++i) acc[i][q] += (double)wv[u][i][e] * xv;
+          }
+    }
+    for (; c < d.ldw; c += 64 * VN) {
+      VT wv[PRECOND_RPW];
+#pragma unroll
+      for (int i = 0; i < PRECOND_RPW; ++i)
+        wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
+#pragma unroll
+      for (int e = 0; e < VN; ++e)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const double xv = vs[q * d.ldw + c + e];
+#pragma unroll
+          for (int i = 0; i < PRECOND_RPW; ++i) acc[i][q] += (double)wv[i][e] * xv;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PRECOND_RPW; ++i)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double s = wave_sum(acc[i][q]);
+        if (lane == 0 && r0 + i < r_end) z[q * z_stride + tilde_idx[d.t_off + r0 + i]] = s;
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -683,6 +773,17 @@ __global__ __launch_bounds__(256) void k_extract_w(const SubDesc* __restrict__ d
 // owns one row and keeps that row of the basis in registers, so the fused
 // "w -= V h, then V^T w" pass reads V once.
 // ---------------------------------------------------------------------------
+// Per-right-hand-side strides of the batched Krylov kernels (blockIdx.y = the
+// right-hand side; all zero with a one-row grid for a single solve).
+struct BatchStrides {
+  int64_t v = 0;      // basis V (and w, a column of it)
+  int64_t z = 0;      // preconditioned basis Z
+  int64_t e = 0;      // extension scratch
+  int64_t part = 0;   // partial sums
+  int64_t small = 0;  // small buffer (H, rotations, scalars)
+  int64_t slot = 0;   // host slots
+};
+
 constexpr int RED_THREADS = 256;
 constexpr int MAX_BASIS = 64;       // restart length limit (columns of V per pass)
 constexpr int RED_MAX_BLOCKS = 4096;
@@ -833,9 +934,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_stencil_dots(int64_t n, double 
                                                               const double* __restrict__ e, double* __restrict__ w,
                                                               double* __restrict__ X, int64_t ldx, int ncols,
                                                               double* __restrict__ part, int scale_col,
-                                                              const double* __restrict__ scale) {
+                                                              const double* __restrict__ scale, BatchStrides bs) {
   constexpr int NC = 32;
-  const double sc = scale_col >= 0 ? *scale : 1.0;
+  const int64_t b = blockIdx.y;  // right-hand side of a batch
+  z += b * bs.z;
+  e += b * bs.e;
+  w += b * bs.v;
+  X += b * bs.v;
+  part += b * bs.part;
+  const double sc = scale_col >= 0 ? scale[b * bs.small] : 1.0;
   for (int j0 = 0; j0 < ncols; j0 += NC) {
     const int nc = min(NC, ncols - j0);
     double acc[NC];
@@ -870,8 +977,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_stencil_dots(int64_t n, double 
 // w -= V[0..k] h (h: k+1 values), then part = V^T w (mode 0) or ||w||^2 (mode 1).
 __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const double* __restrict__ V, int64_t ld, int k,
                                                            const double* __restrict__ h, double* __restrict__ w,
-                                                           double* __restrict__ part, int mode) {
+                                                           double* __restrict__ part, int mode, BatchStrides bs) {
   constexpr int NC = 32;
+  const int64_t b = blockIdx.y;  // right-hand side of a batch
+  V += b * bs.v;
+  w += b * bs.v;
+  h += b * bs.small;
+  part += b * bs.part;
   __shared__ double hs[MAX_BASIS];
   for (int q = threadIdx.x; q <= k; q += RED_THREADS) hs[q] = h[q];
   __syncthreads();
@@ -944,7 +1056,9 @@ __device__ __forceinline__ double column_total(const double* __restrict__ part, 
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_cols(const double* __restrict__ part, int nblocks,
-                                                             double* __restrict__ out) {
+                                                             double* __restrict__ out, BatchStrides bs) {
+  part += blockIdx.y * bs.part;  // right-hand side of a batch
+  out += blockIdx.y * bs.small;
   const double t = column_total(part, nblocks, blockIdx.x);
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
@@ -970,8 +1084,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_norm_finish(const double* __res
 // LDS so that the serial rotation sweep does not wait on device memory.
 __global__ __launch_bounds__(RED_THREADS) void k_arnoldi(const double* __restrict__ part, int nblocks, int k,
                                                          SmallLayout L, double* __restrict__ sm, HostSlot* slot,
-                                                         unsigned long long ticket) {
+                                                         unsigned long long ticket, BatchStrides bs) {
   __shared__ double hc[MAX_BASIS + 2], csl[MAX_BASIS], snl[MAX_BASIS];
+  part += blockIdx.y * bs.part;  // right-hand side of a batch
+  sm += blockIdx.y * bs.small;
+  if (slot) slot += blockIdx.y * bs.slot;
   const double tot = column_total(part, nblocks, 0);
   const int ldh = L.m + 1;
   double* H = sm + L.H() + (int64_t)k * ldh;
