@@ -14,11 +14,13 @@ precisions are measured: `value` is the plain FP64 form, the FP32-factor form
 
 A serving leg follows (`serving` in the output): a request loop over a mix of
 surfaces (unit sphere, torus R = 1, r = 0.4, bumpy icosphere with 20480
-triangles) and grid spacings h in {0.05, 0.025}, Poisson arrivals at 80% of the
-solve capacity with cached factors measured just before, c log-normal on [0.1, 10] quantised to 16
-levels, 1-32 implicit steps per request, cached FP32 factors, admission by
-device-memory footprint; it reports p50/p99 latency (arrival to last step) and
-solves/s.
+triangles) and grid spacings h in {0.05, 0.025}, c log-normal on [0.1, 10]
+quantised to 16 levels, 1-32 implicit steps per request, cached FP32 factors,
+admission by device-memory footprint, Poisson arrivals at 80% of the capacity
+for the stream (its steps at the cached-factor rate plus one factorisation per
+new key, both measured just before); it reports p50/p99 latency (arrival to
+last step) and solves/s. The same K right-hand sides are also solved in
+lockstep batches (`batched`), which share each pass over the factors.
 
 Prints one JSON line.
 """
@@ -322,8 +324,8 @@ def serve_surfaces():
 
 def run_serving(n_requests):
     """Serving leg: prepare the host set-up of every (surface, h), calibrate the
-    solve capacity with one cached factorisation per (surface, h), then serve
-    Poisson arrivals at 80% of it."""
+    step and factorisation costs with one factorisation per (surface, h), then
+    serve Poisson arrivals at 80% of the stream's capacity."""
     import torch
     import paper_1909_08734_amd as P
     from paper_1909_08734_amd import serve
@@ -341,12 +343,19 @@ def run_serving(n_requests):
     calib = [serve.Request(rid=q, surface=n, h=h, c=1.0, nsteps=2, seed=100 + q, arrival=0.0)
              for q, (n, h) in enumerate(pairs)]
     srv.run(calib, realtime=False)
+    first = srv.makespan
     srv.run(calib, realtime=False)
     mean_step = srv.makespan / (2 * len(calib))  # device time per step with all slots busy
-    mean_service = mean_step * 16.5  # mean of 1..32 steps
-    rate = 0.8 / mean_service
+    t_factor = max(first - srv.makespan, 0.0) / len(calib)  # device time per factorisation
+    # arrivals at 80% of the capacity for this request stream: its steps at the
+    # cached-factor rate plus one factorisation per distinct (surface, h, c level)
+    probe = serve.poisson_requests(n_requests, 1.0, names, list(SERVE_HS), seed=6)
+    keys = {srv.key(r) for r in probe} - {srv.key(r) for r in calib}
+    busy = sum(r.nsteps for r in probe) * mean_step + len(keys) * t_factor
+    rate = 0.8 * n_requests / busy
     reqs = serve.poisson_requests(n_requests, rate, names, list(SERVE_HS), seed=6)
-    log(f"serving: step {mean_step * 1e3:.1f} ms mean -> rate {rate:.2f}/s, {n_requests} requests")
+    log(f"serving: step {mean_step * 1e3:.1f} ms, factorisation {t_factor:.2f} s, {len(keys)} new keys "
+        f"-> rate {rate:.2f}/s, {n_requests} requests")
     torch.cuda.synchronize()
     out = srv.run(reqs, realtime=True)
     st = serve.summary(out, srv.makespan)
@@ -356,6 +365,7 @@ def run_serving(n_requests):
         "factors": "fp32 (fp64 krylov)", "budget_GB": srv.budget / 1e9, "peak_reserved_GB": srv.peak_used / 1e9,
         "evictions": srv.evictions, "factorisations": srv.n_factor - len(calib),
         "factor_s_total": srv.factor_s, "calibration_step_ms": mean_step * 1e3,
+        "calibration_factor_s": t_factor, "load": 0.8,
         "failed": int(sum(1 for r in out if r.status != P.OK)),
     })
     srv.close()
