@@ -62,6 +62,9 @@ _SIGS = {
     "cpm_factor_groups": (C.c_int, [C.c_void_p]),
     "cpm_set_precond_chunk": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_precond_chunk": (C.c_int, [C.c_void_p]),
+    "cpm_set_precond_tiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_precond_tiling": (C.c_int, [C.c_void_p]),
+    "cpm_autotune_precond": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "cpm_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int,
                             C.POINTER(SolveInfo)]),
     "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
@@ -231,6 +234,20 @@ class Context:
 
     def precond_chunk(self):
         return int(self._L.cpm_precond_chunk(self._h))
+
+    def set_precond_tiling(self, tiling):
+        self._check(self._L.cpm_set_precond_tiling(self._h, int(tiling)), "set_precond_tiling")
+
+    def precond_tiling(self):
+        return int(self._L.cpm_precond_tiling(self._h))
+
+    def autotune_precond(self, reps=3):
+        """Time the apply tilings on the resident factors and keep the fastest.
+        Returns (best tiling, [ms per tiling])."""
+        best = C.c_int()
+        ms = (C.c_double * 6)()
+        self._check(self._L.cpm_autotune_precond(self._h, int(reps), C.byref(best), ms), "autotune_precond")
+        return best.value, list(ms)
 
     def solve(self, f, tol=1e-8, max_iter=1000, restart=30):
         """Host arrays: f (N_A,) or (nrhs, N_A). Returns (u, [info dicts])."""

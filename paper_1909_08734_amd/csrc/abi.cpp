@@ -379,6 +379,21 @@ int cpm_set_precond_chunk(cpm_ctx* ctx, int columns) {
 
 int cpm_precond_chunk(const cpm_ctx* ctx) { return ctx ? ctx->dev.chunk : 0; }
 
+int cpm_set_precond_tiling(cpm_ctx* ctx, int tiling) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "set_precond_tiling: factor first");
+  return guarded(ctx, [&]() -> int { return cpm::dev_set_tiling(ctx, tiling); });
+}
+
+int cpm_precond_tiling(const cpm_ctx* ctx) { return ctx ? ctx->dev.tiling : 0; }
+
+int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "autotune_precond: factor first");
+  if (reps < 1) return fail(ctx, CPM_EINVAL, "autotune_precond: reps must be >= 1");
+  return guarded(ctx, [&]() -> int { return cpm::dev_autotune(ctx, reps, best, ms); });
+}
+
 int cpm_set_timing(cpm_ctx* ctx, int on) {
   if (!ctx) return CPM_EINVAL;
   if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "set_timing: host-only context");

@@ -98,6 +98,8 @@ struct Dev {
   int max_m = 0;
   int n_groups = 0;             // subdomain groups of the last factorisation
   int chunk = 0;                // 0: v|Sigma_j staged whole; else columns per pass (chunked apply)
+  int tiling = 0;               // tiling of the unchunked apply (see dev_set_tiling)
+  std::vector<SubDesc> hdesc;   // host copy of the apply descriptors
   int chunk_req = 0;            // requested chunk (0: only when v|Sigma_j exceeds LDS)
   size_t ws_limit = size_t(64) << 30;  // factor workspace per group, bytes
   size_t w_bytes = 0;
@@ -153,6 +155,8 @@ int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max
 int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol, int max_iter, int restart,
                     cpm_solve_info* info);
 int dev_batch_width(cpm_ctx* ctx, int nrhs);
+int dev_set_tiling(cpm_ctx* ctx, int t);
+int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms);
 int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double scale, double tol, int max_iter,
                     int restart, cpm_solve_info* info);
 int dev_export_w(cpm_ctx* ctx, int j, double* w);

@@ -175,6 +175,41 @@ static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const doub
          (const double*)d.e, f, y);
 }
 
+// Tilings of the single-right-hand-side apply (rows per wave, 16-byte chunks
+// in flight per row); index 0 is the default. All give identical results.
+constexpr int N_TILINGS = 6;
+constexpr int kTilingRpw[N_TILINGS] = {2, 1, 4, 2, 1, 4};
+constexpr int kTilingUnr[N_TILINGS] = {2, 2, 2, 1, 1, 1};
+
+template <typename T>
+static const void* tiled_fn(int t) {
+  switch (t) {
+    case 1: return (const void*)k_precond<T, 1, 2>;
+    case 2: return (const void*)k_precond<T, 4, 2>;
+    case 3: return (const void*)k_precond<T, 2, 1>;
+    case 4: return (const void*)k_precond<T, 1, 1>;
+    case 5: return (const void*)k_precond<T, 4, 1>;
+    default: return (const void*)k_precond<T, 2, 2>;
+  }
+}
+
+template <typename T>
+static void launch_tiled(cpm_ctx* ctx, int t, size_t lds, const double* v, const double* scale, double* z) {
+  Dev& d = ctx->dev;
+  const dim3 g(d.n_blocks), b(PRECOND_THREADS);
+  const SubDesc* desc = d.desc;
+  const int32_t *bs = d.blk_sub, *si = d.sig_idx, *ti = d.tilde_idx;
+  const T* W = (const T*)d.W;
+  switch (t) {
+    case 1: launch(ctx, TIMER_PRECOND, k_precond<T, 1, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 2: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 3: launch(ctx, TIMER_PRECOND, k_precond<T, 2, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 4: launch(ctx, TIMER_PRECOND, k_precond<T, 1, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 5: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    default: launch(ctx, TIMER_PRECOND, k_precond<T, 2, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+  }
+}
+
 // z = scale * M^{-1} v (scale: device scalar or nullptr for 1)
 static void launch_precond(cpm_ctx* ctx, const double* v, double* z, const double* scale = nullptr) {
   Dev& d = ctx->dev;
@@ -192,13 +227,9 @@ static void launch_precond(cpm_ctx* ctx, const double* v, double* z, const doubl
   }
   const size_t lds = (size_t)d.max_m * sizeof(double);
   if (d.prec == CPM_FP64)
-    launch(ctx, TIMER_PRECOND, k_precond<double>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
-           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
-           (const int32_t*)d.tilde_idx, (const double*)d.W, v, scale, z);
+    launch_tiled<double>(ctx, d.tiling, lds, v, scale, z);
   else
-    launch(ctx, TIMER_PRECOND, k_precond<float>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
-           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
-           (const int32_t*)d.tilde_idx, (const float*)d.W, v, scale, z);
+    launch_tiled<float>(ctx, d.tiling, lds, v, scale, z);
 }
 
 int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y) {
@@ -564,6 +595,8 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     }
   cleanup();
   dv.desc = ddesc;
+  dv.hdesc = P.desc;
+  dv.tiling = 0;
   dv.sig_idx = dU;
   dv.tilde_idx = dtidx;
   dv.blk_sub = dblk;
@@ -1191,6 +1224,94 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
                       (size_t)D.n_sub * (4 + 8);
   if (resident) *resident = res;
   if (peak) *peak = res + work;
+}
+
+// Apply plan for tiling t: the resident block slots for its occupancy
+// apportioned to subdomains as at factor time; the descriptors' block fields
+// and the block -> subdomain table are rewritten on the device.
+int dev_set_tiling(cpm_ctx* ctx, int t) {
+  Dev& dv = ctx->dev;
+  if (t < 0 || t >= N_TILINGS) {
+    ctx->err = "precond tiling out of range";
+    return CPM_EINVAL;
+  }
+  if (dv.prec < 0 || dv.chunk > 0) {
+    ctx->err = "precond tiling: needs a factorisation with the unchunked apply";
+    return CPM_ESTATE;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t lds = (size_t)dv.max_m * sizeof(double);
+  const void* fn = dv.prec == CPM_FP64 ? tiled_fn<double>(t) : tiled_fn<float>(t);
+  if (lds > 64 * 1024) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int n_cu = 0, per_cu = 0;
+  HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PRECOND_THREADS, lds));
+  per_cu = std::max(1, per_cu);
+  const std::vector<int> want = apportion_blocks(ctx->dec, n_cu * per_cu);
+  std::vector<int32_t> blk_sub;
+  int32_t blk = 0;
+  for (int j = 0; j < ctx->dec.n_sub; ++j) {
+    SubDesc& d = dv.hdesc[j];
+    d.rpb = std::max(1, (d.t + want[j] - 1) / want[j]);
+    const int nb = (d.t + d.rpb - 1) / d.rpb;
+    d.blk_off = blk;
+    for (int q = 0; q < nb; ++q) blk_sub.push_back(j);
+    blk += nb;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(dv.desc, dv.hdesc.data(), dv.hdesc.size() * sizeof(SubDesc), hipMemcpyHostToDevice));
+  dfree(dv.blk_sub);
+  int rc = upload(ctx, &dv.blk_sub, blk_sub);
+  if (rc != CPM_OK) return rc;
+  dv.n_blocks = blk;
+  dv.tiling = t;
+  return CPM_OK;
+}
+
+// Time every tiling on the resident factors (one warm-up and `reps` applies
+// each, HIP events on the context stream) and keep the fastest.
+int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms) {
+  Dev& dv = ctx->dev;
+  if (dv.prec < 0 || dv.chunk > 0) {
+    ctx->err = "autotune: needs a factorisation with the unchunked apply";
+    return CPM_ESTATE;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t na = ctx->band.n_act;
+  double *v = nullptr, *z = nullptr;
+  HIPCHK(hipMalloc((void**)&v, na * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&z, na * sizeof(double)));
+  k_fill<<<nblk(na, 256), 256, 0, ctx->stream>>>(na, v, 1.0);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = CPM_OK, arg = 0;
+  double tbest = 0.0;
+  for (int t = 0; t < N_TILINGS && rc == CPM_OK; ++t) {
+    rc = dev_set_tiling(ctx, t);
+    if (rc != CPM_OK) break;
+    launch_precond(ctx, v, z);
+    hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps; ++r) launch_precond(ctx, v, z);
+    hipEventRecord(e1, ctx->stream);
+    hipEventSynchronize(e1);
+    float el = 0.f;
+    hipEventElapsedTime(&el, e0, e1);
+    const double per = (double)el / reps;
+    if (ms) ms[t] = per;
+    if (t == 0 || per < tbest) {
+      tbest = per;
+      arg = t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamSynchronize(ctx->stream);
+  dfree(v);
+  dfree(z);
+  if (rc != CPM_OK) return rc;
+  if (best) *best = arg;
+  return dev_set_tiling(ctx, arg);
 }
 
 // Implicit steps with resident factors: u_0 = A^{-1} f, u_k = A^{-1}(scale u_{k-1}).

@@ -129,8 +129,10 @@ constexpr int PRECOND_RPW = 2;        // rows a wave streams at once
 
 // Block b serves rows [(b - blk_off) rpb, ...) of subdomain blk_sub[b]; the
 // host sizes rpb so that every block streams about the same number of bytes
-// and all blocks are resident at once (no partial last round).
-template <typename T>
+// and all blocks are resident at once (no partial last round). RPW rows per
+// wave and UNR 16-byte chunks in flight per row are the tunable tiling; every
+// tiling forms each row's sum in the same order (bit-identical results).
+template <typename T, int RPW = PRECOND_RPW, int UNR = VecOf<T>::unroll>
 __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* __restrict__ desc,
                                                              const int32_t* __restrict__ blk_sub,
                                                              const int32_t* __restrict__ sig_idx,
@@ -142,7 +144,6 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* _
   extern __shared__ double vs[];
   typedef typename VecOf<T>::type VT;
   constexpr int VN = VecOf<T>::n;
-  constexpr int PRECOND_UNROLL = VecOf<T>::unroll;
   constexpr int NWAVE = PRECOND_THREADS / 64;
   const int blk = blockIdx.x;
   const int j = blk_sub[blk];
@@ -153,45 +154,45 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* _
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = (blk - d.blk_off) * d.rpb;
   const int r_end = min(r_begin + d.rpb, d.t);
-  for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += NWAVE * PRECOND_RPW) {
-    const T* wr[PRECOND_RPW];
-    double acc[PRECOND_RPW];
+  for (int r0 = r_begin + wave * RPW; r0 < r_end; r0 += NWAVE * RPW) {
+    const T* wr[RPW];
+    double acc[RPW];
 #pragma unroll
-    for (int i = 0; i < PRECOND_RPW; ++i) {
+    for (int i = 0; i < RPW; ++i) {
       wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw;
       acc[i] = 0.0;
     }
     int c = lane * VN;
-    for (; c + (PRECOND_UNROLL - 1) * 64 * VN < d.ldw; c += PRECOND_UNROLL * 64 * VN) {
-      VT wv[PRECOND_UNROLL][PRECOND_RPW];
+    for (; c + (UNR - 1) * 64 * VN < d.ldw; c += UNR * 64 * VN) {
+      VT wv[UNR][RPW];
 #pragma unroll
-      for (int u = 0; u < PRECOND_UNROLL; ++u)
+      for (int u = 0; u < UNR; ++u)
 #pragma unroll
-        for (int i = 0; i < PRECOND_RPW; ++i)
+        for (int i = 0; i < RPW; ++i)
           wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c + u * 64 * VN));
 #pragma unroll
-      for (int u = 0; u < PRECOND_UNROLL; ++u)
+      for (int u = 0; u < UNR; ++u)
 #pragma unroll
         for (int e = 0; e < VN; ++e) {
           const double xv = vs[c + u * 64 * VN + e];
 #pragma unroll
-          for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[u][i][e] * xv;
+          for (int i = 0; i < RPW; ++i) acc[i] += (double)wv[u][i][e] * xv;
         }
     }
     for (; c < d.ldw; c += 64 * VN) {
-      VT wv[PRECOND_RPW];
+      VT wv[RPW];
 #pragma unroll
-      for (int i = 0; i < PRECOND_RPW; ++i)
+      for (int i = 0; i < RPW; ++i)
         wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
 #pragma unroll
       for (int e = 0; e < VN; ++e) {
         const double xv = vs[c + e];
 #pragma unroll
-        for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[i][e] * xv;
+        for (int i = 0; i < RPW; ++i) acc[i] += (double)wv[i][e] * xv;
       }
     }
 #pragma unroll
-    for (int i = 0; i < PRECOND_RPW; ++i) {
+    for (int i = 0; i < RPW; ++i) {
       const double s = wave_sum(acc[i]);
       if (lane == 0 && r0 + i < r_end) z[tilde_idx[d.t_off + r0 + i]] = s;
     }

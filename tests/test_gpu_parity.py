@@ -354,3 +354,35 @@ def test_one_large_subdomain_uses_chunked_apply_and_is_a_direct_solve():
     assert rc == P.OK and info[0]["iters"] <= 2, info
     assert np.linalg.norm(f - A @ u) / np.linalg.norm(f) <= 1.05e-10
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
+def test_precond_tilings_are_identical_and_autotune_keeps_results(prec):
+    """Every tiling of the apply gives the same bits; the autotuner picks one
+    of them and the solve is unchanged."""
+    b, dec, ctx = _setup("sphere", 3, "rcb", 7, 2, "ORAS", 3.16, 0.0)
+    ctx.factor(prec)
+    na = b.n_act
+    v = dev(np.random.default_rng(9).standard_normal(na))
+    ref = None
+    for t in range(6):
+        ctx.set_precond_tiling(t)
+        assert ctx.precond_tiling() == t
+        z = torch.zeros(na, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(v, z)
+        if ref is None:
+            ref = z.cpu().numpy()
+        else:
+            np.testing.assert_array_equal(z.cpu().numpy(), ref)
+    with pytest.raises(P.CpmError):
+        ctx.set_precond_tiling(6)
+    f = ci.rhs_sphere_y20(b.cp[: b.n_act], 1.0)
+    ctx.set_precond_tiling(0)
+    u0, i0, _ = ctx.solve(f, tol=1e-10, max_iter=300)
+    best, ms = ctx.autotune_precond(reps=2)
+    say("tiling times (ms)", ms, "best", best)
+    assert 0 <= best < 6 and ctx.precond_tiling() == best and all(x > 0 for x in ms)
+    u1, i1, _ = ctx.solve(f, tol=1e-10, max_iter=300)
+    np.testing.assert_array_equal(u1, u0)
+    assert i1[0]["iters"] == i0[0]["iters"]
+    ctx.close()
