@@ -175,6 +175,17 @@ int cpm_precond_tiling(const cpm_ctx* ctx);
 int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms);
 
 /*
+ * FGMRES iterations as HIP graphs (off by default): each iteration's kernels
+ * for a given position k in the restart cycle are captured once and replayed;
+ * the graphs are dropped whenever the factors, the operator, the Krylov space
+ * or the apply plan change. Results are the same either way (replaying costs
+ * a few microseconds more per iteration than direct launches on ROCm 7, hence
+ * the default). Not used while per-kernel timing is on, nor for batches of
+ * right-hand sides.
+ */
+int cpm_set_graphs(cpm_ctx* ctx, int on);
+
+/*
  * Local operators A_j (eq. localOP) assembled on the device and factored by
  * batched dense LU with partial pivoting (Section 5) in `prec`; the factors
  * are reduced to the restricted local solution operators

@@ -65,6 +65,7 @@ _SIGS = {
     "cpm_set_precond_tiling": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_precond_tiling": (C.c_int, [C.c_void_p]),
     "cpm_autotune_precond": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "cpm_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int,
                             C.POINTER(SolveInfo)]),
     "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
@@ -240,6 +241,10 @@ class Context:
 
     def precond_tiling(self):
         return int(self._L.cpm_precond_tiling(self._h))
+
+    def set_graphs(self, on=True):
+        """Replay captured FGMRES iterations (HIP graphs) or launch kernels one by one."""
+        self._check(self._L.cpm_set_graphs(self._h, 1 if on else 0), "set_graphs")
 
     def autotune_precond(self, reps=3):
         """Time the apply tilings on the resident factors and keep the fastest.

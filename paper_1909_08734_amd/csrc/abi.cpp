@@ -387,6 +387,13 @@ int cpm_set_precond_tiling(cpm_ctx* ctx, int tiling) {
 
 int cpm_precond_tiling(const cpm_ctx* ctx) { return ctx ? ctx->dev.tiling : 0; }
 
+int cpm_set_graphs(cpm_ctx* ctx, int on) {
+  if (!ctx) return CPM_EINVAL;
+  ctx->dev.use_graphs = on != 0;
+  if (!ctx->host_only) cpm::drop_graphs(ctx->dev);
+  return CPM_OK;
+}
+
 int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms) {
   if (!ctx) return CPM_EINVAL;
   if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "autotune_precond: factor first");

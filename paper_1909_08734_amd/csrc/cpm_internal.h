@@ -125,6 +125,9 @@ struct Dev {
   struct HostSlot* bslots = nullptr;      // b_n x (restart+2), host view
   struct HostSlot* bslots_dev = nullptr;  // device view
   size_t batch_bytes = 0;
+  // FGMRES iteration k captured as HIP graph k (single right-hand side)
+  bool use_graphs = false;
+  std::vector<hipGraphExec_t> graphs;
   size_t op_bytes = 0;
 };
 
@@ -156,6 +159,7 @@ int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol
                     cpm_solve_info* info);
 int dev_batch_width(cpm_ctx* ctx, int nrhs);
 int dev_set_tiling(cpm_ctx* ctx, int t);
+void drop_graphs(Dev& d);
 int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms);
 int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double scale, double tol, int max_iter,
                     int restart, cpm_solve_info* info);

@@ -82,9 +82,18 @@ void timer_harvest(cpm_ctx* ctx) {
   t.used = 0;
 }
 
+// Captured iterations hold the device addresses and launch shapes of the
+// moment they were captured: drop them whenever any of those change.
+void drop_graphs(Dev& d) {
+  for (hipGraphExec_t g : d.graphs)
+    if (g) hipGraphExecDestroy(g);
+  d.graphs.clear();
+}
+
 void dev_free_factor(cpm_ctx* ctx) {
   Dev& d = ctx->dev;
   hipStreamSynchronize(ctx->stream);
+  drop_graphs(d);
   dfree(d.desc);
   dfree(d.blk_sub);
   dfree(d.sig_idx);
@@ -97,6 +106,7 @@ void dev_free_factor(cpm_ctx* ctx) {
 
 static void free_krylov(cpm_ctx* ctx) {
   Dev& d = ctx->dev;
+  drop_graphs(d);
   dfree(d.V);
   dfree(d.Z);
   dfree(d.F);
@@ -134,6 +144,7 @@ int dev_upload_operator(cpm_ctx* ctx) {
   HIPCHK(hipSetDevice(ctx->device));
   const Band& b = ctx->band;
   Dev& d = ctx->dev;
+  drop_graphs(d);
   int rc;
   if ((rc = upload(ctx, &d.lines, b.lines)) != CPM_OK) return rc;
   if ((rc = upload(ctx, &d.wts, b.wts)) != CPM_OK) return rc;
@@ -789,7 +800,7 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   int iters = 0, cycles = 0;
   double rel_true = 1.0, rel_est = 1.0;
   int status = CPM_ENOTCONV;
-  auto enqueue_iteration = [&](int k) -> int {
+  auto kernels_of_iteration = [&](int k, unsigned long long ticket) {
     double* vk = d.V + (size_t)k * d.ld;
     double* w = d.V + (size_t)(k + 1) * d.ld;
     double* zk = d.Z + (size_t)k * d.ld;
@@ -804,7 +815,34 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
     k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0, one);
     k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h2(), one);
     k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h2(), w, d.part, 1, one);
-    k_arnoldi<<<1, RED_THREADS, 0, st>>>(d.part, rb, k, L, sm, slots_dev + k, ticket_for(k), one);
+    k_arnoldi<<<1, RED_THREADS, 0, st>>>(d.part, rb, k, L, sm, slots_dev + k, ticket, one);
+  };
+  // With graphs, iteration k is captured once (ticket 1 baked in) and replayed;
+  // the host clears slot k's ticket before each replay, which is safe because
+  // the slot's previous write finished before the host's last wait in this
+  // stream order.
+  const bool graphs = d.use_graphs && !ctx->timer.on;
+  if (graphs && (int)d.graphs.size() != m) {
+    drop_graphs(d);
+    d.graphs.assign(m, nullptr);
+  }
+  auto enqueue_iteration = [&](int k) -> int {
+    if (!graphs) {
+      kernels_of_iteration(k, ticket_for(k));
+      return CPM_OK;
+    }
+    if (!d.graphs[k]) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      kernels_of_iteration(k, 1);
+      HIPCHK(hipStreamEndCapture(st, &g));
+      const hipError_t e = hipGraphInstantiate(&d.graphs[k], g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(e);
+    }
+    *(volatile unsigned long long*)&slots[k].ticket = 0;
+    expect[k] = 1;
+    HIPCHK(hipGraphLaunch(d.graphs[k], st));
     return CPM_OK;
   };
   for (;;) {
@@ -1259,6 +1297,7 @@ int dev_set_tiling(cpm_ctx* ctx, int t) {
     blk += nb;
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  drop_graphs(dv);
   HIPCHK(hipMemcpy(dv.desc, dv.hdesc.data(), dv.hdesc.size() * sizeof(SubDesc), hipMemcpyHostToDevice));
   dfree(dv.blk_sub);
   int rc = upload(ctx, &dv.blk_sub, blk_sub);

@@ -386,3 +386,35 @@ def test_precond_tilings_are_identical_and_autotune_keeps_results(prec):
     np.testing.assert_array_equal(u1, u0)
     assert i1[0]["iters"] == i0[0]["iters"]
     ctx.close()
+
+
+def test_graph_replayed_iterations_equal_eager_launches():
+    """FGMRES iterations captured as HIP graphs and replayed give the eager
+    results bit for bit, replay after replay, with eager work in between, after
+    a restart-length change and after a new factorisation."""
+    b, dec, ctx = _setup("sphere", 3, "rcb", 7, 2, "ORAS", 3.16, 10.0)
+    na = b.n_act
+    F = [ci.rhs_sphere_random_sh(b.cp[:na], 1.0, seed=40 + q)[0] for q in range(2)]
+
+    def run(f, restart):
+        fd = dev(f)
+        u = torch.zeros(na, dtype=torch.float64, device="cuda")
+        info, rc = ctx.solve_device(fd, u, tol=1e-10, max_iter=400, restart=restart)
+        return u.cpu().numpy(), info[0]["iters"]
+
+    for prec in (P.FP64, P.FP32):
+        ctx.factor(prec)
+        ctx.set_graphs(False)
+        eager = {(q, m): run(F[q], m) for q in range(2) for m in (30, 5)}
+        ctx.set_graphs(True)
+        for rep in range(3):
+            for (q, m), (u_e, it_e) in eager.items():
+                u_g, it_g = run(F[q], m)
+                np.testing.assert_array_equal(u_g, u_e)
+                assert it_g == it_e
+            # eager work between replays
+            z = torch.zeros(na, dtype=torch.float64, device="cuda")
+            ctx.apply_precond(dev(F[0]), z)
+            ctx.apply_operator(z, z.clone())
+            torch.cuda.synchronize()
+    ctx.close()
