@@ -139,15 +139,18 @@ def lu_flops(ctx, n_sub, kind_oras, nb=32, kmax=128):
     return tot
 
 
-def pmc_traffic(kind, source_hash):
+def pmc_traffic(kind, source_hash, tiling):
+    """HBM bytes per apply launch of the given tiling from the committed
+    counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"precond_{kind}_sphere_h0025_rcb64_pmc.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or tiling is None:
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != source_hash:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    by = rec.get("hbm_bytes_per_launch_by_tiling") or []
+    return by[tiling] if tiling < len(by) else None
 
 
 def operator_roofline(ctx, torch, P, na, ng, reps=50, degree=3):
@@ -481,12 +484,13 @@ def main():
         "operator_apply": op,
         "roofline": {
             "kernel": "k_precond<double> (restricted local solves, eq. algRAS)",
+            "tiling": r64["precond_tiling"],
             "bound": "hbm",
             "achieved": r64["precond_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r64["precond_GBs"] / HBM_PEAK_GBS,
-            "traffic": pmc_traffic("fp64", src) if default and r64["precond_tiling"] == 0 else None,
+            "traffic": pmc_traffic("fp64", src, r64["precond_tiling"]) if default else None,
             "algorithmic_bytes_per_launch": r64["precond_bytes"],
             "avg_launch_ms": r64["precond_ms_avg"],
             "kernel_source_hash": src,

@@ -160,16 +160,20 @@ int cpm_precond_chunk(const cpm_ctx* ctx);
 
 /*
  * Tiling of the (unchunked, single right-hand side) preconditioner apply:
- * rows of W_j each wave streams at once and 16-byte chunks in flight per row.
- * 0: 2 rows, 2 chunks (default after cpm_factor); 1: 1, 2; 2: 4, 2; 3: 2, 1;
- * 4: 1, 1; 5: 4, 1. Every tiling forms each row's sum in the same order, so
- * results do not depend on it; only the speed does. cpm_set_precond_tiling
- * re-plans the apply blocks for the tiling's occupancy (ESTATE before
- * cpm_factor or with the chunked apply, EINVAL out of range).
+ * rows of W_j each wave streams at once, 16-byte chunks in flight per row and
+ * apply blocks per resident block slot. 0: 2 rows, 2 chunks, 2 blocks per
+ * slot (default after cpm_factor); 1: 4, 1, 2; 2: 2, 2, 1.5; 3: 4, 1, 3;
+ * 4: 4, 4, 1; 5: 4, 4, 2; 6: 8, 2, 2; 7: 4, 2, 2. Every tiling forms each
+ * row's sum in the same order, so results do not depend on it; only the
+ * speed does.
+ * cpm_set_precond_tiling re-plans the apply blocks for the tiling's occupancy
+ * (ESTATE before cpm_factor or with the chunked apply, EINVAL out of range).
  * cpm_autotune_precond times every tiling `reps` times on the resident factors
  * (HIP events on the context stream), keeps the fastest and returns it in
- * *best (may be NULL); ms (may be NULL) receives the 6 average times in ms.
+ * *best (may be NULL); ms (may be NULL) receives the CPM_PRECOND_TILINGS
+ * average times in ms.
  */
+#define CPM_PRECOND_TILINGS 8
 int cpm_set_precond_tiling(cpm_ctx* ctx, int tiling);
 int cpm_precond_tiling(const cpm_ctx* ctx);
 int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms);

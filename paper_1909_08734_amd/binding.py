@@ -21,6 +21,7 @@ RAS, ORAS = 0, 1
 FP64, FP32 = 0, 1
 PART_OCTANT, PART_RCB, PART_GRAPH = 0, 1, 2
 PART_ALIGN = 16
+PRECOND_TILINGS = 8  # CPM_PRECOND_TILINGS
 TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM = 0, 1, 2, 3
 
 _NAMES = {OK: "OK", ENOTCONV: "ENOTCONV", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM",
@@ -250,7 +251,7 @@ class Context:
         """Time the apply tilings on the resident factors and keep the fastest.
         Returns (best tiling, [ms per tiling])."""
         best = C.c_int()
-        ms = (C.c_double * 6)()
+        ms = (C.c_double * PRECOND_TILINGS)()
         self._check(self._L.cpm_autotune_precond(self._h, int(reps), C.byref(best), ms), "autotune_precond")
         return best.value, list(ms)
 

@@ -186,20 +186,27 @@ static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const doub
          (const double*)d.e, f, y);
 }
 
-// Tilings of the single-right-hand-side apply (rows per wave, 16-byte chunks
-// in flight per row); index 0 is the default. All give identical results.
-constexpr int N_TILINGS = 6;
-constexpr int kTilingRpw[N_TILINGS] = {2, 1, 4, 2, 1, 4};
-constexpr int kTilingUnr[N_TILINGS] = {2, 2, 2, 1, 1, 1};
+// Tilings of the single-right-hand-side apply: rows per wave, 16-byte chunks
+// in flight per row, and apply blocks per resident block slot (in halves;
+// with more blocks than slots the later blocks go to the slots that free
+// first, which evens out the finish times). Index 0 is the default; every
+// tiling gives bit-identical results.
+constexpr int N_TILINGS = CPM_PRECOND_TILINGS;
+struct Tiling {
+  int rpw, unr, over2;
+};
+constexpr Tiling kTilings[N_TILINGS] = {{2, 2, 4}, {4, 1, 4}, {2, 2, 3}, {4, 1, 6},
+                                        {4, 4, 2}, {4, 4, 4}, {8, 2, 4}, {4, 2, 4}};
 
 template <typename T>
 static const void* tiled_fn(int t) {
   switch (t) {
-    case 1: return (const void*)k_precond<T, 1, 2>;
-    case 2: return (const void*)k_precond<T, 4, 2>;
-    case 3: return (const void*)k_precond<T, 2, 1>;
-    case 4: return (const void*)k_precond<T, 1, 1>;
-    case 5: return (const void*)k_precond<T, 4, 1>;
+    case 1:
+    case 3: return (const void*)k_precond<T, 4, 1>;
+    case 4:
+    case 5: return (const void*)k_precond<T, 4, 4>;
+    case 6: return (const void*)k_precond<T, 8, 2>;
+    case 7: return (const void*)k_precond<T, 4, 2>;
     default: return (const void*)k_precond<T, 2, 2>;
   }
 }
@@ -212,11 +219,12 @@ static void launch_tiled(cpm_ctx* ctx, int t, size_t lds, const double* v, const
   const int32_t *bs = d.blk_sub, *si = d.sig_idx, *ti = d.tilde_idx;
   const T* W = (const T*)d.W;
   switch (t) {
-    case 1: launch(ctx, TIMER_PRECOND, k_precond<T, 1, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
-    case 2: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
-    case 3: launch(ctx, TIMER_PRECOND, k_precond<T, 2, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
-    case 4: launch(ctx, TIMER_PRECOND, k_precond<T, 1, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
-    case 5: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 1:
+    case 3: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 1>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 4:
+    case 5: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 4>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 6: launch(ctx, TIMER_PRECOND, k_precond<T, 8, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
+    case 7: launch(ctx, TIMER_PRECOND, k_precond<T, 4, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
     default: launch(ctx, TIMER_PRECOND, k_precond<T, 2, 2>, g, b, lds, desc, bs, si, ti, W, v, scale, z); break;
   }
 }
@@ -272,8 +280,8 @@ struct FactorPlan {
   int max_m = 0, max_n = 0, max_rows = 0, n_blocks = 0;
 };
 
-// Apply blocks per subdomain: the resident block slots apportioned by W bytes
-// (largest remainder, at least one each), so that no block waits for a slot.
+// Apply blocks per subdomain: `slots` blocks apportioned by W bytes (largest
+// remainder, at least one each).
 std::vector<int> apportion_blocks(const Decomp& D, int slots) {
   const int ns = D.n_sub;
   std::vector<double> bytes(ns);
@@ -294,6 +302,13 @@ std::vector<int> apportion_blocks(const Decomp& D, int slots) {
   });
   for (size_t q = 0; given < slots && q < rem.size(); ++q, ++given) want[rem[q].second] += 1;
   return want;
+}
+
+// Rows of W_j per apply block for `want` blocks: whole tiles, so that a
+// block's waves read whole tiles.
+inline int rows_per_block(int t, int want) {
+  const int r = std::max(1, (t + want - 1) / want);
+  return (r + W_TILE - 1) / W_TILE * W_TILE;
 }
 
 void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) {
@@ -320,13 +335,12 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) 
     d.lda = (int32_t)round_up(d.cols, 16);
     d.a_off = a_off;
     d.blk_off = blk;
-    const int want = want_blocks[j];
-    d.rpb = std::max(1, (d.t + want - 1) / want);
+    d.rpb = rows_per_block(d.t, want_blocks[j]);
     const int nb = (d.t + d.rpb - 1) / d.rpb;
     for (int q = 0; q < nb; ++q) P.blk_sub.push_back(j);
     blk += nb;
     a_off += (int64_t)d.rows * d.lda;
-    w_off += (int64_t)d.t * d.ldw;
+    w_off += w_rows_stored(d.t) * d.ldw;
     // unknowns [Sigma_j ; B_j] and their sorted lookup
     std::vector<int32_t> u(s.sigma);
     if (oras) u.insert(u.end(), s.bnd.begin(), s.bnd.end());
@@ -653,19 +667,15 @@ int dev_factor(cpm_ctx* ctx, int prec) {
       HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond_chunked<double>, PRECOND_THREADS, lds));
     else
       HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond_chunked<float>, PRECOND_THREADS, lds));
-  } else {
-    if (lds > 64 * 1024) {
-      hipFuncSetAttribute((const void*)k_precond<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipFuncSetAttribute((const void*)k_precond<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    }
-    if (prec == CPM_FP64)
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<double>, PRECOND_THREADS, lds));
-    else
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_precond<float>, PRECOND_THREADS, lds));
+  } else {  // the default tiling's kernel
+    const void* fn = prec == CPM_FP64 ? tiled_fn<double>(0) : tiled_fn<float>(0);
+    if (lds > 64 * 1024) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PRECOND_THREADS, lds));
   }
   per_cu = std::max(1, per_cu);
   FactorPlan P;
-  make_plan(ctx, P, n_cu * per_cu, dv.chunk > 0 ? PRECOND_RPB_MAX : 0);
+  make_plan(ctx, P, dv.chunk > 0 ? n_cu * per_cu : n_cu * per_cu * kTilings[0].over2 / 2,
+            dv.chunk > 0 ? PRECOND_RPB_MAX : 0);
   return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec) : run_factor<float>(ctx, P, prec);
 }
 
@@ -675,11 +685,12 @@ int dev_export_w(cpm_ctx* ctx, int j, double* w) {
   SubDesc d;
   HIPCHK(hipMemcpy(&d, dv.desc + j, sizeof(SubDesc), hipMemcpyDeviceToHost));
   const size_t esz = dv.prec == CPM_FP64 ? 8 : 4;
-  std::vector<char> buf((size_t)d.t * d.ldw * esz);
+  const int cw = esz == 8 ? W_CW<double> : W_CW<float>;
+  std::vector<char> buf((size_t)w_rows_stored(d.t) * d.ldw * esz);
   HIPCHK(hipMemcpy(buf.data(), (char*)dv.W + d.w_off * esz, buf.size(), hipMemcpyDeviceToHost));
   for (int q = 0; q < d.t; ++q)
     for (int c = 0; c < d.m; ++c) {
-      const size_t at = (size_t)q * d.ldw + c;
+      const size_t at = (size_t)w_tile_index(d.ldw, cw, q, c);
       w[(size_t)q * d.m + c] = esz == 8 ? ((const double*)buf.data())[at] : (double)((const float*)buf.data())[at];
     }
   return CPM_OK;
@@ -1246,7 +1257,7 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
     d.t = (int32_t)s.tilde.size();
     d.rows = d.n + d.t;
     d.lda = (int32_t)round_up(d.n + d.m, 16);
-    w_elems += (int64_t)d.t * round_up(d.m, 8);
+    w_elems += w_rows_stored(d.t) * round_up(d.m, 8);
     u_total += d.n;
     t_total += d.t;
   }
@@ -1285,12 +1296,12 @@ int dev_set_tiling(cpm_ctx* ctx, int t) {
   HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PRECOND_THREADS, lds));
   per_cu = std::max(1, per_cu);
-  const std::vector<int> want = apportion_blocks(ctx->dec, n_cu * per_cu);
+  const std::vector<int> want = apportion_blocks(ctx->dec, n_cu * per_cu * kTilings[t].over2 / 2);
   std::vector<int32_t> blk_sub;
   int32_t blk = 0;
   for (int j = 0; j < ctx->dec.n_sub; ++j) {
     SubDesc& d = dv.hdesc[j];
-    d.rpb = std::max(1, (d.t + want[j] - 1) / want[j]);
+    d.rpb = rows_per_block(d.t, want[j]);
     const int nb = (d.t + d.rpb - 1) / d.rpb;
     d.blk_off = blk;
     for (int q = 0; q < nb; ++q) blk_sub.push_back(j);

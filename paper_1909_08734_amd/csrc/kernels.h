@@ -107,7 +107,15 @@ __global__ __launch_bounds__(256) void k_stencil(int64_t na, double diag, double
 // Preconditioner apply (eq. algRAS): for every subdomain j and row q of
 // Sigma~_j, z[tilde_j(q)] = sum_c W_j[q, c] v[sigma_j(c)]. One block per
 // (subdomain, group of rows); v|Sigma_j is gathered into LDS once per block,
-// W rows stream from HBM with 16-byte loads; each row is written once.
+// W streams from HBM with 16-byte loads; each row is written once.
+//
+// Layout of W_j (ldw = |Sigma_j| rounded up to 8 columns, the padding zero):
+// rows in tiles of W_TILE, the last tile padded; inside a tile the columns in
+// chunks of W_CW<T> = 64 lanes x 16 bytes (128 FP64 / 256 FP32 values), each
+// chunk stored as W_TILE rows of W_CW values one after another, the last
+// chunk ragged (W_TILE rows of ldw mod W_CW). A block's waves, streaming the
+// tile's rows chunk by chunk, then read one contiguous stretch of memory per
+// step instead of one short piece of each of many rows.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct VecOf;
@@ -125,15 +133,37 @@ struct VecOf<float> {
 };
 
 constexpr int PRECOND_THREADS = 512;  // 8 waves per block
-constexpr int PRECOND_RPW = 2;        // rows a wave streams at once
+constexpr int W_TILE = 32;            // rows per tile of W_j
+template <typename T>
+constexpr int W_CW = 64 * VecOf<T>::n;  // columns per chunk
 
-// Block b serves rows [(b - blk_off) rpb, ...) of subdomain blk_sub[b]; the
-// host sizes rpb so that every block streams about the same number of bytes
-// and all blocks are resident at once (no partial last round). RPW rows per
-// wave and UNR 16-byte chunks in flight per row are the tunable tiling; every
-// tiling forms each row's sum in the same order (bit-identical results).
-template <typename T, int RPW = PRECOND_RPW, int UNR = VecOf<T>::unroll>
-__global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* __restrict__ desc,
+// Element offset of W_j[r, c] from the start of W_j (cw = W_CW<T>).
+__host__ __device__ inline int64_t w_tile_index(int ldw, int cw, int r, int c) {
+  const int R = r / W_TILE * W_TILE, i = r - R;
+  const int nfull = ldw / cw, k = c / cw;
+  const int64_t tile = (int64_t)R * ldw;
+  if (k < nfull) return tile + (int64_t)k * W_TILE * cw + (int64_t)i * cw + (c - k * cw);
+  const int wk = ldw - nfull * cw;
+  return tile + (int64_t)nfull * W_TILE * cw + (int64_t)i * wk + (c - nfull * cw);
+}
+// Rows of W_j as stored (t rounded up to whole tiles).
+__host__ __device__ inline int64_t w_rows_stored(int t) { return (int64_t)(t + W_TILE - 1) / W_TILE * W_TILE; }
+
+// Block b serves rows [(b - blk_off) rpb, ...) of subdomain blk_sub[b] (rpb a
+// multiple of W_TILE); the host sizes rpb so that every block streams about
+// the same number of bytes. RPW rows per wave and UNR chunks in flight per
+// row are the tunable tiling; every tiling forms each row's sum over the same
+// columns in the same order (lane l: columns l VN + k W_CW, k ascending, then
+// the ragged chunk), so all give bit-identical results.
+// Waves per SIMD a tiling is compiled for (its register budget, no spills):
+// 4 rows per wave need more than the 64 registers of 8 waves, 8 loads in
+// flight more than the 80 of 6, 16 more than the 128 of 4.
+constexpr int precond_waves(int rpw, int unr) {
+  return rpw * unr >= 16 ? 3 : rpw * unr >= 8 ? 4 : rpw >= 4 ? 6 : 8;
+}
+
+template <typename T, int RPW, int UNR>
+__global__ __launch_bounds__(PRECOND_THREADS, precond_waves(RPW, UNR)) void k_precond(const SubDesc* __restrict__ desc,
                                                              const int32_t* __restrict__ blk_sub,
                                                              const int32_t* __restrict__ sig_idx,
                                                              const int32_t* __restrict__ tilde_idx,
@@ -144,6 +174,8 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* _
   extern __shared__ double vs[];
   typedef typename VecOf<T>::type VT;
   constexpr int VN = VecOf<T>::n;
+  constexpr int CW = W_CW<T>;
+  constexpr int64_t KS = (int64_t)W_TILE * CW;  // stride between chunks of one row
   constexpr int NWAVE = PRECOND_THREADS / 64;
   const int blk = blockIdx.x;
   const int j = blk_sub[blk];
@@ -154,39 +186,59 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* _
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = (blk - d.blk_off) * d.rpb;
   const int r_end = min(r_begin + d.rpb, d.t);
+  const int nfull = d.ldw / CW, wk = d.ldw - nfull * CW;
+  const double* vl = vs + lane * VN;
   for (int r0 = r_begin + wave * RPW; r0 < r_end; r0 += NWAVE * RPW) {
-    const T* wr[RPW];
+    // rows r0 .. r0 + RPW - 1 (the last clamped to r_end - 1) lie in one tile
+    const int R = r0 / W_TILE * W_TILE;
+    const T* wf = W + d.w_off + (int64_t)R * d.ldw + (r0 - R) * CW + lane * VN;  // chunk 0, row r0
+    int ro[RPW];                                                                   // row offsets in a chunk
     double acc[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
-      wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw;
+      ro[i] = min(i, r_end - 1 - r0);
       acc[i] = 0.0;
     }
-    int c = lane * VN;
-    for (; c + (UNR - 1) * 64 * VN < d.ldw; c += UNR * 64 * VN) {
+    int k = 0;
+#pragma unroll 1
+    for (; k + UNR <= nfull; k += UNR) {
       VT wv[UNR][RPW];
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
         for (int i = 0; i < RPW; ++i)
-          wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c + u * 64 * VN));
+          wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wf + (k + u) * KS + ro[i] * CW));
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
         for (int e = 0; e < VN; ++e) {
-          const double xv = vs[c + u * 64 * VN + e];
+          const double xv = vl[(k + u) * CW + e];
 #pragma unroll
           for (int i = 0; i < RPW; ++i) acc[i] += (double)wv[u][i][e] * xv;
         }
     }
-    for (; c < d.ldw; c += 64 * VN) {
+#pragma unroll 1
+    for (; k < nfull; ++k) {
       VT wv[RPW];
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
-        wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
+        wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wf + k * KS + ro[i] * CW));
 #pragma unroll
       for (int e = 0; e < VN; ++e) {
-        const double xv = vs[c + e];
+        const double xv = vl[k * CW + e];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) acc[i] += (double)wv[i][e] * xv;
+      }
+    }
+    if (lane * VN < wk) {
+      // ragged chunk: rows of wk values
+      const T* wt = W + d.w_off + (int64_t)R * d.ldw + nfull * KS + (r0 - R) * wk + lane * VN;
+      VT wv[RPW];
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wt + ro[i] * wk));
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        const double xv = vl[nfull * CW + e];
 #pragma unroll
         for (int i = 0; i < RPW; ++i) acc[i] += (double)wv[i][e] * xv;
       }
@@ -204,6 +256,7 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond(const SubDesc* _
 // (at most PRECOND_RPB_MAX rows per block), then the rows are written once.
 constexpr int PRECOND_CHUNK = 4096;     // columns of v per pass (default)
 constexpr int PRECOND_RPB_MAX = 1024;   // rows per block in the chunked form
+constexpr int CHUNKED_RPW = 2;
 
 template <typename T>
 __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const SubDesc* __restrict__ desc,
@@ -219,6 +272,7 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
   double* ps = lds + chunk;  // partial sums of the block's rows
   typedef typename VecOf<T>::type VT;
   constexpr int VN = VecOf<T>::n;
+  constexpr int CW = W_CW<T>;
   constexpr int NWAVE = PRECOND_THREADS / 64;
   const int blk = blockIdx.x;
   const int j = blk_sub[blk];
@@ -227,6 +281,7 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = (blk - d.blk_off) * d.rpb;
   const int r_end = min(r_begin + d.rpb, d.t);
+  const T* Wj = W + d.w_off;
   for (int q = threadIdx.x; q < r_end - r_begin; q += PRECOND_THREADS) ps[q] = 0.0;
   for (int c0 = 0; c0 < d.ldw; c0 += chunk) {
     const int cw = min(chunk, d.ldw - c0);
@@ -234,27 +289,29 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
     for (int c = threadIdx.x; c < cw; c += PRECOND_THREADS)
       vs[c] = c0 + c < d.m ? sc * v[sig_idx[d.u_off + c0 + c]] : 0.0;
     __syncthreads();
-    for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += NWAVE * PRECOND_RPW) {
-      const T* wr[PRECOND_RPW];
-      double acc[PRECOND_RPW];
+    for (int r0 = r_begin + wave * CHUNKED_RPW; r0 < r_end; r0 += NWAVE * CHUNKED_RPW) {
+      int rr[CHUNKED_RPW];
+      double acc[CHUNKED_RPW];
 #pragma unroll
-      for (int i = 0; i < PRECOND_RPW; ++i) {
-        wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw + c0;
+      for (int i = 0; i < CHUNKED_RPW; ++i) {
+        rr[i] = min(r0 + i, r_end - 1);
         acc[i] = 0.0;
       }
       for (int c = lane * VN; c < cw; c += 64 * VN) {
-        VT wv[PRECOND_RPW];
+        VT wv[CHUNKED_RPW];
 #pragma unroll
-        for (int i = 0; i < PRECOND_RPW; ++i) wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
+        for (int i = 0; i < CHUNKED_RPW; ++i)
+          wv[i] = __builtin_nontemporal_load(
+              reinterpret_cast<const VT*>(Wj + w_tile_index(d.ldw, CW, rr[i], c0 + c)));
 #pragma unroll
         for (int e = 0; e < VN; ++e) {
           const double xv = vs[c + e];
 #pragma unroll
-          for (int i = 0; i < PRECOND_RPW; ++i) acc[i] += (double)wv[i][e] * xv;
+          for (int i = 0; i < CHUNKED_RPW; ++i) acc[i] += (double)wv[i][e] * xv;
         }
       }
 #pragma unroll
-      for (int i = 0; i < PRECOND_RPW; ++i) {
+      for (int i = 0; i < CHUNKED_RPW; ++i) {
         const double s = wave_sum(acc[i]);
         if (lane == 0 && r0 + i < r_end) ps[r0 + i - r_begin] += s;
       }
@@ -269,8 +326,12 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
 // conflicts), each W element multiplied by all of them. For every
 // right-hand side the sums are formed in the order of k_precond, so a batched
 // apply equals NB single applies bit for bit.
+constexpr int MULTI_RPW = 2;
+// register budget (waves per SIMD) without spills
+constexpr int multi_waves(int nb, int vn) { return nb >= 4 ? (vn >= 4 ? 4 : 6) : (vn >= 4 ? 7 : 8); }
+
 template <typename T, int NB>
-__global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_multi(const SubDesc* __restrict__ desc,
+__global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n)) void k_precond_multi(const SubDesc* __restrict__ desc,
                                                                    const int32_t* __restrict__ blk_sub,
                                                                    const int32_t* __restrict__ sig_idx,
                                                                    const int32_t* __restrict__ tilde_idx,
@@ -282,7 +343,9 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_multi(const SubD
   extern __shared__ double vs[];  // vs[q * ldw + c]
   typedef typename VecOf<T>::type VT;
   constexpr int VN = VecOf<T>::n;
-  constexpr int PRECOND_UNROLL = VecOf<T>::unroll;
+  constexpr int UNR = VecOf<T>::unroll;
+  constexpr int CW = W_CW<T>;
+  constexpr int64_t KS = (int64_t)W_TILE * CW;
   constexpr int NWAVE = PRECOND_THREADS / 64;
   const int blk = blockIdx.x;
   const int j = blk_sub[blk];
@@ -299,50 +362,70 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_multi(const SubD
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = (blk - d.blk_off) * d.rpb;
   const int r_end = min(r_begin + d.rpb, d.t);
-  for (int r0 = r_begin + wave * PRECOND_RPW; r0 < r_end; r0 += NWAVE * PRECOND_RPW) {
-    const T* wr[PRECOND_RPW];
-    double acc[PRECOND_RPW][NB];
+  const int nfull = d.ldw / CW, wk = d.ldw - nfull * CW;
+  const double* vl = vs + lane * VN;
+  for (int r0 = r_begin + wave * MULTI_RPW; r0 < r_end; r0 += NWAVE * MULTI_RPW) {
+    const int R = r0 / W_TILE * W_TILE;
+    const T* wf = W + d.w_off + (int64_t)R * d.ldw + (r0 - R) * CW + lane * VN;
+    int ro[MULTI_RPW];
+    double acc[MULTI_RPW][NB];
 #pragma unroll
-    for (int i = 0; i < PRECOND_RPW; ++i) {
-      wr[i] = W + d.w_off + (int64_t)min(r0 + i, r_end - 1) * d.ldw;
+    for (int i = 0; i < MULTI_RPW; ++i) {
+      ro[i] = min(i, r_end - 1 - r0);
 #pragma unroll
       for (int q = 0; q < NB; ++q) acc[i][q] = 0.0;
     }
-    int c = lane * VN;
-    for (; c + (PRECOND_UNROLL - 1) * 64 * VN < d.ldw; c += PRECOND_UNROLL * 64 * VN) {
-      VT wv[PRECOND_UNROLL][PRECOND_RPW];
+    int k = 0;
+#pragma unroll 1
+    for (; k + UNR <= nfull; k += UNR) {
+      VT wv[UNR][MULTI_RPW];
 #pragma unroll
-      for (int u = 0; u < PRECOND_UNROLL; ++u)
+      for (int u = 0; u < UNR; ++u)
 #pragma unroll
-        for (int i = 0; i < PRECOND_RPW; ++i)
-          wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c + u * 64 * VN));
+        for (int i = 0; i < MULTI_RPW; ++i)
+          wv[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wf + (k + u) * KS + ro[i] * CW));
 #pragma unroll
-      for (int u = 0; u < PRECOND_UNROLL; ++u)
+      for (int u = 0; u < UNR; ++u)
 #pragma unroll
         for (int e = 0; e < VN; ++e)
 #pragma unroll
           for (int q = 0; q < NB; ++q) {
-            const double xv = vs[q * d.ldw + c + u * 64 * VN + e];
+            const double xv = vl[q * d.ldw + (k + u) * CW + e];
 #pragma unroll
-            for (int i = 0; i < PRECOND_RPW; ++i) acc[i][q] += (double)wv[u][i][e] * xv;
+            for (int i = 0; i < MULTI_RPW; ++i) acc[i][q] += (double)wv[u][i][e] * xv;
           }
     }
-    for (; c < d.ldw; c += 64 * VN) {
-      VT wv[PRECOND_RPW];
+#pragma unroll 1
+    for (; k < nfull; ++k) {
+      VT wv[MULTI_RPW];
 #pragma unroll
-      for (int i = 0; i < PRECOND_RPW; ++i)
-        wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wr[i] + c));
+      for (int i = 0; i < MULTI_RPW; ++i)
+        wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wf + k * KS + ro[i] * CW));
 #pragma unroll
       for (int e = 0; e < VN; ++e)
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-          const double xv = vs[q * d.ldw + c + e];
+          const double xv = vl[q * d.ldw + k * CW + e];
 #pragma unroll
-          for (int i = 0; i < PRECOND_RPW; ++i) acc[i][q] += (double)wv[i][e] * xv;
+          for (int i = 0; i < MULTI_RPW; ++i) acc[i][q] += (double)wv[i][e] * xv;
+        }
+    }
+    if (lane * VN < wk) {
+      const T* wt = W + d.w_off + (int64_t)R * d.ldw + nfull * KS + (r0 - R) * wk + lane * VN;
+      VT wv[MULTI_RPW];
+#pragma unroll
+      for (int i = 0; i < MULTI_RPW; ++i) wv[i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wt + ro[i] * wk));
+#pragma unroll
+      for (int e = 0; e < VN; ++e)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const double xv = vl[q * d.ldw + nfull * CW + e];
+#pragma unroll
+          for (int i = 0; i < MULTI_RPW; ++i) acc[i][q] += (double)wv[i][e] * xv;
         }
     }
 #pragma unroll
-    for (int i = 0; i < PRECOND_RPW; ++i)
+    for (int i = 0; i < MULTI_RPW; ++i)
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const double s = wave_sum(acc[i][q]);
@@ -753,7 +836,8 @@ __global__ __launch_bounds__(256) void k_tile_selftest(T* C, const T* Am, const 
   tile_update<T>(C, GEMM_TILE, GEMM_TILE, GEMM_TILE, kdim, 0, 0, Am, LU_KMAX, Bm, GEMM_TILE);
 }
 
-// W_j = -(lower-right block) of the eliminated augmented matrix, row stride ldw.
+// W_j = -(lower-right block) of the eliminated augmented matrix, written in the
+// tiled layout of the apply kernels (w_tile_index).
 template <typename T>
 __global__ __launch_bounds__(256) void k_extract_w(const SubDesc* __restrict__ desc, const T* __restrict__ A,
                                                    T* __restrict__ W) {
@@ -762,8 +846,8 @@ __global__ __launch_bounds__(256) void k_extract_w(const SubDesc* __restrict__ d
   const int q = blockIdx.x;
   if (q >= d.t) return;
   const T* src = A + d.a_off + (int64_t)(d.n + q) * d.lda + d.n;
-  T* dst = W + d.w_off + (int64_t)q * d.ldw;
-  for (int c = threadIdx.x; c < d.ldw; c += 256) dst[c] = c < d.m ? -src[c] : (T)0;
+  T* dst = W + d.w_off;
+  for (int c = threadIdx.x; c < d.ldw; c += 256) dst[w_tile_index(d.ldw, W_CW<T>, q, c)] = c < d.m ? -src[c] : (T)0;
 }
 
 // ---------------------------------------------------------------------------

@@ -2,9 +2,9 @@
 
 Builds the h = 0.025 unit-sphere problem (64 RCB subdomains, overlap 3, ORAS
 alpha = 1/h), factors the local operators in the requested precision, runs a
-few preconditioner applies and operator applies, then one plain device copy
-of known size (used to calibrate the memory counters). Meant to run under
-``rocprofv3 --pmc ...``.
+few preconditioner applies (and operator applies) with each apply tiling in
+turn, tiling 0 first, then one plain device copy of known size (used to
+calibrate the memory counters). Meant to run under ``rocprofv3 --pmc ...``.
 """
 
 from __future__ import annotations
@@ -38,16 +38,19 @@ def main():
     na, _, _ = ctx.band_sizes()
     v = torch.randn(na, dtype=torch.float64, device="cuda")
     z = torch.zeros_like(v)
-    for _ in range(a.applies):
-        ctx.apply_precond(v, z)
-        ctx.apply_operator(z, v)
+    for t in range(P.PRECOND_TILINGS):
+        ctx.set_precond_tiling(t)
+        for _ in range(a.applies):
+            ctx.apply_precond(v, z)
+            ctx.apply_operator(z, v)
     n = a.copy_mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(f"profile workload done: {a.prec}, {a.applies} applies, copy {a.copy_mib} MiB", flush=True)
+    print(f"profile workload done: {a.prec}, {a.applies} applies x {P.PRECOND_TILINGS} tilings, "
+          f"copy {a.copy_mib} MiB", flush=True)
     ctx.close()
 
 

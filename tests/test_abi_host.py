@@ -31,6 +31,18 @@ def test_library_exports_every_declared_symbol():
     assert sorted(P.EXPORTED) == names
 
 
+def test_binding_constants_match_header():
+    """Every #define and enum value of the header is mirrored by the binding."""
+    text = open(os.path.join(ROOT, "include", "cpm.h")).read()
+    defines = dict(re.findall(r"#define\s+CPM_([A-Z_]+)\s+(-?\d+)", text))
+    enums = dict(re.findall(r"\bCPM_([A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    values = {**enums, **defines}
+    assert int(values["PRECOND_TILINGS"]) == P.PRECOND_TILINGS
+    for name in ("OK", "ENOTCONV", "EINVAL", "ESTATE", "ENOMEM", "ESINGULAR", "EDEVICE", "RAS", "ORAS", "FP64",
+                 "FP32", "PART_OCTANT", "PART_RCB", "PART_GRAPH", "PART_ALIGN"):
+        assert int(values[name]) == getattr(P, name), name
+
+
 CASES = [
     (ci.Sphere(), 0.1, 3, "rcb", 8, 2),
     (ci.Sphere(), 0.1, 3, "octant", 8, 2),

@@ -365,7 +365,7 @@ def test_precond_tilings_are_identical_and_autotune_keeps_results(prec):
     na = b.n_act
     v = dev(np.random.default_rng(9).standard_normal(na))
     ref = None
-    for t in range(6):
+    for t in range(P.PRECOND_TILINGS):
         ctx.set_precond_tiling(t)
         assert ctx.precond_tiling() == t
         z = torch.zeros(na, dtype=torch.float64, device="cuda")
@@ -375,13 +375,13 @@ def test_precond_tilings_are_identical_and_autotune_keeps_results(prec):
         else:
             np.testing.assert_array_equal(z.cpu().numpy(), ref)
     with pytest.raises(P.CpmError):
-        ctx.set_precond_tiling(6)
+        ctx.set_precond_tiling(P.PRECOND_TILINGS)
     f = ci.rhs_sphere_y20(b.cp[: b.n_act], 1.0)
     ctx.set_precond_tiling(0)
     u0, i0, _ = ctx.solve(f, tol=1e-10, max_iter=300)
     best, ms = ctx.autotune_precond(reps=2)
     say("tiling times (ms)", ms, "best", best)
-    assert 0 <= best < 6 and ctx.precond_tiling() == best and all(x > 0 for x in ms)
+    assert 0 <= best < P.PRECOND_TILINGS and ctx.precond_tiling() == best and all(x > 0 for x in ms)
     u1, i1, _ = ctx.solve(f, tol=1e-10, max_iter=300)
     np.testing.assert_array_equal(u1, u0)
     assert i1[0]["iters"] == i0[0]["iters"]
