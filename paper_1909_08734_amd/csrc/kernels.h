@@ -1078,18 +1078,21 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const doub
 #pragma unroll
     for (int u = 0; u < NC; ++u) acc[u] = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
-      double v[NC];
       double s = 0.0;
 #pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        v[u] = u < ncols ? V[(int64_t)u * ld + r] : 0.0;
-        if (u < ncols) s += v[u] * hs[u];
-      }
+      for (int u = 0; u < NC; ++u)
+        if (u < ncols) s += V[(int64_t)u * ld + r] * hs[u];
       const double wn = w[r] - s;
       w[r] = wn;
       if (mode == 0) {
+        // The row of V is read again (from cache) rather than kept in 32 more
+        // registers: the kernel then fits 4 waves per SIMD, so the whole grid
+        // is resident in one round. The compiler barrier keeps the two reads
+        // apart.
+        asm volatile("" ::: "memory");
 #pragma unroll
-        for (int u = 0; u < NC; ++u) acc[u] += v[u] * wn;
+        for (int u = 0; u < NC; ++u)
+          if (u < ncols) acc[u] += V[(int64_t)u * ld + r] * wn;
       } else {
         acc[0] += wn * wn;
       }
