@@ -523,6 +523,9 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
 // ---------------------------------------------------------------------------
 constexpr int LU_NB = 32;
 constexpr int PANEL_THREADS = 1024;
+constexpr int PANEL_GROUP = 8;  // columns of a row updated together in the panel
+constexpr int PANEL_TB = 4;     // 32-row tiles per round of the panel's gather and write-back
+static_assert(LU_NB % PANEL_GROUP == 0, "panel groups cover the scratch columns exactly");
 
 // (value, row) pair reduction over the block: largest |value|, lowest row on ties.
 __device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri, int* out) {
@@ -557,7 +560,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
                                                             int32_t* __restrict__ info, T* __restrict__ scratch,
                                                             const int64_t* __restrict__ scr_off) {
   constexpr int NW = PANEL_THREADS / 64;
-  __shared__ T tile[32][33];
+  __shared__ T tile[PANEL_TB * 32][33];
   __shared__ T prow[LU_NB];
   __shared__ double rv[NW];
   __shared__ int ri[NW];
@@ -572,16 +575,28 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
   const int64_t lda = d.lda;
   T* P = scratch + scr_off[j];  // column c at P + c * rows
   const int t = threadIdx.x;
-  // gather the panel (32-row tiles, transposed through LDS)
-  for (int r0 = 0; r0 < rows; r0 += 32) {
+  // gather the panel (PANEL_TB 32-row tiles per round, transposed through LDS;
+  // a round's loads are in flight together)
+  for (int r0 = 0; r0 < rows; r0 += PANEL_TB * 32) {
     {
       const int rl = t >> 5, c = t & 31;
-      if (r0 + rl < rows && c < kb) tile[rl][c] = a[(int64_t)(r0 + rl) * lda + c];
+      T g[PANEL_TB];
+#pragma unroll
+      for (int b = 0; b < PANEL_TB; ++b) {
+        const int r = r0 + b * 32 + rl;
+        g[b] = (r < rows && c < kb) ? a[(int64_t)r * lda + c] : (T)0;
+      }
+#pragma unroll
+      for (int b = 0; b < PANEL_TB; ++b) tile[b * 32 + rl][c] = g[b];
     }
     __syncthreads();
     {
       const int c = t >> 5, rl = t & 31;
-      if (r0 + rl < rows && c < kb) P[(int64_t)c * rows + r0 + rl] = tile[rl][c];
+#pragma unroll
+      for (int b = 0; b < PANEL_TB; ++b) {
+        const int r = r0 + b * 32 + rl;
+        if (r < rows && c < kb) P[(int64_t)c * rows + r] = tile[b * 32 + rl][c];
+      }
     }
     __syncthreads();
   }
@@ -616,13 +631,26 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
       for (int r = jj + 1 + t; r < rows; r += PANEL_THREADS) {
         const T l = pj[r] / pv;
         pj[r] = l;
-        for (int c = jj + 1; c < kb; ++c) {
-          T* pc = P + (int64_t)c * rows;
-          const T nv = pc[r] - l * prow[c];
-          pc[r] = nv;
-          if (c == jj + 1 && r < np) {
-            const double av = fabs((double)nv);
-            if (av > best) { best = av; bi = r; }
+        // the row's remaining entries, PANEL_GROUP columns at a time: a
+        // group's loads are all issued before its stores, and none of them
+        // is conditional (a column outside jj < c < kb is written back
+        // unchanged; the scratch has LU_NB columns), so no wait is needed
+        // between them
+        T* pr = P + r;
+        for (int c0 = (jj + 1) / PANEL_GROUP * PANEL_GROUP; c0 < kb; c0 += PANEL_GROUP) {
+          T v[PANEL_GROUP];
+#pragma unroll
+          for (int q = 0; q < PANEL_GROUP; ++q) v[q] = pr[(int64_t)(c0 + q) * rows];
+#pragma unroll
+          for (int q = 0; q < PANEL_GROUP; ++q) {
+            const int c = c0 + q;
+            const bool live = c > jj && c < kb;
+            const T nv = live ? v[q] - l * prow[c] : v[q];
+            pr[(int64_t)c * rows] = nv;
+            if (live && c == jj + 1 && r < np) {
+              const double av = fabs((double)nv);
+              if (av > best) { best = av; bi = r; }
+            }
           }
         }
       }
@@ -636,16 +664,27 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
     if (jj + 1 < kb) piv = block_argmax(best, bi, rv, ri, &piv_s);
     else __syncthreads();
   }
-  // write the factored panel back
-  for (int r0 = 0; r0 < rows; r0 += 32) {
+  // write the factored panel back (same rounds)
+  for (int r0 = 0; r0 < rows; r0 += PANEL_TB * 32) {
     {
       const int c = t >> 5, rl = t & 31;
-      if (r0 + rl < rows && c < kb) tile[rl][c] = P[(int64_t)c * rows + r0 + rl];
+      T g[PANEL_TB];
+#pragma unroll
+      for (int b = 0; b < PANEL_TB; ++b) {
+        const int r = r0 + b * 32 + rl;
+        g[b] = (r < rows && c < kb) ? P[(int64_t)c * rows + r] : (T)0;
+      }
+#pragma unroll
+      for (int b = 0; b < PANEL_TB; ++b) tile[b * 32 + rl][c] = g[b];
     }
     __syncthreads();
     {
       const int rl = t >> 5, c = t & 31;
-      if (r0 + rl < rows && c < kb) a[(int64_t)(r0 + rl) * lda + c] = tile[rl][c];
+#pragma unroll
+      for (int b = 0; b < PANEL_TB; ++b) {
+        const int r = r0 + b * 32 + rl;
+        if (r < rows && c < kb) a[(int64_t)r * lda + c] = tile[b * 32 + rl][c];
+      }
     }
     __syncthreads();
   }
