@@ -523,9 +523,12 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
 // ---------------------------------------------------------------------------
 constexpr int LU_NB = 32;
 constexpr int PANEL_THREADS = 1024;
-constexpr int PANEL_GROUP = 8;  // columns of a row updated together in the panel
+// columns of a row updated together in the panel (fewer in FP64: registers)
+template <typename T>
+constexpr int PANEL_GROUP = sizeof(T) == 8 ? 4 : 8;
 constexpr int PANEL_TB = 4;     // 32-row tiles per round of the panel's gather and write-back
-static_assert(LU_NB % PANEL_GROUP == 0, "panel groups cover the scratch columns exactly");
+static_assert(LU_NB % PANEL_GROUP<double> == 0 && LU_NB % PANEL_GROUP<float> == 0,
+              "panel groups cover the scratch columns exactly");
 
 // (value, row) pair reduction over the block: largest |value|, lowest row on ties.
 __device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri, int* out) {
@@ -628,28 +631,44 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
     best = -1.0;
     bi = INT32_MAX;
     if (piv >= 0) {
-      for (int r = jj + 1 + t; r < rows; r += PANEL_THREADS) {
-        const T l = pj[r] / pv;
-        pj[r] = l;
-        // the row's remaining entries, PANEL_GROUP columns at a time: a
-        // group's loads are all issued before its stores, and none of them
-        // is conditional (a column outside jj < c < kb is written back
-        // unchanged; the scratch has LU_NB columns), so no wait is needed
-        // between them
-        T* pr = P + r;
-        for (int c0 = (jj + 1) / PANEL_GROUP * PANEL_GROUP; c0 < kb; c0 += PANEL_GROUP) {
-          T v[PANEL_GROUP];
+      // two rows per pass (r and r + PANEL_THREADS; a missing second row
+      // repeats the first, which rewrites the same values), PANEL_GROUP columns
+      // at a time: all loads of a group are issued before its stores, and none
+      // is conditional (a column outside jj < c < kb is written back
+      // unchanged; the scratch has LU_NB columns), so the loads of both rows
+      // are in flight together with no wait between them
+      for (int r = jj + 1 + t; r < rows; r += 2 * PANEL_THREADS) {
+        const bool two = r + PANEL_THREADS < rows;
+        const int r2 = two ? r + PANEL_THREADS : r;
+        T* pa = P + r;
+        T* pb = P + r2;
+        const T la = pj[r] / pv, lb = pj[r2] / pv;
+        pj[r] = la;
+        pj[r2] = lb;
+        for (int c0 = (jj + 1) / PANEL_GROUP<T> * PANEL_GROUP<T>; c0 < kb; c0 += PANEL_GROUP<T>) {
+          T va[PANEL_GROUP<T>], vb[PANEL_GROUP<T>];
 #pragma unroll
-          for (int q = 0; q < PANEL_GROUP; ++q) v[q] = pr[(int64_t)(c0 + q) * rows];
+          for (int q = 0; q < PANEL_GROUP<T>; ++q) {
+            va[q] = pa[(int64_t)(c0 + q) * rows];
+            vb[q] = pb[(int64_t)(c0 + q) * rows];
+          }
 #pragma unroll
-          for (int q = 0; q < PANEL_GROUP; ++q) {
+          for (int q = 0; q < PANEL_GROUP<T>; ++q) {
             const int c = c0 + q;
             const bool live = c > jj && c < kb;
-            const T nv = live ? v[q] - l * prow[c] : v[q];
-            pr[(int64_t)c * rows] = nv;
-            if (live && c == jj + 1 && r < np) {
-              const double av = fabs((double)nv);
-              if (av > best) { best = av; bi = r; }
+            const T na = live ? va[q] - la * prow[c] : va[q];
+            const T nb = live ? vb[q] - lb * prow[c] : vb[q];
+            pa[(int64_t)c * rows] = na;
+            pb[(int64_t)c * rows] = nb;
+            if (live && c == jj + 1) {
+              if (r < np) {
+                const double av = fabs((double)na);
+                if (av > best) { best = av; bi = r; }
+              }
+              if (two && r2 < np) {
+                const double av = fabs((double)nb);
+                if (av > best) { best = av; bi = r2; }
+              }
             }
           }
         }
@@ -713,31 +732,37 @@ constexpr int TRSM_COLS = 64;
 // Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
 // [c_lo, c_hi); with `trsm`, then U = L11^{-1} A on rows [kstart, kstart+kdim)
 // (L11 unit lower triangular). One wave per 64 columns, column values in LDS.
+// The interchanges are loaded once, two per lane, and broadcast by shuffles
+// (most are the identity, so the loop then rarely touches memory).
 template <typename T>
 __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                             const int32_t* __restrict__ ipiv,
                                                             const LuJob* __restrict__ jobs,
                                                             const int32_t* __restrict__ prefix, int n_jobs,
                                                             int trsm) {
+  static_assert(LU_KMAX <= 2 * TRSM_COLS, "two interchanges per lane");
   __shared__ T X[LU_KMAX][TRSM_COLS];
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
-  const int c = jb.c_lo + (blockIdx.x - prefix[q]) * TRSM_COLS + threadIdx.x;
-  if (c >= jb.c_hi) return;
+  const int t = threadIdx.x;
+  const int c = jb.c_lo + (blockIdx.x - prefix[q]) * TRSM_COLS + t;
+  const bool live = c < jb.c_hi;  // every lane takes part in the shuffles
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
+  const int32_t* pg = ipiv + d.u_off + jb.kstart;
+  const int pv0 = t < jb.kdim ? pg[t] : 0;
+  const int pv1 = t + TRSM_COLS < jb.kdim ? pg[t + TRSM_COLS] : 0;
   for (int i = 0; i < jb.kdim; ++i) {
-    const int p = ipiv[d.u_off + jb.kstart + i];
+    const int p = __shfl(i < TRSM_COLS ? pv0 : pv1, i & (TRSM_COLS - 1), TRSM_COLS);
     const int r = jb.kstart + i;
-    if (p != r) {
+    if (live && p != r) {
       const T tmp = a[r * lda + c];
       a[r * lda + c] = a[p * lda + c];
       a[p * lda + c] = tmp;
     }
   }
-  if (!trsm) return;
-  const int t = threadIdx.x;
+  if (!trsm || !live) return;
   const T* l = a + (int64_t)jb.kstart * lda + jb.kstart;
   for (int i = 0; i < jb.kdim; ++i) X[i][t] = a[(jb.kstart + i) * lda + c];
   for (int qq = 0; qq < jb.kdim; ++qq) {
