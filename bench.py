@@ -424,7 +424,24 @@ def cpu_baseline(wl, gpu_iters):
         w = w - np.dot(V[i], w) * V[i]
     t_mgs = time.perf_counter() - t0
     per_iter = t_pre + t_op + t_mgs
+    # the same per-iteration work on one thread
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            M.apply(v)
+            t_pre1 = (time.perf_counter() - t0) * (n_sub / len(sample))
+        one = 1.0 / (gpu_iters * (t_pre1 + t_op + t_mgs))
+    except Exception:
+        one = None
+    host = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            host = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / (gpu_iters * per_iter), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "value_1_thread": one, "host": host,
             "sample": (f"oracle dense-LU local solves of {len(sample)}/{n_sub} subdomains scaled "
                        f"x{n_sub / len(sample):g} ({t_pre * 1e3:.0f} ms/apply), CSR A.v ({t_op * 1e3:.1f} ms), "
                        f"one MGS pass at depth {k} ({t_mgs * 1e3:.1f} ms), x {gpu_iters:.1f} iterations; "
