@@ -514,7 +514,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     // earlier L columns. After the outer block, the trailing matrix gets the
     // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
     // and one MFMA update with K = LU_KMAX.
-    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3 };
+    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4 };
     struct Launch {
       int kind, k, job_off, n_jobs, units;
     };
@@ -568,10 +568,10 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
         const int K1 = std::min(K0 + LU_KMAX, d.n);
         const LuJob jb{j, K0, K1 - K0, K1, K1, d.cols};
         ts.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
-        gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE) * cdiv(d.cols - K1, GEMM_TILE)});
+        gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE_R) * cdiv(d.cols - K1, GEMM_TILE)});
       }
       add(L_SWAP_TRSM, K0, ts);
-      add(L_GEMM, K0, gm);
+      add(L_GEMM_TRAIL, K0, gm);
     }
     FCHK(upload(ctx, &jobs_buf, jobs));
     FCHK(upload(ctx, &dpre, prefix));
@@ -595,6 +595,10 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
         case L_SWAP:
           k_lu_swap_trsm<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, gipiv, jb, pre, L.n_jobs,
                                                                      L.kind == L_SWAP_TRSM ? 1 : 0);
+          break;
+        case L_GEMM_TRAIL:
+          launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE_R, GEMM_TILE>, dim3(L.units), dim3(256), 0,
+                 (const SubDesc*)gdesc, dA, jb, pre, L.n_jobs);
           break;
         case L_GEMM:
           launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(L.units), dim3(256), 0, (const SubDesc*)gdesc, dA, jb, pre,

@@ -797,23 +797,29 @@ struct Acc4<float> {
 };
 
 constexpr int GEMM_TILE = 64;
+constexpr int GEMM_TILE_R = 128;  // rows of the trailing-update tile (columns: GEMM_TILE)
 
-template <typename T>
+// TM x TN tile of C; four waves in a 2 x 2 arrangement, each (TM/2) x (TN/2)
+// as (TM/32) x (TN/32) blocks of 16 x 16. Every C element accumulates the same
+// MFMA steps in the same order whatever the tile shape, so all shapes give
+// the same bits.
+template <typename T, int TM = GEMM_TILE, int TN = GEMM_TILE>
 __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int rows, int cols, int kdim,
                                             int r0, int c0, const T* __restrict__ lsrc, int64_t lld,
                                             const T* __restrict__ usrc, int64_t uld) {
   // C[r0.., c0..] -= Lsrc[r0.., 0..kdim) * Usrc[0..kdim, c0..]   (C = a, rows x cols in view)
-  __shared__ T Ls[GEMM_TILE][LU_NB + 1];
-  __shared__ T Us[LU_NB][GEMM_TILE + 1];
+  constexpr int NBR = TM / 32, NBC = TN / 32;  // 16 x 16 blocks per wave
+  __shared__ T Ls[TM][LU_NB + 1];
+  __shared__ T Us[LU_NB][TN + 1];
   typedef typename Acc4<T>::type AT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave >> 1) * (TM / 2), wc = (wave & 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
-  AT acc[2][2];
+  AT acc[NBR][NBC];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
@@ -822,20 +828,20 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
   // K in chunks of LU_NB, staged through LDS; the next chunk's loads are issued
   // into registers before the current chunk's matrix-core steps, so their
   // latency overlaps the arithmetic.
-  constexpr int PER = GEMM_TILE * LU_NB / 256;
-  T lreg[PER], ureg[PER];
+  constexpr int PL = TM * LU_NB / 256, PU = LU_NB * TN / 256;
+  T lreg[PL], ureg[PU];
   auto fetch = [&](int kc) {
     const int kb = min(LU_NB, kdim - kc);
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
+    for (int t = 0; t < PL; ++t) {
       const int idx = threadIdx.x + t * 256;
       const int i = idx / LU_NB, qq = idx - (idx / LU_NB) * LU_NB;
       lreg[t] = (r0 + i < rows && qq < kb) ? lsrc[(int64_t)(r0 + i) * lld + kc + qq] : (T)0;
     }
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
+    for (int t = 0; t < PU; ++t) {
       const int idx = threadIdx.x + t * 256;
-      const int qq = idx / GEMM_TILE, jx = idx - (idx / GEMM_TILE) * GEMM_TILE;
+      const int qq = idx / TN, jx = idx - (idx / TN) * TN;
       ureg[t] = (qq < kb && c0 + jx < cols) ? usrc[(int64_t)(kc + qq) * uld + c0 + jx] : (T)0;
     }
   };
@@ -843,31 +849,35 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
   for (int kc = 0; kc < kdim; kc += LU_NB) {
     const int kb = min(LU_NB, kdim - kc);
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
+    for (int t = 0; t < PL; ++t) {
       const int idx = threadIdx.x + t * 256;
       Ls[idx / LU_NB][idx - (idx / LU_NB) * LU_NB] = lreg[t];
-      Us[idx / GEMM_TILE][idx - (idx / GEMM_TILE) * GEMM_TILE] = ureg[t];
+    }
+#pragma unroll
+    for (int t = 0; t < PU; ++t) {
+      const int idx = threadIdx.x + t * 256;
+      Us[idx / TN][idx - (idx / TN) * TN] = ureg[t];
     }
     __syncthreads();
     if (kc + LU_NB < kdim) fetch(kc + LU_NB);
     const int ksteps = (kb + 3) >> 2;
     for (int kk = 0; kk < ksteps; ++kk) {
-      T av[2], bv[2];
+      T av[NBR], bv[NBC];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi) av[bi] = -Ls[wr + bi * 16 + li][kk * 4 + lk];
+      for (int bi = 0; bi < NBR; ++bi) av[bi] = -Ls[wr + bi * 16 + li][kk * 4 + lk];
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) bv[bj] = Us[kk * 4 + lk][wc + bj * 16 + li];
+      for (int bj = 0; bj < NBC; ++bj) bv[bj] = Us[kk * 4 + lk][wc + bj * 16 + li];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_16x16x4(av[bi], bv[bj], acc[bi][bj]);
+        for (int bj = 0; bj < NBC; ++bj) acc[bi][bj] = mfma_16x16x4(av[bi], bv[bj], acc[bi][bj]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
@@ -875,7 +885,9 @@ __device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int 
       }
 }
 
-template <typename T>
+// One tile of a job's update per block (jobs located through the prefix of
+// their tile counts); TM x TN the tile shape the host planned the job with.
+template <typename T, int TM = GEMM_TILE, int TN = GEMM_TILE>
 __global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                  const LuJob* __restrict__ jobs, const int32_t* __restrict__ prefix,
                                                  int n_jobs) {
@@ -883,15 +895,15 @@ __global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ des
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
   const int ncol = jb.c_hi - jb.c_lo;
-  const int ntc = (ncol + GEMM_TILE - 1) / GEMM_TILE;
+  const int ntc = (ncol + TN - 1) / TN;
   const int tile = blockIdx.x - prefix[q];
   const int tr = tile / ntc, tc = tile - (tile / ntc) * ntc;
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
   // view with origin (r_lo, c_lo)
-  tile_update<T>(a + (int64_t)jb.r_lo * lda + jb.c_lo, lda, d.rows - jb.r_lo, ncol, jb.kdim, tr * GEMM_TILE,
-                 tc * GEMM_TILE, a + (int64_t)jb.r_lo * lda + jb.kstart, lda,
-                 a + (int64_t)jb.kstart * lda + jb.c_lo, lda);
+  tile_update<T, TM, TN>(a + (int64_t)jb.r_lo * lda + jb.c_lo, lda, d.rows - jb.r_lo, ncol, jb.kdim, tr * TM,
+                         tc * TN, a + (int64_t)jb.r_lo * lda + jb.kstart, lda,
+                         a + (int64_t)jb.kstart * lda + jb.c_lo, lda);
 }
 
 // Self-test of the matrix-core tile: C (64x64) -= A (64 x kdim) B (kdim x 64), row-major.
