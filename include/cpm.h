@@ -168,10 +168,12 @@ int cpm_precond_chunk(const cpm_ctx* ctx);
  * speed does.
  * cpm_set_precond_tiling re-plans the apply blocks for the tiling's occupancy
  * (ESTATE before cpm_factor or with the chunked apply, EINVAL out of range).
- * cpm_autotune_precond times every tiling `reps` times on the resident factors
- * (HIP events on the context stream), keeps the fastest and returns it in
- * *best (may be NULL); ms (may be NULL) receives the CPM_PRECOND_TILINGS
- * average times in ms.
+ * cpm_autotune_precond times every tiling `reps` times on the resident factors,
+ * each apply taking a vector that an operator apply has just written (as
+ * inside FGMRES; per-launch HIP events on the context stream, the kernel
+ * timers of cpm_kernel_time left unchanged), keeps the fastest and returns it
+ * in *best (may be NULL); ms (may be NULL) receives the CPM_PRECOND_TILINGS
+ * average apply times in ms.
  */
 #define CPM_PRECOND_TILINGS 8
 int cpm_set_precond_tiling(cpm_ctx* ctx, int tiling);

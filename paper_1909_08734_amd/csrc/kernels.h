@@ -149,6 +149,34 @@ __host__ __device__ inline int64_t w_tile_index(int ldw, int cw, int r, int c) {
 // Rows of W_j as stored (t rounded up to whole tiles).
 __host__ __device__ inline int64_t w_rows_stored(int t) { return (int64_t)(t + W_TILE - 1) / W_TILE * W_TILE; }
 
+// vs[c] = sc * v[sigma_j(c)] for c < m, 0 for m <= c < ldw. The index loads
+// of PRECOND_GATHER columns are issued together, then their gathers (an index
+// past m reads entry 0 of the list, whose value is discarded), so a block
+// starts streaming W after two round trips to memory rather than two per
+// column group.
+constexpr int PRECOND_GATHER = 8;
+// (si: the index list from the first staged column; m >= 1 entries of it are
+// real, ncols columns are staged.)
+__device__ __forceinline__ void gather_v(const int32_t* __restrict__ si, int m, int ncols,
+                                         const double* __restrict__ v, double sc, double* __restrict__ vs) {
+  for (int c0 = threadIdx.x; c0 < ncols; c0 += PRECOND_GATHER * PRECOND_THREADS) {
+    int32_t g[PRECOND_GATHER];
+    double x[PRECOND_GATHER];
+#pragma unroll
+    for (int u = 0; u < PRECOND_GATHER; ++u) {
+      const int c = c0 + u * PRECOND_THREADS;
+      g[u] = si[c < m ? c : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < PRECOND_GATHER; ++u) x[u] = v[g[u]];
+#pragma unroll
+    for (int u = 0; u < PRECOND_GATHER; ++u) {
+      const int c = c0 + u * PRECOND_THREADS;
+      if (c < ncols) vs[c] = c < m ? sc * x[u] : 0.0;
+    }
+  }
+}
+
 // Block b serves rows [(b - blk_off) rpb, ...) of subdomain blk_sub[b] (rpb a
 // multiple of W_TILE); the host sizes rpb so that every block streams about
 // the same number of bytes. RPW rows per wave and UNR chunks in flight per
@@ -181,7 +209,7 @@ __global__ __launch_bounds__(PRECOND_THREADS, precond_waves(RPW, UNR)) void k_pr
   const int j = blk_sub[blk];
   const SubDesc d = desc[j];
   const double sc = scale ? *scale : 1.0;  // z = sc * M^{-1} v (M^{-1} is linear)
-  for (int c = threadIdx.x; c < d.ldw; c += PRECOND_THREADS) vs[c] = c < d.m ? sc * v[sig_idx[d.u_off + c]] : 0.0;
+  gather_v(sig_idx + d.u_off, d.m, d.ldw, v, sc, vs);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = (blk - d.blk_off) * d.rpb;
@@ -286,8 +314,7 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
   for (int c0 = 0; c0 < d.ldw; c0 += chunk) {
     const int cw = min(chunk, d.ldw - c0);
     __syncthreads();  // the previous chunk is consumed
-    for (int c = threadIdx.x; c < cw; c += PRECOND_THREADS)
-      vs[c] = c0 + c < d.m ? sc * v[sig_idx[d.u_off + c0 + c]] : 0.0;
+    gather_v(sig_idx + d.u_off + c0, d.m - c0, cw, v, sc, vs);  // c0 < m: ldw - m < 8 <= chunk
     __syncthreads();
     for (int r0 = r_begin + wave * CHUNKED_RPW; r0 < r_end; r0 += NWAVE * CHUNKED_RPW) {
       int rr[CHUNKED_RPW];
@@ -353,10 +380,28 @@ __global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n)) void
   double sc[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) sc[q] = scale ? scale[q * scale_stride] : 1.0;
-  for (int c = threadIdx.x; c < d.ldw; c += PRECOND_THREADS) {
-    const int32_t g = c < d.m ? sig_idx[d.u_off + c] : 0;
+  {  // gather as in gather_v, all NB vectors' loads of a column group together
+    const int32_t* si = sig_idx + d.u_off;
+    for (int c0 = threadIdx.x; c0 < d.ldw; c0 += PRECOND_GATHER * PRECOND_THREADS) {
+      int32_t g[PRECOND_GATHER];
+      double x[NB][PRECOND_GATHER];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) vs[q * d.ldw + c] = c < d.m ? sc[q] * v[q * v_stride + g] : 0.0;
+      for (int u = 0; u < PRECOND_GATHER; ++u) {
+        const int c = c0 + u * PRECOND_THREADS;
+        g[u] = si[c < d.m ? c : 0];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int u = 0; u < PRECOND_GATHER; ++u) x[q][u] = v[q * v_stride + g[u]];
+#pragma unroll
+      for (int u = 0; u < PRECOND_GATHER; ++u) {
+        const int c = c0 + u * PRECOND_THREADS;
+        if (c < d.ldw)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) vs[q * d.ldw + c] = c < d.m ? sc[q] * x[q][u] : 0.0;
+      }
+    }
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
