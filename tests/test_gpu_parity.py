@@ -382,9 +382,16 @@ def test_precond_tilings_are_identical_and_autotune_keeps_results(prec):
     f = ci.rhs_sphere_y20(b.cp[: b.n_act], 1.0)
     ctx.set_precond_tiling(0)
     u0, i0, _ = ctx.solve(f, tol=1e-10, max_iter=300)
+    ctx.set_timing(True)
+    ctx.apply_precond(v, z)
+    before = [ctx.kernel_time(w) for w in (P.TIMER_PRECOND, P.TIMER_EXTEND, P.TIMER_STENCIL)]
     best, ms = ctx.autotune_precond(reps=2)
     say("tiling times (ms)", ms, "best", best)
     assert 0 <= best < P.PRECOND_TILINGS and ctx.precond_tiling() == best and all(x > 0 for x in ms)
+    # the caller's kernel timers are left as they were
+    assert [ctx.kernel_time(w) for w in (P.TIMER_PRECOND, P.TIMER_EXTEND, P.TIMER_STENCIL)] == before
+    assert before[0][1] == 1
+    ctx.set_timing(False)
     u1, i1, _ = ctx.solve(f, tol=1e-10, max_iter=300)
     np.testing.assert_array_equal(u1, u0)
     assert i1[0]["iters"] == i0[0]["iters"]
