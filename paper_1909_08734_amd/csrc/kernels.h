@@ -1102,6 +1102,35 @@ __device__ __forceinline__ void block_partials32(double (&acc)[32], int j0, int 
   __syncthreads();
 }
 
+// acc[u] += X[j0 + u][r] wr for u < nc (nc <= 32), the column scale_col (when
+// in [j0, j0 + nc)) first multiplied by sc and written back. Columns are read
+// eight at a time with all eight loads issued before any use (a group's last
+// columns past nc repeat its first and feed accumulators that are never
+// reported), and the one write comes after the reads, so the loads of a row
+// are in flight together instead of one round trip per column.
+__device__ __forceinline__ void row_dots(double (&acc)[32], double* __restrict__ X, int64_t ldx, int64_t r, int j0,
+                                         int nc, double wr, int scale_col, double sc) {
+  double xs = 0.0;
+#pragma unroll
+  for (int g = 0; g < 32; g += 8) {
+    if (g < nc) {
+      double xv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[q] = X[(int64_t)(j0 + (g + q < nc ? g + q : g)) * ldx + r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double x = xv[q];
+        if (j0 + g + q == scale_col) {
+          x *= sc;
+          xs = x;
+        }
+        acc[g + q] += x * wr;
+      }
+    }
+  }
+  if (scale_col >= j0 && scale_col < j0 + nc) X[(int64_t)scale_col * ldx + r] = xs;
+}
+
 // part[blk][j] = sum over the block's rows of X_j[r] w[r], j < ncols. With
 // `scale_col` >= 0 that column of X is first scaled in place by *scale.
 __global__ __launch_bounds__(RED_THREADS) void k_dots(int64_t n, double* __restrict__ X, int64_t ldx, int ncols,
@@ -1114,20 +1143,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_dots(int64_t n, double* __restr
     double acc[NC];
 #pragma unroll
     for (int u = 0; u < NC; ++u) acc[u] = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
-      const double wr = w[r];
-#pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        if (u < nc) {
-          double x = X[(int64_t)(j0 + u) * ldx + r];
-          if (j0 + u == scale_col) {
-            x *= sc;
-            X[(int64_t)(j0 + u) * ldx + r] = x;
-          }
-          acc[u] += x * wr;
-        }
-      }
-    }
+    for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS)
+      row_dots(acc, X, ldx, r, j0, nc, w[r], scale_col, sc);
     block_partials32(acc, j0, nc, part);
   }
 }
@@ -1164,17 +1181,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_stencil_dots(int64_t n, double 
       } else {
         wr = w[r];
       }
-#pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        if (u < nc) {
-          double x = X[(int64_t)(j0 + u) * ldx + r];
-          if (j0 + u == scale_col) {
-            x *= sc;
-            X[(int64_t)(j0 + u) * ldx + r] = x;
-          }
-          acc[u] += x * wr;
-        }
-      }
+      row_dots(acc, X, ldx, r, j0, nc, wr, scale_col, sc);
     }
     block_partials32(acc, j0, nc, part);
   }
@@ -1234,12 +1241,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const doub
 #pragma unroll
       for (int u = 0; u < NC; ++u) acc[u] = 0.0;
       for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n;
-           r += (int64_t)gridDim.x * RED_THREADS) {
-        const double wr = w[r];
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-          if (u < nc) acc[u] += V[(int64_t)(j0 + u) * ld + r] * wr;
-      }
+           r += (int64_t)gridDim.x * RED_THREADS)
+        row_dots(acc, const_cast<double*>(V), ld, r, j0, nc, w[r], -1, 1.0);  // no column is written
       block_partials32(acc, j0, nc, part);
     }
   } else {
