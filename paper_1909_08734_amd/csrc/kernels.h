@@ -1206,10 +1206,20 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const doub
 #pragma unroll
     for (int u = 0; u < NC; ++u) acc[u] = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; r < n; r += (int64_t)gridDim.x * RED_THREADS) {
+      // s = sum_u V[u][r] h[u] in u order, the row read eight columns at a
+      // time with the group's loads issued before any use (as in row_dots)
       double s = 0.0;
 #pragma unroll
-      for (int u = 0; u < NC; ++u)
-        if (u < ncols) s += V[(int64_t)u * ld + r] * hs[u];
+      for (int g = 0; g < NC; g += 8) {
+        if (g < ncols) {
+          double xv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xv[q] = V[(int64_t)(g + q < ncols ? g + q : g) * ld + r];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (g + q < ncols) s += xv[q] * hs[g + q];
+        }
+      }
       const double wn = w[r] - s;
       w[r] = wn;
       if (mode == 0) {
@@ -1218,9 +1228,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpy_dots(int64_t n, const doub
         // is resident in one round. The compiler barrier keeps the two reads
         // apart.
         asm volatile("" ::: "memory");
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-          if (u < ncols) acc[u] += V[(int64_t)u * ld + r] * wn;
+        row_dots(acc, const_cast<double*>(V), ld, r, 0, ncols, wn, -1, 1.0);  // no column is written
       } else {
         acc[0] += wn * wn;
       }
