@@ -330,7 +330,7 @@ def serve_surfaces():
     }
 
 
-def run_serving(n_requests):
+def run_serving(n_requests, hs=SERVE_HS):
     """Serving leg: prepare the host set-up of every (surface, h), calibrate the
     step and factorisation costs with one factorisation per (surface, h), then
     serve Poisson arrivals at 80% of the stream's capacity."""
@@ -342,9 +342,10 @@ def run_serving(n_requests):
     srv = serve.Server(surfaces, slots=SERVE_SLOTS, prec=P.FP32, restart=RESTART, tol=TOL)
     names = sorted(surfaces)
     t0 = time.time()
-    pairs = [(name, h) for name in names for h in SERVE_HS]
+    pairs = [(name, h) for name in names for h in hs]
     for name, h in pairs:
         srv._base(name, h)
+        log(f"serving: host set-up of {name} h={h:g} done ({time.time() - t0:.1f}s)")
     log(f"serving: host set-up of {len(pairs)} (surface, h) pairs {time.time() - t0:.1f}s")
     # capacity: two steps per (surface, h) near c = 1, run once to factor and
     # once more with the factors cached (the second run is the one measured)
@@ -357,18 +358,22 @@ def run_serving(n_requests):
     t_factor = max(first - srv.makespan, 0.0) / len(calib)  # device time per factorisation
     # arrivals at 80% of the capacity for this request stream: its steps at the
     # cached-factor rate plus one factorisation per distinct (surface, h, c level)
-    probe = serve.poisson_requests(n_requests, 1.0, names, list(SERVE_HS), seed=6)
+    probe = serve.poisson_requests(n_requests, 1.0, names, list(hs), seed=6)
     keys = {srv.key(r) for r in probe} - {srv.key(r) for r in calib}
     busy = sum(r.nsteps for r in probe) * mean_step + len(keys) * t_factor
     rate = 0.8 * n_requests / busy
-    reqs = serve.poisson_requests(n_requests, rate, names, list(SERVE_HS), seed=6)
+    reqs = serve.poisson_requests(n_requests, rate, names, list(hs), seed=6)
     log(f"serving: step {mean_step * 1e3:.1f} ms, factorisation {t_factor:.2f} s, {len(keys)} new keys "
         f"-> rate {rate:.2f}/s, {n_requests} requests")
     torch.cuda.synchronize()
-    out = srv.run(reqs, realtime=True)
+    def progress(done, total):
+        if done % 10 == 0 or done == total:
+            log(f"serving: {done}/{total} requests done")
+    out = srv.run(reqs, realtime=True, progress=progress)
     st = serve.summary(out, srv.makespan)
     st.update({
-        "workload": "mix: sphere, torus(1,0.4), bumpy icosphere (20480 triangles) x h {0.05, 0.025}",
+        "workload": ("mix: sphere, torus(1,0.4), bumpy icosphere (20480 triangles) x h {"
+                     + ", ".join(f"{h:g}" for h in hs) + "}"),
         "arrival_rate_per_s": rate, "slots": SERVE_SLOTS, "c_levels": 16, "steps_per_request": "1-32",
         "factors": "fp32 (fp64 krylov)", "budget_GB": srv.budget / 1e9, "peak_reserved_GB": srv.peak_used / 1e9,
         "evictions": srv.evictions, "factorisations": srv.n_factor - len(calib),
@@ -456,6 +461,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="check the last solve with the oracle")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-hs", type=float, nargs="+", default=list(SERVE_HS),
+                    help="grid spacings of the serving mix (default 0.05 0.025)")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads()),
                     help="benchmark configuration (default: the headline one)")
     ap.add_argument("--no-restart60", dest="restart60", action="store_false",
@@ -514,7 +521,7 @@ def main():
         },
     }
     if args.serve_requests > 0 and default:
-        out["serving"] = run_serving(args.serve_requests)
+        out["serving"] = run_serving(args.serve_requests, tuple(args.serve_hs))
         log(f"serving: {json.dumps(out['serving'])}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, r64["iters_mean"])

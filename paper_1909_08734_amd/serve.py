@@ -240,9 +240,10 @@ class Server:
                 self._release(vec_bytes)
 
     # ---- the loop ----------------------------------------------------------------------------
-    def run(self, requests, realtime=True):
+    def run(self, requests, realtime=True, progress=None):
         """Serve `requests` (arrival times in seconds from now). With realtime=False
-        every request is available at once. Returns a list of Result (request order)."""
+        every request is available at once. `progress(done, total)`, if given, is
+        called after each request. Returns a list of Result (request order)."""
         torch = self.torch
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         results = {r.rid: Result(r.rid, self.key(r), self.key(r)[2], r.arrival if realtime else 0.0) for r in reqs}
@@ -288,7 +289,10 @@ class Server:
                 with self._lock:
                     self._claimed.discard(res.key)
                     state["done"] += 1
+                    done = state["done"]
                     self._lock.notify_all()
+                if progress is not None:
+                    progress(done, len(reqs))
 
         threads = [threading.Thread(target=worker, args=(w,), daemon=True) for w in range(self.slots)]
         for t in threads:
