@@ -356,6 +356,12 @@ def test_one_large_subdomain_uses_chunked_apply_and_is_a_direct_solve():
     u, info, rc = ctx.solve(f, tol=1e-10, max_iter=20, restart=30)
     assert rc == P.OK and info[0]["iters"] <= 2, info
     assert np.linalg.norm(f - A @ u) / np.linalg.norm(f) <= 1.05e-10
+    # the tilings and their autotuner are for the unchunked apply only
+    with pytest.raises(P.CpmError) as e1:
+        ctx.set_precond_tiling(1)
+    with pytest.raises(P.CpmError) as e2:
+        ctx.autotune_precond(reps=1)
+    assert e1.value.code == P.ESTATE and e2.value.code == P.ESTATE
     ctx.close()
 
 
