@@ -376,8 +376,11 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) 
   P.n_blocks = blk;
 }
 
-// Factor workspace of one subdomain (bordered matrix + column-major panel scratch), elements.
-inline int64_t factor_ws_elems(const SubDesc& d) { return (int64_t)d.rows * d.lda + (int64_t)LU_NB * d.rows; }
+// Factor workspace of one subdomain (bordered matrix, column-major panel scratch,
+// I - L11^{-1} of an outer block), elements.
+inline int64_t factor_ws_elems(const SubDesc& d) {
+  return (int64_t)d.rows * d.lda + (int64_t)LU_NB * d.rows + (int64_t)LU_KMAX * LU_KMAX;
+}
 
 // Consecutive groups of subdomains whose factor workspaces fit in `limit` bytes
 // together (a subdomain larger than the limit forms a group of its own).
@@ -416,10 +419,11 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   T* dA = nullptr;
   T* dW = nullptr;
   T* dscr = nullptr;
+  T* dlm = nullptr;  // per subdomain of a group: I - L11^{-1} of the current outer block
   int rc = CPM_OK;
   auto free_group = [&]() {
     hipStreamSynchronize(ctx->stream);
-    dfree(gdesc); dfree(dA); dfree(dscr); dfree(dscr_off); dfree(jobs_buf); dfree(dpre);
+    dfree(gdesc); dfree(dA); dfree(dscr); dfree(dscr_off); dfree(jobs_buf); dfree(dpre); dfree(dlm);
   };
   auto cleanup = [&]() {
     free_group();
@@ -514,7 +518,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     // earlier L columns. After the outer block, the trailing matrix gets the
     // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
     // and one MFMA update with K = LU_KMAX.
-    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4 };
+    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4, L_LINV = 5, L_GEMM_U = 6 };
     struct Launch {
       int kind, k, job_off, n_jobs, units;
     };
@@ -561,16 +565,22 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
           add(L_SWAP, k, sw);
         }
       }
-      std::vector<std::pair<LuJob, int>> ts, gm;
+      // trailing: interchanges, U12 = L11^{-1} U12 (as Lm = I - L11^{-1}, then
+      // U12 -= Lm U12 on matrix cores), then A22 -= L21 U12
+      std::vector<std::pair<LuJob, int>> sw, li, gu, gm;
       for (int j = 0; j < gn; ++j) {
         const SubDesc& d = gd[j];
         if (K0 >= d.n) continue;
         const int K1 = std::min(K0 + LU_KMAX, d.n);
         const LuJob jb{j, K0, K1 - K0, K1, K1, d.cols};
-        ts.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
+        sw.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
+        li.push_back({LuJob{j, K0, K1 - K0, 0, 0, LU_KMAX}, LU_KMAX / TRSM_COLS});
+        gu.push_back({LuJob{j, K0, K1 - K0, K0, K1, d.cols}, cdiv(d.cols - K1, GEMM_TILE)});
         gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE_R) * cdiv(d.cols - K1, GEMM_TILE)});
       }
-      add(L_SWAP_TRSM, K0, ts);
+      add(L_SWAP, K0, sw);
+      add(L_LINV, K0, li);
+      add(L_GEMM_U, K0, gu);
       add(L_GEMM_TRAIL, K0, gm);
     }
     FCHK(upload(ctx, &jobs_buf, jobs));
@@ -584,6 +594,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     }
     FCHK(upload(ctx, &dscr_off, scr_off));
     FHIP(hipMalloc((void**)&dscr, scr_total * sizeof(T)));
+    FHIP(hipMalloc((void**)&dlm, (size_t)gn * LU_KMAX * LU_KMAX * sizeof(T)));
     for (const Launch& L : lplan) {
       const LuJob* jb = jobs_buf + L.job_off;
       const int32_t* pre = dpre + L.job_off;
@@ -595,6 +606,12 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
         case L_SWAP:
           k_lu_swap_trsm<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, gipiv, jb, pre, L.n_jobs,
                                                                      L.kind == L_SWAP_TRSM ? 1 : 0);
+          break;
+        case L_LINV:
+          k_lu_linv<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm);
+          break;
+        case L_GEMM_U:  // not in the LU-update timer, which covers the Schur-complement updates
+          k_lu_gemm_u<T><<<L.units, 256, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm);
           break;
         case L_GEMM_TRAIL:
           launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE_R, GEMM_TILE>, dim3(L.units), dim3(256), 0,

@@ -849,10 +849,12 @@ constexpr int GEMM_TILE_R = 128;  // rows of the trailing-update tile (columns: 
 // MFMA steps in the same order whatever the tile shape, so all shapes give
 // the same bits.
 template <typename T, int TM = GEMM_TILE, int TN = GEMM_TILE>
-__device__ __forceinline__ void tile_update(T* __restrict__ a, int64_t lda, int rows, int cols, int kdim,
+__device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int cols, int kdim,
                                             int r0, int c0, const T* __restrict__ lsrc, int64_t lld,
-                                            const T* __restrict__ usrc, int64_t uld) {
-  // C[r0.., c0..] -= Lsrc[r0.., 0..kdim) * Usrc[0..kdim, c0..]   (C = a, rows x cols in view)
+                                            const T* usrc, int64_t uld) {
+  // C[r0.., c0..] -= Lsrc[r0.., 0..kdim) * Usrc[0..kdim, c0..]   (C = a, rows x cols in view).
+  // Usrc may be C itself when one tile covers all kdim rows (TM >= kdim, r0 = 0):
+  // every read of Usrc comes before the tile's only write of C, at the end.
   constexpr int NBR = TM / 32, NBC = TN / 32;  // 16 x 16 blocks per wave
   __shared__ T Ls[TM][LU_NB + 1];
   __shared__ T Us[LU_NB][TN + 1];
@@ -949,6 +951,49 @@ __global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ des
   tile_update<T, TM, TN>(a + (int64_t)jb.r_lo * lda + jb.c_lo, lda, d.rows - jb.r_lo, ncol, jb.kdim, tr * TM,
                          tc * TN, a + (int64_t)jb.r_lo * lda + jb.kstart, lda,
                          a + (int64_t)jb.kstart * lda + jb.c_lo, lda);
+}
+
+// The unit-lower solve of a full outer block as a matrix-core product: first
+// Lm = I - L11^{-1} (strictly lower; L11^{-1} by forward substitution on the
+// identity, 64 columns per block), written row-major, LU_KMAX x LU_KMAX per
+// subdomain; then U12 -= Lm U12 in place (k_lu_gemm_u), i.e. U12 = L11^{-1} U12.
+template <typename T>
+__global__ __launch_bounds__(TRSM_COLS) void k_lu_linv(const SubDesc* __restrict__ desc, const T* __restrict__ A,
+                                                       const LuJob* __restrict__ jobs,
+                                                       const int32_t* __restrict__ prefix, int n_jobs,
+                                                       T* __restrict__ lm) {
+  __shared__ T X[LU_KMAX][TRSM_COLS];
+  const int q = find_job(prefix, n_jobs, blockIdx.x);
+  const LuJob jb = jobs[q];
+  const SubDesc d = desc[jb.j];
+  const int t = threadIdx.x;
+  const int col = (blockIdx.x - prefix[q]) * TRSM_COLS + t;  // < LU_KMAX
+  const int kd = jb.kdim;
+  const int64_t lda = d.lda;
+  const T* l = A + d.a_off + (int64_t)jb.kstart * lda + jb.kstart;
+  for (int i = 0; i < kd; ++i) X[i][t] = i == col ? (T)1 : (T)0;
+  for (int qq = 0; qq < kd; ++qq) {
+    const T xq = X[qq][t];
+    for (int i = qq + 1; i < kd; ++i) X[i][t] -= l[(int64_t)i * lda + qq] * xq;
+  }
+  T* out = lm + (int64_t)jb.j * LU_KMAX * LU_KMAX;
+  for (int i = 0; i < LU_KMAX; ++i)
+    out[(int64_t)i * LU_KMAX + col] = (i < kd && col < kd && i > col) ? -X[i][t] : (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_gemm_u(const SubDesc* __restrict__ desc, T* __restrict__ A,
+                                                   const LuJob* __restrict__ jobs,
+                                                   const int32_t* __restrict__ prefix, int n_jobs,
+                                                   const T* __restrict__ lm) {
+  const int q = find_job(prefix, n_jobs, blockIdx.x);
+  const LuJob jb = jobs[q];
+  const SubDesc d = desc[jb.j];
+  const int ncol = jb.c_hi - jb.c_lo;
+  const int tc = blockIdx.x - prefix[q];
+  T* u = A + d.a_off + (int64_t)jb.kstart * d.lda + jb.c_lo;  // the U12 block, rows [kstart, kstart + kdim)
+  tile_update<T, LU_KMAX, GEMM_TILE>(u, d.lda, jb.kdim, ncol, jb.kdim, 0, tc * GEMM_TILE,
+                                     lm + (int64_t)jb.j * LU_KMAX * LU_KMAX, LU_KMAX, u, d.lda);
 }
 
 // Self-test of the matrix-core tile: C (64x64) -= A (64 x kdim) B (kdim x 64), row-major.
