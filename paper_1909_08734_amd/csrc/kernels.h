@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
 // Batched right-looking LU with partial pivoting on the augmented matrices
 // (pivots searched in the first n_j rows only), panel width NB.
 // ---------------------------------------------------------------------------
-constexpr int LU_NB = 32;
+constexpr int LU_NB = 32;  // panel width
 constexpr int PANEL_THREADS = 1024;
 // columns of a row updated together in the panel (fewer in FP64: registers)
 template <typename T>
@@ -771,7 +771,8 @@ struct LuJob {
   int32_t j, kstart, kdim, r_lo, c_lo, c_hi;
 };
 
-constexpr int LU_KMAX = 4 * LU_NB;  // outer block width (panels caught up left-looking inside it)
+constexpr int LU_KMAX = 128;  // outer block width (panels caught up left-looking inside it)
+static_assert(LU_KMAX % LU_NB == 0, "whole panels per outer block");
 constexpr int TRSM_COLS = 64;
 
 // Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
 }
 
 // Trailing update on matrix cores: C -= Lsrc * Usrc for one 64x64 tile of C,
-// K = kdim in chunks of LU_NB staged through LDS; C is read and written once.
+// K = kdim in chunks of GEMM_KC staged through LDS; C is read and written once.
 // 16x16x4 operand layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k. Result D[i][j], j = lane % 16: for f32 element e of lane l holds
 // row 4(l/16) + e; for f64 it holds row l/16 + 4e (measured on gfx950).
@@ -841,6 +842,7 @@ struct Acc4<float> {
   __device__ static int row(int lk, int e) { return 4 * lk + e; }
 };
 
+constexpr int GEMM_KC = 32;      // K chunk of the matrix-core updates staged through LDS
 constexpr int GEMM_TILE = 64;
 constexpr int GEMM_TILE_R = 128;  // rows of the trailing-update tile (columns: GEMM_TILE)
 
@@ -856,8 +858,8 @@ __device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int col
   // Usrc may be C itself when one tile covers all kdim rows (TM >= kdim, r0 = 0):
   // every read of Usrc comes before the tile's only write of C, at the end.
   constexpr int NBR = TM / 32, NBC = TN / 32;  // 16 x 16 blocks per wave
-  __shared__ T Ls[TM][LU_NB + 1];
-  __shared__ T Us[LU_NB][TN + 1];
+  __shared__ T Ls[TM][GEMM_KC + 1];
+  __shared__ T Us[GEMM_KC][TN + 1];
   typedef typename Acc4<T>::type AT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * (TM / 2), wc = (wave & 1) * (TN / 2);
@@ -872,17 +874,17 @@ __device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int col
         const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
         acc[bi][bj][i] = (rr < rows && cc < cols) ? a[(int64_t)rr * lda + cc] : (T)0;
       }
-  // K in chunks of LU_NB, staged through LDS; the next chunk's loads are issued
+  // K in chunks of GEMM_KC, staged through LDS; the next chunk's loads are issued
   // into registers before the current chunk's matrix-core steps, so their
   // latency overlaps the arithmetic.
-  constexpr int PL = TM * LU_NB / 256, PU = LU_NB * TN / 256;
+  constexpr int PL = TM * GEMM_KC / 256, PU = GEMM_KC * TN / 256;
   T lreg[PL], ureg[PU];
   auto fetch = [&](int kc) {
-    const int kb = min(LU_NB, kdim - kc);
+    const int kb = min(GEMM_KC, kdim - kc);
 #pragma unroll
     for (int t = 0; t < PL; ++t) {
       const int idx = threadIdx.x + t * 256;
-      const int i = idx / LU_NB, qq = idx - (idx / LU_NB) * LU_NB;
+      const int i = idx / GEMM_KC, qq = idx - (idx / GEMM_KC) * GEMM_KC;
       lreg[t] = (r0 + i < rows && qq < kb) ? lsrc[(int64_t)(r0 + i) * lld + kc + qq] : (T)0;
     }
 #pragma unroll
@@ -893,12 +895,12 @@ __device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int col
     }
   };
   if (kdim > 0) fetch(0);
-  for (int kc = 0; kc < kdim; kc += LU_NB) {
-    const int kb = min(LU_NB, kdim - kc);
+  for (int kc = 0; kc < kdim; kc += GEMM_KC) {
+    const int kb = min(GEMM_KC, kdim - kc);
 #pragma unroll
     for (int t = 0; t < PL; ++t) {
       const int idx = threadIdx.x + t * 256;
-      Ls[idx / LU_NB][idx - (idx / LU_NB) * LU_NB] = lreg[t];
+      Ls[idx / GEMM_KC][idx - (idx / GEMM_KC) * GEMM_KC] = lreg[t];
     }
 #pragma unroll
     for (int t = 0; t < PU; ++t) {
@@ -906,7 +908,7 @@ __device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int col
       Us[idx / TN][idx - (idx / TN) * TN] = ureg[t];
     }
     __syncthreads();
-    if (kc + LU_NB < kdim) fetch(kc + LU_NB);
+    if (kc + GEMM_KC < kdim) fetch(kc + GEMM_KC);
     const int ksteps = (kb + 3) >> 2;
     for (int kk = 0; kk < ksteps; ++kk) {
       T av[NBR], bv[NBC];
