@@ -662,15 +662,17 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
       ipiv[d.u_off + k + jj] = k + (piv < 0 ? jj : piv);
       if (piv < 0 && info[j] == 0) info[j] = k + jj + 1;
     }
-    if (piv >= 0 && piv != jj)
-      for (int c = t; c < kb; c += PANEL_THREADS) {
-        T* pc = P + (int64_t)c * rows;
-        const T tmp = pc[jj];
-        pc[jj] = pc[piv];
-        pc[piv] = tmp;
+    // interchange rows jj and piv (thread c: column c) and keep the new row jj
+    if (t < kb) {
+      T* pc = P + (int64_t)t * rows;
+      const T rj = pc[jj];
+      const T rp = piv >= 0 ? pc[piv] : rj;
+      if (piv >= 0 && piv != jj) {
+        pc[jj] = rp;
+        pc[piv] = rj;
       }
-    __syncthreads();
-    if (t < kb) prow[t] = P[(int64_t)t * rows + jj];
+      prow[t] = rp;
+    }
     __syncthreads();
     const T pv = prow[jj];
     best = -1.0;
