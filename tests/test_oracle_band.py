@@ -18,17 +18,10 @@ def _paper_counts():
         return json.load(fh)
 
 
-@pytest.mark.parametrize("inv_h", [50, 100])
+@pytest.mark.parametrize("inv_h", [50, 100, 125, 175, 200, 250])
 def test_paper_active_counts(inv_h):
-    g = _paper_counts()
-    b = oracle.build_band(ci.Sphere(), 1.0 / inv_h, g["p"], [-1.2] * 3, [1.2] * 3,
-                          band_factor=g["band_factor"])
-    assert b.n_act == g["counts"][str(inv_h)]
-
-
-@pytest.mark.slow
-@pytest.mark.parametrize("inv_h", [125, 175, 200, 250])
-def test_paper_active_counts_fine(inv_h):
+    """The six sphere band sizes printed in Sections 6.2 and 6.6 (p = 2); the
+    finest take about a minute each."""
     g = _paper_counts()
     b = oracle.build_band(ci.Sphere(), 1.0 / inv_h, g["p"], [-1.2] * 3, [1.2] * 3,
                           band_factor=g["band_factor"])
