@@ -14,13 +14,19 @@ precisions are measured: `value` is the plain FP64 form, the FP32-factor form
 
 A serving leg follows (`serving` in the output): a request loop over a mix of
 surfaces (unit sphere, torus R = 1, r = 0.4, bumpy icosphere with 20480
-triangles) and grid spacings h in {0.05, 0.025}, c log-normal on [0.1, 10]
-quantised to 16 levels, 1-32 implicit steps per request, cached FP32 factors,
+triangles) and grid spacings h in {0.05, 0.025, 0.0125}, c log-normal on
+[0.1, 10], 1-32 implicit steps per request, cached FP32 factors of 16
+quantised c levels preconditioning the operator of the request's own c,
 admission by device-memory footprint, Poisson arrivals at 80% of the capacity
 for the stream (its steps at the cached-factor rate plus one factorisation per
 new key, both measured just before); it reports p50/p99 latency (arrival to
-last step) and solves/s. The same K right-hand sides are also solved in
-lockstep batches (`batched`), which share each pass over the factors.
+last step), the cache hit rate and solves/s, overall and per h. The same K
+right-hand sides are also solved in lockstep batches (`batched`), which share
+each pass over the factors.
+
+Every solution of the first right-hand side is compared with the oracle's
+direct solution (`err_vs_oracle`), and the CPU baseline is one full oracle
+solve on the host's cores.
 
 Prints one JSON line.
 """
@@ -184,10 +190,36 @@ def operator_roofline(ctx, torch, P, na, ng, reps=50, degree=3):
     return out
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "sphere_h0025_seed1_solution.npz")
+
+
+def golden_solution(wl_name, na):
+    """The stored direct solution u = A^{-1} f of the headline problem's first
+    right-hand side (seed 1), written by the oracle (tests/golden/); None for
+    other workloads."""
+    if wl_name != DEFAULT_WORKLOAD or not os.path.exists(GOLDEN):
+        return None
+    with np.load(GOLDEN, allow_pickle=False) as z:
+        u = z["u"]
+    return u if len(u) == na else None
+
+
+def err_vs(u, ref):
+    return {"max_rel": float(np.abs(u - ref).max() / np.abs(ref).max()),
+            "l2_rel": float(np.linalg.norm(u - ref) / np.linalg.norm(ref))}
+
+
 def run_gpu(args, wl):
     import torch
     import paper_1909_08734_amd as P
 
+    # all device work on one side stream (the library follows torch's current stream)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        return _run_gpu(args, wl, torch, P)
+
+
+def _run_gpu(args, wl, torch, P):
     ctx = P.Context(0)
     t0 = time.time()
     surf = wl["surface"]()
@@ -197,9 +229,10 @@ def run_gpu(args, wl):
     cp = ctx.band_arrays(3)["cp"][:na]
     log(f"band {time.time() - t0:.1f}s  N_A={na} N_G={ng}")
     nrhs = args.warmup + args.steps
-    F = np.stack([wl["rhs"](cp, q) for q in range(nrhs)])
+    F = np.stack([wl["rhs"](cp, q) for q in range(max(nrhs, 1))])
     f_dev = torch.from_numpy(F).cuda()
     u_dev = torch.zeros_like(f_dev)
+    u_gold = golden_solution(args.workload, na)
     torch.cuda.synchronize()
     op = operator_roofline(ctx, torch, P, na, ng)
     log(f"operator apply: {json.dumps(op)}")
@@ -302,6 +335,16 @@ def run_gpu(args, wl):
                 w60 = time.perf_counter() - t0
                 r["restart60"] = {"solves_per_s": args.steps / w60, "ms_per_solve": 1e3 * w60 / args.steps,
                                   "iters_mean": float(np.mean(its60))}
+            if u_gold is not None:
+                # error of the first right-hand side's solution against the
+                # oracle's direct solution, at the benchmark tolerance and at 1e-12
+                # (outside the timed region)
+                r["err_vs_oracle"] = {"rhs": "seed 1", "reference": "oracle sparse direct solve"}
+                for t_name, t in (("tol_" + format(tol, "g"), tol), ("tol_1e-12", 1e-12)):
+                    ue = torch.zeros_like(f_dev[0])
+                    info, rc = ctx.solve_device(f_dev[0], ue, tol=t, max_iter=3000, restart=RESTART)
+                    r["err_vs_oracle"][t_name] = dict(err_vs(ue.cpu().numpy(), u_gold),
+                                                      relres_true=info[0]["relres_true"], iters=info[0]["iters"])
             res[a_name][prec_name] = r
             log(f"{a_name} {prec_name}: {json.dumps(r)}")
             if args.check:
@@ -315,8 +358,9 @@ def run_gpu(args, wl):
     return res, na, op
 
 
-SERVE_HS = (0.05, 0.025)
+SERVE_HS = (0.05, 0.025, 0.0125)
 SERVE_SLOTS = 4
+SERVE_REQUESTS = 48
 
 
 def serve_surfaces():
@@ -371,9 +415,20 @@ def run_serving(n_requests, hs=SERVE_HS):
             log(f"serving: {done}/{total} requests done")
     out = srv.run(reqs, realtime=True, progress=progress)
     st = serve.summary(out, srv.makespan)
+    by_h = {}
+    for h in hs:
+        sub = [r for r in out if r.key[1] == float(h)]
+        if sub:
+            lat = np.array([r.latency for r in sub]) * 1e3
+            by_h[format(h, "g")] = {"requests": len(sub), "solves": int(sum(len(r.iters) for r in sub)),
+                                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                                    "hit_rate": float(np.mean([r.hit for r in sub])),
+                                    "mean_iters": float(np.mean([np.mean(r.iters) for r in sub if r.iters]))}
     st.update({
-        "workload": ("mix: sphere, torus(1,0.4), bumpy icosphere (20480 triangles) x h {"
+        "workload": (f"{n_requests} Poisson-arrival requests (a bounded sample of the 2000 of the configuration), "
+                     "mix: sphere, torus(1,0.4), bumpy icosphere (20480 triangles) x h {"
                      + ", ".join(f"{h:g}" for h in hs) + "}"),
+        "by_h": by_h,
         "arrival_rate_per_s": rate, "slots": SERVE_SLOTS, "c_levels": 16, "steps_per_request": "1-32",
         "factors": "fp32 (fp64 krylov)", "budget_GB": srv.budget / 1e9, "peak_reserved_GB": srv.peak_used / 1e9,
         "evictions": srv.evictions, "factorisations": srv.n_factor - len(calib),
@@ -385,72 +440,88 @@ def run_serving(n_requests, hs=SERVE_HS):
     return st
 
 
-def cpu_baseline(wl, gpu_iters):
-    """The oracle as it stands, timed on a bounded sample of the same workload:
-    local LU solves of 4 subdomains (scaled to all of them), one CSR operator
-    apply and one modified Gram-Schmidt pass at the mean Krylov depth; solves/s
-    = 1 / (iterations x per-iteration time), iterations taken from the GPU run."""
+def host_cores():
+    """Threads the host leg may use: the scheduler's CPU set, capped by
+    OMP_NUM_THREADS when set (the GPU machine sets it to the CPU share of its GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(wl, gpu_iters, u_gold=None):
+    """The oracle as it stands, timed on the host on one full solve of the
+    workload's first right-hand side: every subdomain's local matrix assembled
+    and LU-factored (oracle.schwarz.Preconditioner), then oracle.fgmres
+    (FGMRES(30), tol as on the GPU) with the oracle's Schwarz preconditioner.
+    The oracle's arithmetic is unchanged; its per-subdomain objects are spread
+    over a thread pool of `cores` threads (one BLAS thread each), for the
+    factorisation and for each preconditioner apply, whose LAPACK calls run
+    without the interpreter lock. The one-thread figure times one apply and
+    one operator product on one thread, times the iteration count."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
     import oracle
     from oracle import schwarz
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    h, c, n_sub = wl["h"], wl["c"], wl["n_sub"]
+    cores = host_cores()
+    h, c, n_sub, tol = wl["h"], wl["c"], wl["n_sub"], wl["tol"]
+    _, alpha, alpha_x = wl["alphas"][0]
+    t0 = time.perf_counter()
     b = oracle.build_band(wl["surface"](), h, 3, [-2.0] * 3, [2.0] * 3)
     A = oracle.stabilized_operator(b, c)
-    _, alpha, alpha_x = wl["alphas"][0]
     if wl["method"] == "octant":
         part = oracle.octant_partition(b)
     else:
         part = oracle.rcb_partition(b, n_sub, weights=wl["weights"]() if wl["weights"] else None)
-    sample = sorted({0, n_sub // 3, (2 * n_sub) // 3, n_sub - 1})
-    dec = schwarz.decompose(b, part, wl["overlap"], wl["kind"], alpha=alpha, alpha_cross=alpha_x,
-                            only=set(sample))
-    t0 = time.perf_counter()
-    M = schwarz.Preconditioner(b, dec, c, subs=sample)
-    factor_s = time.perf_counter() - t0
-    v = np.random.default_rng(0).standard_normal(b.n_act)
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        M.apply(v)
-    t_pre = (time.perf_counter() - t0) / reps * (n_sub / len(sample))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        A @ v
-    t_op = (time.perf_counter() - t0) / reps
-    k = RESTART // 2
-    V = np.random.default_rng(1).standard_normal((k + 1, b.n_act))
-    t0 = time.perf_counter()
-    w = v.copy()
-    for i in range(k + 1):
-        w = w - np.dot(V[i], w) * V[i]
-    t_mgs = time.perf_counter() - t0
-    per_iter = t_pre + t_op + t_mgs
-    # the same per-iteration work on one thread
-    try:
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
+    dec = schwarz.decompose(b, part, wl["overlap"], wl["kind"], alpha=alpha, alpha_cross=alpha_x)
+    setup_s = time.perf_counter() - t0
+    na = b.n_act
+    f = wl["rhs"](b.cp[:na], 0)
+    with threadpool_limits(limits=1), ThreadPoolExecutor(cores) as pool:
+        t0 = time.perf_counter()
+        parts = list(pool.map(lambda j: schwarz.Preconditioner(b, dec, c, subs=[j]), range(n_sub)))
+        factor_s = time.perf_counter() - t0
+
+        def apply(v):
+            z = np.empty(na)
+            for j, zj in enumerate(pool.map(lambda M: M.apply(v), parts)):
+                t = dec.subs[j].tilde
+                z[t] = zj[t]
+            return z
+
+        t0 = time.perf_counter()
+        u, info = oracle.fgmres(lambda x: A @ x, f, apply, tol=tol, restart=RESTART, max_iter=3000)
+        solve_s = time.perf_counter() - t0
+        # one thread: one preconditioner apply and one operator product
+        v = np.random.default_rng(0).standard_normal(na)
+        t0 = time.perf_counter()
+        for M in parts:
             M.apply(v)
-            t_pre1 = (time.perf_counter() - t0) * (n_sub / len(sample))
-        one = 1.0 / (gpu_iters * (t_pre1 + t_op + t_mgs))
-    except Exception:
-        one = None
+        A @ v
+        per_iter_1 = time.perf_counter() - t0
+    del parts
     host = ""
     try:
         with open("/proc/cpuinfo") as fh:
             host = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": 1.0 / (gpu_iters * per_iter), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "value_1_thread": one, "host": host,
-            "sample": (f"oracle dense-LU local solves of {len(sample)}/{n_sub} subdomains scaled "
-                       f"x{n_sub / len(sample):g} ({t_pre * 1e3:.0f} ms/apply), CSR A.v ({t_op * 1e3:.1f} ms), "
-                       f"one MGS pass at depth {k} ({t_mgs * 1e3:.1f} ms), x {gpu_iters:.1f} iterations; "
-                       f"oracle factor of the {len(sample)} sampled subdomains {factor_s:.1f}s (excluded)")}
+    out = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "factor_s": factor_s, "solve_s": solve_s, "iters": info["iters"], "relres": info["relres"],
+           "setup_s": setup_s, "value_1_thread": 1.0 / (info["iters"] * per_iter_1), "host": host,
+           "sample": (f"one full oracle solve of the first right-hand side ({n_sub} dense local LUs, "
+                      f"FGMRES({RESTART}) to {tol:g}) on {cores} threads; factorisation {factor_s:.1f} s "
+                      f"reported apart; 1-thread value = 1 / (iterations x one apply + operator product on "
+                      f"one thread)")}
+    if u_gold is not None and len(u_gold) == na:
+        out["err_vs_direct"] = err_vs(u, u_gold)
+    return out
 
 
 def main():
@@ -460,9 +531,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="check the last solve with the oracle")
-    ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS,
+                    help=f"requests in the serving leg (0: skip; default {SERVE_REQUESTS})")
     ap.add_argument("--serve-hs", type=float, nargs="+", default=list(SERVE_HS),
-                    help="grid spacings of the serving mix (default 0.05 0.025)")
+                    help="grid spacings of the serving mix (default 0.05 0.025 0.0125)")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads()),
                     help="benchmark configuration (default: the headline one)")
     ap.add_argument("--no-restart60", dest="restart60", action="store_false",
@@ -524,7 +596,7 @@ def main():
         out["serving"] = run_serving(args.serve_requests, tuple(args.serve_hs))
         log(f"serving: {json.dumps(out['serving'])}")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, r64["iters_mean"])
+        out["cpu_baseline"] = cpu_baseline(wl, r64["iters_mean"], golden_solution(args.workload, na))
     print(json.dumps(out), flush=True)
 
 

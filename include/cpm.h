@@ -76,13 +76,37 @@ typedef struct {
   double relres_true;   /* ||f - A u||_2 / ||f||_2 at exit, computed on the device */
   double relres_est;    /* GMRES residual estimate / ||f||_2 at exit */
   double ms;            /* wall time of the solve on the device stream */
+  /* Device time of the solve's phases in ms, filled while per-kernel timing
+   * is on (cpm_set_timing), else 0: [0] preconditioner applies (eq. algRAS),
+   * [1] operator applies (extension and stencil, Section 2.1, including the
+   * true residual at each restart; the stencil carries the first
+   * Gram-Schmidt pass's dot products), [2] orthogonalisation, norms and the
+   * Givens least-squares updates, [3] solution updates and vector copies.
+   * For a lockstep batch these are the batch's totals. */
+  double phase_ms[4];
 } cpm_solve_info;
 
 /* Create a context on HIP device `device` (>= 0). device < 0 gives a
  * host-only context: set-up and queries work, factor/solve return
- * CPM_EDEVICE. The context creates and owns one HIP stream. */
+ * CPM_EDEVICE. The context creates and owns one HIP stream, which it uses
+ * until cpm_set_stream names another. */
 int cpm_create(cpm_ctx** out, int device);
 void cpm_destroy(cpm_ctx* ctx);
+
+/*
+ * Stream for the context's device work. caller != 0: the caller's HIP stream
+ * `hip_stream` on the context's device (NULL = the device's null stream); it
+ * is borrowed, not destroyed, and must stay valid while the context uses it.
+ * caller == 0: the context's own stream again (hip_stream ignored). Device
+ * work a call issues is queued on that stream after whatever the caller queued
+ * there before, so device inputs written by earlier work on the same stream
+ * need no device-wide synchronisation; calls still return after their own
+ * device work has finished (they synchronise that stream only). On the null
+ * stream FGMRES iterations are launched directly (HIP graphs cannot be
+ * captured there). EDEVICE for a host-only context. Takes effect at the next
+ * call.
+ */
+int cpm_set_stream(cpm_ctx* ctx, int caller, void* hip_stream);
 
 /*
  * New context on `device` (as cpm_create) holding a copy of src's host
@@ -97,8 +121,9 @@ int cpm_clone(const cpm_ctx* src, int device, cpm_ctx** out);
 
 /*
  * Thread use: distinct contexts may be used concurrently from different host
- * threads (each has its own stream and device memory); one context must not
- * be used by two threads at once.
+ * threads (each has its own device memory and, unless cpm_set_stream names a
+ * shared one, its own stream); one context must not be used by two threads at
+ * once.
  */
 const char* cpm_last_error(const cpm_ctx* ctx);
 
@@ -117,6 +142,20 @@ int cpm_build_band(cpm_ctx* ctx, cpm_cp_fn fn, void* user, const double lo[3],
 
 /* Operator A = c I - Delta_S^h (Section 2.1). EINVAL if c <= 0 or not finite. */
 int cpm_build_operator(cpm_ctx* ctx, double c);
+
+/*
+ * Change c in the operator A = c I - Delta_S^h (Section 2.1) and keep the
+ * factors: they stay those of the c they were made for (c_f), so the
+ * preconditioner becomes the Schwarz operator of c_f I - Delta_S^h, and the
+ * FGMRES of cpm_solve* still stops on the true residual of the new A (c only
+ * moves the diagonal, c + 6/h^2). For serving many values of c from a few
+ * cached factorisations. ESTATE before cpm_build_operator; the state is
+ * unchanged (factored stays factored).
+ * EINVAL if c <= 0 or not finite. cpm_factor_c reports c_f (0 before any
+ * factorisation).
+ */
+int cpm_set_operator_c(cpm_ctx* ctx, double c);
+double cpm_factor_c(const cpm_ctx* ctx);
 
 /*
  * Overlapping decomposition (Sections 3, 4, 5).
@@ -272,9 +311,13 @@ size_t cpm_footprint_bytes(const cpm_ctx* ctx);
 int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident,
                            size_t* peak);
 
-/* Per-kernel timing with HIP events on the context stream (off by default).
- * which: 0 = preconditioner apply, 1 = extension apply, 2 = stencil apply,
- * 3 = LU trailing update. total_ms and launches since the last reset. */
+/* Per-kernel timing with HIP events on the context stream (off by default;
+ * the events ride on the kernel dispatches, no extra packets). which:
+ * 0 = preconditioner apply, 1 = extension apply, 2 = stencil apply (also in
+ * its fused form with the first Gram-Schmidt dot products), 3 = LU trailing
+ * update, 4 = orthogonalisation, norms and least squares, 5 = solution
+ * updates and vector copies. total_ms and launches since the last reset. */
+#define CPM_N_TIMERS 6
 int cpm_set_timing(cpm_ctx* ctx, int on);
 int cpm_kernel_time(cpm_ctx* ctx, int which, double* total_ms, int64_t* launches);
 

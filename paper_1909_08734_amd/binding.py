@@ -3,7 +3,10 @@
 Every computation runs in the shared library ``libcpm.so`` built for gfx950;
 importing this module fails loudly when the library has not been built.
 PyTorch is used only to hand device buffers (``torch.Tensor`` on a HIP
-device) to the library.
+device) and its current HIP stream to the library: a device context queues
+its work on torch's current stream of its device (``cpm_set_stream``), after
+whatever torch queued there before, so no device-wide synchronisation is
+needed around the calls.
 """
 
 from __future__ import annotations
@@ -22,7 +25,8 @@ FP64, FP32 = 0, 1
 PART_OCTANT, PART_RCB, PART_GRAPH = 0, 1, 2
 PART_ALIGN = 16
 PRECOND_TILINGS = 8  # CPM_PRECOND_TILINGS
-TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM = 0, 1, 2, 3
+TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM, TIMER_KRYLOV, TIMER_UPDATE = 0, 1, 2, 3, 4, 5
+PHASES = ("precond", "operator", "orthogonalisation", "update")  # cpm_solve_info.phase_ms
 
 _NAMES = {OK: "OK", ENOTCONV: "ENOTCONV", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM",
           ESINGULAR: "ESINGULAR", EDEVICE: "EDEVICE", ECALLBACK: "ECALLBACK"}
@@ -34,10 +38,12 @@ CP_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POI
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("status", C.c_int32),
                 ("reserved", C.c_int32), ("relres_true", C.c_double), ("relres_est", C.c_double),
-                ("ms", C.c_double)]
+                ("ms", C.c_double), ("phase_ms", C.c_double * 4)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "phase_ms")}
+        d["phase_ms"] = dict(zip(PHASES, list(self.phase_ms)))
+        return d
 
 
 class CpmError(RuntimeError):
@@ -52,6 +58,9 @@ _SIGS = {
     "cpm_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "cpm_destroy": (None, [C.c_void_p]),
     "cpm_clone": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    "cpm_set_stream": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "cpm_set_operator_c": (C.c_int, [C.c_void_p, C.c_double]),
+    "cpm_factor_c": (C.c_double, [C.c_void_p]),
     "cpm_last_error": (C.c_char_p, [C.c_void_p]),
     "cpm_build_band": (C.c_int, [C.c_void_p, CP_FN, C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.c_double, C.c_int, C.c_double]),
@@ -123,11 +132,6 @@ def _dev_ptr(t, dtype="float64"):
     return C.c_void_p(t.data_ptr())
 
 
-def _sync_torch():
-    import torch
-    torch.cuda.synchronize()
-
-
 def selftest_tile(a, b, c, prec=FP64, device=0):
     """c - a @ b on one 64x64 matrix-core tile of the LU trailing update (returns new c)."""
     kb = a.shape[1]
@@ -156,6 +160,17 @@ class Context:
         self._h = _handle
         self._cb = None
         self.device = int(device)
+        self._stream = None  # the HIP stream last handed to the library
+
+    def _bind_stream(self):
+        """Queue the context's device work on torch's current stream of its device."""
+        if self.device < 0:
+            return
+        import torch
+        s = int(torch.cuda.current_stream(self.device).cuda_stream)
+        if s != self._stream:
+            self._check(self._L.cpm_set_stream(self._h, 1, C.c_void_p(s)), "set_stream")
+            self._stream = s
 
     def clone(self, device=0):
         """New context on `device` with a copy of this one's band, c and partition."""
@@ -209,6 +224,13 @@ class Context:
     def build_operator(self, c):
         self._check(self._L.cpm_build_operator(self._h, float(c)), "build_operator")
 
+    def set_operator_c(self, c):
+        """Change c in the operator, keeping the factors (made for factor_c())."""
+        self._check(self._L.cpm_set_operator_c(self._h, float(c)), "set_operator_c")
+
+    def factor_c(self):
+        return float(self._L.cpm_factor_c(self._h))
+
     def partition(self, method=PART_RCB, n_sub=8, weights=None, overlap=2, kind=RAS, alpha=0.0,
                   alpha_cross=0.0):
         w = None
@@ -221,6 +243,7 @@ class Context:
                                           float(alpha), float(alpha_cross)), "partition")
 
     def factor(self, prec=FP64):
+        self._bind_stream()
         self._check(self._L.cpm_factor(self._h, int(prec)), "factor")
 
     def set_factor_workspace(self, nbytes=0):
@@ -238,6 +261,7 @@ class Context:
         return int(self._L.cpm_precond_chunk(self._h))
 
     def set_precond_tiling(self, tiling):
+        self._bind_stream()
         self._check(self._L.cpm_set_precond_tiling(self._h, int(tiling)), "set_precond_tiling")
 
     def precond_tiling(self):
@@ -252,6 +276,7 @@ class Context:
         Returns (best tiling, [ms per tiling])."""
         best = C.c_int()
         ms = (C.c_double * PRECOND_TILINGS)()
+        self._bind_stream()
         self._check(self._L.cpm_autotune_precond(self._h, int(reps), C.byref(best), ms), "autotune_precond")
         return best.value, list(ms)
 
@@ -261,31 +286,29 @@ class Context:
         nrhs = 1 if f.ndim == 1 else f.shape[0]
         u = np.zeros_like(f)
         info = (SolveInfo * max(nrhs, 1))()
+        self._bind_stream()
         rc = self._check(self._L.cpm_solve(self._h, _ptr(f), _ptr(u), nrhs, float(tol), int(max_iter),
                                            int(restart), info), "solve")
         return u, [info[q].as_dict() for q in range(nrhs)], rc
 
-    def solve_device(self, f, u, tol=1e-8, max_iter=1000, restart=30, sync=True):
-        """torch float64 HIP tensors f, u of N_A x nrhs (column-major = (nrhs, N_A) row-major).
-        sync=False skips the device-wide synchronisation that makes torch's pending
-        writes to f visible (for callers that synchronised already)."""
+    def solve_device(self, f, u, tol=1e-8, max_iter=1000, restart=30):
+        """torch float64 HIP tensors f, u of N_A x nrhs (column-major = (nrhs, N_A) row-major),
+        used on torch's current stream."""
         nrhs = 1 if f.dim() == 1 else f.shape[0]
         info = (SolveInfo * max(nrhs, 1))()
-        if sync:
-            _sync_torch()
+        self._bind_stream()
         rc = self._check(self._L.cpm_solve_device(self._h, _dev_ptr(f), _dev_ptr(u), nrhs, float(tol),
                                                   int(max_iter), int(restart), info), "solve_device")
         return [info[q].as_dict() for q in range(nrhs)], rc
 
-    def solve_steps(self, f, u, scale, tol=1e-8, max_iter=1000, restart=30, sync=True):
+    def solve_steps(self, f, u, scale, tol=1e-8, max_iter=1000, restart=30):
         """Implicit steps: u[0] = A^{-1} f, u[k] = A^{-1}(scale u[k-1]); torch float64 HIP
         tensors f (N_A) and u (nsteps, N_A)."""
         if u.dim() != 2 or u.shape[1] != f.shape[0]:
             raise ValueError("u must be (nsteps, N_A)")
         nsteps = u.shape[0]
         info = (SolveInfo * max(nsteps, 1))()
-        if sync:
-            _sync_torch()
+        self._bind_stream()
         rc = self._check(self._L.cpm_solve_steps(self._h, _dev_ptr(f), _dev_ptr(u), nsteps, float(scale),
                                                  float(tol), int(max_iter), int(restart), info), "solve_steps")
         return [info[q].as_dict() for q in range(nsteps)], rc
@@ -293,17 +316,17 @@ class Context:
     def solve_stationary(self, f, u, tol=1e-8, max_iter=1000):
         """(O)RAS as a stationary solver on torch float64 HIP tensors f, u (N_A)."""
         info = SolveInfo()
-        _sync_torch()
+        self._bind_stream()
         rc = self._check(self._L.cpm_solve_stationary(self._h, _dev_ptr(f), _dev_ptr(u), float(tol),
                                                       int(max_iter), C.byref(info)), "solve_stationary")
         return info.as_dict(), rc
 
     def apply_operator(self, x, y):
-        _sync_torch()
+        self._bind_stream()
         self._check(self._L.cpm_apply_operator(self._h, _dev_ptr(x), _dev_ptr(y)), "apply_operator")
 
     def apply_precond(self, v, z):
-        _sync_torch()
+        self._bind_stream()
         self._check(self._L.cpm_apply_precond(self._h, _dev_ptr(v), _dev_ptr(z)), "apply_precond")
 
     # ---- queries --------------------------------------------------------------------
@@ -349,6 +372,7 @@ class Context:
     def factor_export(self, j):
         s = self.subdomain(j)
         w = np.empty((len(s["tilde"]), len(s["sigma"])))
+        self._bind_stream()
         self._check(self._L.cpm_factor_export(self._h, int(j), _ptr(w)), "factor_export")
         return w
 

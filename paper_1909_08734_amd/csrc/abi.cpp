@@ -44,10 +44,12 @@ int cpm_create(cpm_ctx** out, int device) {
       delete ctx;
       return CPM_EDEVICE;
     }
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
       delete ctx;
       return CPM_EDEVICE;
     }
+    ctx->stream = ctx->own_stream;
     ctx->device = device;
     ctx->host_only = false;
   }
@@ -62,9 +64,24 @@ void cpm_destroy(cpm_ctx* ctx) {
     hipStreamSynchronize(ctx->stream);
     cpm::dev_free_all(ctx);
     for (hipEvent_t e : ctx->timer.pool) hipEventDestroy(e);
-    hipStreamDestroy(ctx->stream);
+    hipStreamDestroy(ctx->own_stream);
   }
   delete ctx;
+}
+
+int cpm_set_stream(cpm_ctx* ctx, int caller, void* hip_stream) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "set_stream: host-only context");
+  hipStream_t next = caller ? (hipStream_t)hip_stream : ctx->own_stream;
+  if (next == ctx->stream) return CPM_OK;
+  hipSetDevice(ctx->device);
+  // Every call returns after its device work has finished, so nothing of the
+  // context is pending on the old stream (which other work may still be
+  // using: it is not synchronised). The timers' events are read now.
+  cpm::timer_harvest(ctx);
+  ctx->stream = next;
+  cpm::drop_graphs(ctx->dev);
+  return CPM_OK;
 }
 
 const char* cpm_last_error(const cpm_ctx* ctx) { return ctx ? ctx->err.c_str() : kNull; }
@@ -77,17 +94,13 @@ int cpm_build_band(cpm_ctx* ctx, cpm_cp_fn fn, void* user, const double lo[3], c
     cpm::Band b;
     int rc = cpm::build_band(b, fn, user, lo, hi, h, degree, band_factor, ctx->err);
     if (rc != CPM_OK) return rc;
-    if (!ctx->host_only) cpm::dev_free_all(ctx);
+    // the new operator arrays replace the old device state only once they
+    // are all on the device, so a failure leaves the previous band usable
+    if (!ctx->host_only && (rc = cpm::dev_upload_operator(ctx, b)) != CPM_OK) return rc;
     ctx->band = std::move(b);
     ctx->dec = cpm::Decomp();
+    ctx->c_factor = 0;
     ctx->state = 1;
-    if (!ctx->host_only) {
-      rc = cpm::dev_upload_operator(ctx);
-      if (rc != CPM_OK) {
-        ctx->state = 0;
-        return rc;
-      }
-    }
     return CPM_OK;
   });
 }
@@ -105,7 +118,7 @@ int cpm_clone(const cpm_ctx* src, int device, cpm_ctx** out) {
     ctx->dec = src->dec;
     ctx->c = src->c;
     ctx->state = std::min(src->state, 3);
-    return ctx->host_only ? CPM_OK : cpm::dev_upload_operator(ctx);
+    return ctx->host_only ? CPM_OK : cpm::dev_upload_operator(ctx, ctx->band);
   });
   if (rc != CPM_OK) {
     cpm_destroy(ctx);
@@ -121,9 +134,21 @@ int cpm_build_operator(cpm_ctx* ctx, double c) {
   if (!(c > 0) || !std::isfinite(c)) return fail(ctx, CPM_EINVAL, "build_operator: c must be positive and finite");
   if (!ctx->host_only) cpm::dev_free_factor(ctx);
   ctx->c = c;
+  ctx->c_factor = 0;
   ctx->state = ctx->dec.n_sub > 0 ? 3 : 2;
   return CPM_OK;
 }
+
+int cpm_set_operator_c(cpm_ctx* ctx, double c) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 2) return fail(ctx, CPM_ESTATE, "set_operator_c: build the operator first");
+  if (!(c > 0) || !std::isfinite(c)) return fail(ctx, CPM_EINVAL, "set_operator_c: c must be positive and finite");
+  if (c != ctx->c && !ctx->host_only) cpm::drop_graphs(ctx->dev);  // captured launches hold the diagonal
+  ctx->c = c;
+  return CPM_OK;
+}
+
+double cpm_factor_c(const cpm_ctx* ctx) { return ctx && ctx->state >= 4 ? ctx->c_factor : 0.0; }
 
 int cpm_partition(cpm_ctx* ctx, int method, int n_sub, const double* weights, int overlap, int kind,
                   double alpha, double alpha_cross) {
@@ -149,6 +174,7 @@ int cpm_factor(cpm_ctx* ctx, int prec) {
   return guarded(ctx, [&]() -> int {
     int rc = cpm::dev_factor(ctx, prec);
     ctx->state = rc == CPM_OK ? 4 : 3;
+    ctx->c_factor = rc == CPM_OK ? ctx->c : 0.0;
     return rc;
   });
 }

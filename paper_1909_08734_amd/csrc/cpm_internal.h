@@ -69,12 +69,20 @@ struct SubDesc {
   int32_t rpb;       // rows of W_j per apply block
 };
 
-enum { TIMER_PRECOND = 0, TIMER_EXTEND = 1, TIMER_STENCIL = 2, TIMER_LU_GEMM = 3, N_TIMERS = 4 };
+enum {
+  TIMER_PRECOND = 0,
+  TIMER_EXTEND = 1,
+  TIMER_STENCIL = 2,
+  TIMER_LU_GEMM = 3,
+  TIMER_KRYLOV = 4,  // orthogonalisation, norms, least squares
+  TIMER_UPDATE = 5,  // solution updates and vector copies
+  N_TIMERS = CPM_N_TIMERS
+};
 
 struct Timer {
   bool on = false;
-  double ms[N_TIMERS] = {0, 0, 0, 0};
-  int64_t count[N_TIMERS] = {0, 0, 0, 0};
+  double ms[N_TIMERS] = {};
+  int64_t count[N_TIMERS] = {};
   std::vector<hipEvent_t> pool;   // event pairs recorded since the last harvest
   std::vector<int> which;
   size_t used = 0;
@@ -136,10 +144,12 @@ struct Dev {
 struct cpm_ctx {
   int device = -1;
   bool host_only = true;
-  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // created with the context
+  hipStream_t stream = nullptr;      // the stream in use: own_stream or the caller's
   std::string err;
   int state = 0;  // 0 created, 1 band, 2 operator, 3 partition, 4 factored
-  double c = 0;
+  double c = 0;         // c of the operator A = c I - Delta_S^h
+  double c_factor = 0;  // c the resident factors were made for
   cpm::Band band;
   cpm::Decomp dec;
   cpm::Dev dev;
@@ -148,7 +158,10 @@ struct cpm_ctx {
 
 namespace cpm {
 // Device orchestration (device.hip).
-int dev_upload_operator(cpm_ctx* ctx);
+// Uploads the operator arrays of `b`; on success the context's previous
+// device state (operator, factors, Krylov space) is freed and replaced, on
+// failure it is left as it was.
+int dev_upload_operator(cpm_ctx* ctx, const Band& b);
 int dev_factor(cpm_ctx* ctx, int prec);
 int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y);
 int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);

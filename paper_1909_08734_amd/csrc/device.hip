@@ -70,7 +70,7 @@ void launch(cpm_ctx* ctx, int which, void (*kernel)(KArgs...), dim3 grid, dim3 b
 void timer_harvest(cpm_ctx* ctx) {
   Timer& t = ctx->timer;
   if (t.used == 0) return;
-  hipStreamSynchronize(ctx->stream);
+  hipEventSynchronize(t.pool[t.used - 1]);  // the stop event of the last timed launch
   for (size_t q = 0; q < t.which.size(); ++q) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.pool[2 * q], t.pool[2 * q + 1]) == hipSuccess) {
@@ -81,6 +81,29 @@ void timer_harvest(cpm_ctx* ctx) {
   t.which.clear();
   t.used = 0;
 }
+
+// Device time of a solve's phases from the kernel timers (timing on only):
+// snapshot the totals before the solve, difference after it.
+struct PhaseClock {
+  bool on = false;
+  double ms0[N_TIMERS] = {};
+  void start(cpm_ctx* ctx) {
+    on = ctx->timer.on;
+    if (!on) return;
+    timer_harvest(ctx);
+    for (int q = 0; q < N_TIMERS; ++q) ms0[q] = ctx->timer.ms[q];
+  }
+  void stop(cpm_ctx* ctx, double phase[4]) {
+    for (int q = 0; q < 4; ++q) phase[q] = 0.0;
+    if (!on) return;
+    timer_harvest(ctx);
+    const double* t = ctx->timer.ms;
+    phase[0] = t[TIMER_PRECOND] - ms0[TIMER_PRECOND];
+    phase[1] = (t[TIMER_EXTEND] - ms0[TIMER_EXTEND]) + (t[TIMER_STENCIL] - ms0[TIMER_STENCIL]);
+    phase[2] = t[TIMER_KRYLOV] - ms0[TIMER_KRYLOV];
+    phase[3] = t[TIMER_UPDATE] - ms0[TIMER_UPDATE];
+  }
+};
 
 // Captured iterations hold the device addresses and launch shapes of the
 // moment they were captured: drop them whenever any of those change.
@@ -140,20 +163,40 @@ void dev_free_all(cpm_ctx* ctx) {
   d.op_bytes = 0;
 }
 
-int dev_upload_operator(cpm_ctx* ctx) {
+int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
   HIPCHK(hipSetDevice(ctx->device));
-  const Band& b = ctx->band;
-  Dev& d = ctx->dev;
-  drop_graphs(d);
+  int32_t* lines = nullptr;
+  double* wts = nullptr;
+  int32_t* nbr = nullptr;
+  double* e = nullptr;
+  auto undo = [&](int code) {
+    hipStreamSynchronize(ctx->stream);
+    dfree(lines);
+    dfree(wts);
+    dfree(nbr);
+    dfree(e);
+    return code;
+  };
   int rc;
-  if ((rc = upload(ctx, &d.lines, b.lines)) != CPM_OK) return rc;
-  if ((rc = upload(ctx, &d.wts, b.wts)) != CPM_OK) return rc;
+  if ((rc = upload(ctx, &lines, b.lines)) != CPM_OK) return undo(rc);
+  if ((rc = upload(ctx, &wts, b.wts)) != CPM_OK) return undo(rc);
   std::vector<int32_t> soa(b.n_act * 6);
   for (int64_t i = 0; i < b.n_act; ++i)
-    for (int e = 0; e < 6; ++e) soa[e * b.n_act + i] = b.nbr[i * 6 + e];
-  if ((rc = upload(ctx, &d.nbr, soa)) != CPM_OK) return rc;
-  HIPCHK(hipMalloc((void**)&d.e, b.total() * sizeof(double)));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < 6; ++q) soa[q * b.n_act + i] = b.nbr[i * 6 + q];
+  if ((rc = upload(ctx, &nbr, soa)) != CPM_OK) return undo(rc);
+  hipError_t err = hipMalloc((void**)&e, b.total() * sizeof(double));
+  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
+  if (err != hipSuccess) {
+    ctx->err = std::string("operator upload: ") + hipGetErrorString(err);
+    return undo(err == hipErrorOutOfMemory ? CPM_ENOMEM : CPM_EDEVICE);
+  }
+  // everything is on the device: the previous state goes
+  dev_free_all(ctx);
+  Dev& d = ctx->dev;
+  d.lines = lines;
+  d.wts = wts;
+  d.nbr = nbr;
+  d.e = e;
   d.op_bytes = b.lines.size() * 4 + b.wts.size() * 8 + soa.size() * 4 + b.total() * 8;
   return CPM_OK;
 }
@@ -760,6 +803,8 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
   const unsigned gv = nblk(na, 256);
   const double ih2 = 1.0 / (ctx->band.h * ctx->band.h);
   const double diag = ctx->c + 6.0 * ih2;
+  PhaseClock clock;
+  clock.start(ctx);
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
@@ -809,16 +854,17 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
       info->relres_true = rel_true;
       info->relres_est = rel_est;
       info->ms = ms;
+      clock.stop(ctx, info->phase_ms);
     }
     return code;
   };
 
   // ||f||, with V[0] = f (x0 = 0) as the first residual
-  k_copy<<<gv, 256, 0, st>>>(na, f, d.V);
-  k_fill<<<gv, 256, 0, st>>>(na, u, 0.0);
+  launch(ctx, TIMER_UPDATE, k_copy, dim3(gv), dim3(256), 0, na, f, d.V);
+  launch(ctx, TIMER_UPDATE, k_fill, dim3(gv), dim3(256), 0, na, u, 0.0);
   const int rb = red_blocks(na);
-  k_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, 0, 1, d.V, d.part, -1, nullptr);
-  k_norm_finish<<<1, RED_THREADS, 0, st>>>(d.part, rb, L, sm, slots_dev + (m + 1), ticket_for(m + 1));
+  launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, d.V, 0, 1, d.V, d.part, -1, nullptr);
+  launch(ctx, TIMER_KRYLOV, k_norm_finish, dim3(1), dim3(RED_THREADS), 0, d.part, rb, L, sm, slots_dev + (m + 1), ticket_for(m + 1));
   const double* hv = nullptr;
   if ((rc = wait(m + 1, &hv)) != CPM_OK) return rc;
   const double bnorm = hv[S_BETA];
@@ -841,19 +887,19 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
     // w = A z_k fused with CGS pass 1 (normalising V[k] in place), then pass 2,
     // ||w|| and the Givens update
     const BatchStrides one{};
-    k_stencil_dots<<<rb, RED_THREADS, 0, st>>>(na, diag, ih2, d.nbr, zk, d.e, w, d.V, d.ld, k + 1, d.part, k,
+    launch(ctx, TIMER_STENCIL, k_stencil_dots, dim3(rb), dim3(RED_THREADS), 0, na, diag, ih2, d.nbr, zk, d.e, w, d.V, d.ld, k + 1, d.part, k,
                                                scal + S_INV, one);
-    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h1(), one);
-    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0, one);
-    k_reduce_cols<<<k + 1, RED_THREADS, 0, st>>>(d.part, rb, sm + L.h2(), one);
-    k_axpy_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, d.ld, k, sm + L.h2(), w, d.part, 1, one);
-    k_arnoldi<<<1, RED_THREADS, 0, st>>>(d.part, rb, k, L, sm, slots_dev + k, ticket, one);
+    launch(ctx, TIMER_KRYLOV, k_reduce_cols, dim3(k + 1), dim3(RED_THREADS), 0, d.part, rb, sm + L.h1(), one);
+    launch(ctx, TIMER_KRYLOV, k_axpy_dots, dim3(rb), dim3(RED_THREADS), 0, na, d.V, d.ld, k, sm + L.h1(), w, d.part, 0, one);
+    launch(ctx, TIMER_KRYLOV, k_reduce_cols, dim3(k + 1), dim3(RED_THREADS), 0, d.part, rb, sm + L.h2(), one);
+    launch(ctx, TIMER_KRYLOV, k_axpy_dots, dim3(rb), dim3(RED_THREADS), 0, na, d.V, d.ld, k, sm + L.h2(), w, d.part, 1, one);
+    launch(ctx, TIMER_KRYLOV, k_arnoldi, dim3(1), dim3(RED_THREADS), 0, d.part, rb, k, L, sm, slots_dev + k, ticket, one);
   };
   // With graphs, iteration k is captured once (ticket 1 baked in) and replayed;
   // the host clears slot k's ticket before each replay, which is safe because
   // the slot's previous write finished before the host's last wait in this
   // stream order.
-  const bool graphs = d.use_graphs && !ctx->timer.on;
+  const bool graphs = d.use_graphs && !ctx->timer.on && st != nullptr;  // no capture on the null stream
   if (graphs && (int)d.graphs.size() != m) {
     drop_graphs(d);
     d.graphs.assign(m, nullptr);
@@ -892,11 +938,11 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
       rel_est = hs[S_EST] / bnorm;
       if (!(hs[S_EST] > tol * bnorm) || hs[S_HK1] == 0.0 || !more) break;
     }
-    k_backsolve<<<1, 64, 0, st>>>(kk, L, sm);
-    k_update_x<<<gv, 256, 0, st>>>(na, d.Z, d.ld, kk, sm + L.y(), u);
+    launch(ctx, TIMER_KRYLOV, k_backsolve, dim3(1), dim3(64), 0, kk, L, sm);
+    launch(ctx, TIMER_UPDATE, k_update_x, dim3(gv), dim3(256), 0, na, d.Z, d.ld, kk, sm + L.y(), u);
     launch_operator(ctx, u, d.V, f);  // new residual into V[0]
-    k_dots<<<rb, RED_THREADS, 0, st>>>(na, d.V, 0, 1, d.V, d.part, -1, nullptr);
-    k_norm_finish<<<1, RED_THREADS, 0, st>>>(d.part, rb, L, sm, slots_dev + (m + 1), ticket_for(m + 1));
+    launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, d.V, 0, 1, d.V, d.part, -1, nullptr);
+    launch(ctx, TIMER_KRYLOV, k_norm_finish, dim3(1), dim3(RED_THREADS), 0, d.part, rb, L, sm, slots_dev + (m + 1), ticket_for(m + 1));
     if ((rc = wait(m + 1, &hv)) != CPM_OK) return rc;
     ++cycles;
     rel_true = hv[S_BETA] / bnorm;
@@ -1010,6 +1056,8 @@ int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol
     fr[r] = f + (size_t)r * na;
     ur[r] = u + (size_t)r * na;
   }
+  PhaseClock clock;
+  clock.start(ctx);
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
@@ -1050,6 +1098,8 @@ int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol
     hipEventElapsedTime(&ms, t0, t1);
     hipEventDestroy(t0);
     hipEventDestroy(t1);
+    double phase[4];
+    clock.stop(ctx, phase);
     if (info)
       for (int r = 0; r < nb; ++r) {
         info[r].iters = iters[r];
@@ -1058,19 +1108,20 @@ int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol
         info[r].relres_true = rel_true[r];
         info[r].relres_est = rel_est[r];
         info[r].ms = ms;
+        for (int q = 0; q < 4; ++q) info[r].phase_ms[q] = phase[q];
       }
     return code;
   };
   // ||f_r||, with V_r[0] = f_r (x0 = 0) as the first residual
   for (int r = 0; r < nb; ++r) {
-    k_copy<<<gv, 256, 0, st>>>(na, fr[r], Vp(r, 0));
-    k_fill<<<gv, 256, 0, st>>>(na, ur[r], 0.0);
-    k_dots<<<rb, RED_THREADS, 0, st>>>(na, Vp(r, 0), 0, 1, Vp(r, 0), PART(r), -1, nullptr);
+    launch(ctx, TIMER_UPDATE, k_copy, dim3(gv), dim3(256), 0, na, fr[r], Vp(r, 0));
+    launch(ctx, TIMER_UPDATE, k_fill, dim3(gv), dim3(256), 0, na, ur[r], 0.0);
+    launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, Vp(r, 0), 0, 1, Vp(r, 0), PART(r), -1, nullptr);
   }
   {
     const unsigned long long tk = ticket_for(m + 1);
     for (int r = 0; r < nb; ++r)
-      k_norm_finish<<<1, RED_THREADS, 0, st>>>(PART(r), rb, L, SM(r), d.bslots_dev + r * bs.slot + (m + 1), tk);
+      launch(ctx, TIMER_KRYLOV, k_norm_finish, dim3(1), dim3(RED_THREADS), 0, PART(r), rb, L, SM(r), d.bslots_dev + r * bs.slot + (m + 1), tk);
   }
   for (int r = 0; r < nb; ++r) {
     const double* hv = nullptr;
@@ -1094,15 +1145,15 @@ int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol
     else
       launch_precond_multi<2>(ctx, Vp(0, k), bs.v, scal_inv, bs.small, Zp(0, k), bs.z);
     launch_extend(ctx, Zp(0, k), d.bE, nb, bs.z, bs.e);
-    k_stencil_dots<<<dim3(rb, nb), RED_THREADS, 0, st>>>(na, diag, ih2, d.nbr, Zp(0, k), d.bE, Vp(0, k + 1), d.bV,
+    launch(ctx, TIMER_STENCIL, k_stencil_dots, dim3(rb, nb), dim3(RED_THREADS), 0, na, diag, ih2, d.nbr, Zp(0, k), d.bE, Vp(0, k + 1), d.bV,
                                                          ld, k + 1, d.bpart, k, scal_inv, bs);
-    k_reduce_cols<<<dim3(k + 1, nb), RED_THREADS, 0, st>>>(d.bpart, rb, d.bsmall + L.h1(), bs);
-    k_axpy_dots<<<dim3(rb, nb), RED_THREADS, 0, st>>>(na, d.bV, ld, k, d.bsmall + L.h1(), Vp(0, k + 1), d.bpart, 0,
+    launch(ctx, TIMER_KRYLOV, k_reduce_cols, dim3(k + 1, nb), dim3(RED_THREADS), 0, d.bpart, rb, d.bsmall + L.h1(), bs);
+    launch(ctx, TIMER_KRYLOV, k_axpy_dots, dim3(rb, nb), dim3(RED_THREADS), 0, na, d.bV, ld, k, d.bsmall + L.h1(), Vp(0, k + 1), d.bpart, 0,
                                                       bs);
-    k_reduce_cols<<<dim3(k + 1, nb), RED_THREADS, 0, st>>>(d.bpart, rb, d.bsmall + L.h2(), bs);
-    k_axpy_dots<<<dim3(rb, nb), RED_THREADS, 0, st>>>(na, d.bV, ld, k, d.bsmall + L.h2(), Vp(0, k + 1), d.bpart, 1,
+    launch(ctx, TIMER_KRYLOV, k_reduce_cols, dim3(k + 1, nb), dim3(RED_THREADS), 0, d.bpart, rb, d.bsmall + L.h2(), bs);
+    launch(ctx, TIMER_KRYLOV, k_axpy_dots, dim3(rb, nb), dim3(RED_THREADS), 0, na, d.bV, ld, k, d.bsmall + L.h2(), Vp(0, k + 1), d.bpart, 1,
                                                       bs);
-    k_arnoldi<<<dim3(1, nb), RED_THREADS, 0, st>>>(d.bpart, rb, k, L, d.bsmall, d.bslots_dev + k, ticket_for(k), bs);
+    launch(ctx, TIMER_KRYLOV, k_arnoldi, dim3(1, nb), dim3(RED_THREADS), 0, d.bpart, rb, k, L, d.bsmall, d.bslots_dev + k, ticket_for(k), bs);
   };
   for (;;) {
     bool any = false;
@@ -1136,15 +1187,15 @@ int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol
     // cycle end: update, true residual and its norm for every right-hand side still running
     for (int r = 0; r < nb; ++r) {
       if (done[r]) continue;
-      k_backsolve<<<1, 64, 0, st>>>(kk[r], L, SM(r));
-      k_update_x<<<gv, 256, 0, st>>>(na, Zp(r, 0), ld, kk[r], SM(r) + L.y(), ur[r]);
+      launch(ctx, TIMER_KRYLOV, k_backsolve, dim3(1), dim3(64), 0, kk[r], L, SM(r));
+      launch(ctx, TIMER_UPDATE, k_update_x, dim3(gv), dim3(256), 0, na, Zp(r, 0), ld, kk[r], SM(r) + L.y(), ur[r]);
       launch_operator(ctx, ur[r], Vp(r, 0), fr[r]);
-      k_dots<<<rb, RED_THREADS, 0, st>>>(na, Vp(r, 0), 0, 1, Vp(r, 0), PART(r), -1, nullptr);
+      launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, Vp(r, 0), 0, 1, Vp(r, 0), PART(r), -1, nullptr);
     }
     const unsigned long long tk = ticket_for(m + 1);
     for (int r = 0; r < nb; ++r)
       if (!done[r])
-        k_norm_finish<<<1, RED_THREADS, 0, st>>>(PART(r), rb, L, SM(r), d.bslots_dev + r * bs.slot + (m + 1), tk);
+        launch(ctx, TIMER_KRYLOV, k_norm_finish, dim3(1), dim3(RED_THREADS), 0, PART(r), rb, L, SM(r), d.bslots_dev + r * bs.slot + (m + 1), tk);
     for (int r = 0; r < nb; ++r) {
       if (done[r]) continue;
       const double* hv = nullptr;
@@ -1183,15 +1234,17 @@ int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max
   double* r = d.V;
   double* z = d.Z;
   unsigned long long expect[2] = {0, 0};
+  PhaseClock clock;
+  clock.start(ctx);
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, st));
   auto residual = [&](int slot) {
     launch_operator(ctx, u, r, f);  // r = f - A u
-    k_dots<<<rb, RED_THREADS, 0, st>>>(na, r, 0, 1, r, d.part, -1, nullptr);
+    launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, r, 0, 1, r, d.part, -1, nullptr);
     expect[slot] = ++d.ticket;
-    k_norm_finish<<<1, RED_THREADS, 0, st>>>(d.part, rb, L, sm, d.slots_dev + slot, expect[slot]);
+    launch(ctx, TIMER_KRYLOV, k_norm_finish, dim3(1), dim3(RED_THREADS), 0, d.part, rb, L, sm, d.slots_dev + slot, expect[slot]);
   };
   auto wait = [&](int slot, double* out) -> int {
     volatile unsigned long long* tk = &d.slots[slot].ticket;
@@ -1227,10 +1280,11 @@ int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max
       info->relres_true = rel;
       info->relres_est = rel;
       info->ms = ms;
+      clock.stop(ctx, info->phase_ms);
     }
     return code;
   };
-  k_fill<<<gv, 256, 0, st>>>(na, u, 0.0);
+  launch(ctx, TIMER_UPDATE, k_fill, dim3(gv), dim3(256), 0, na, u, 0.0);
   residual(0);
   double bnorm = 0.0;
   if ((rc = wait(0, &bnorm)) != CPM_OK) return rc;
@@ -1245,7 +1299,7 @@ int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max
   for (;;) {
     // update n, then the residual of u_{n+1}
     launch_precond(ctx, r, z, nullptr);
-    k_axpy<<<gv, 256, 0, st>>>(na, z, u);
+    launch(ctx, TIMER_UPDATE, k_axpy, dim3(gv), dim3(256), 0, na, z, u);
     ++n;
     residual(n & 1);
     double bn = 0.0;
@@ -1414,7 +1468,7 @@ int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double
   for (int k = 0; k < nsteps; ++k) {
     const double* rhs = f;
     if (k > 0) {
-      k_scale<<<nblk(na, 256), 256, 0, ctx->stream>>>(na, scale, u + (size_t)(k - 1) * na, ctx->dev.F);
+      launch(ctx, TIMER_UPDATE, k_scale, dim3(nblk(na, 256)), dim3(256), 0, na, scale, u + (size_t)(k - 1) * na, ctx->dev.F);
       HIPCHK(hipGetLastError());
       rhs = ctx->dev.F;
     }

@@ -11,10 +11,15 @@ server
 * keeps factorisations resident: one context per (surface, h, c level) holds
   its restricted local solution operators until evicted (least recently used
   first, never while in use); c is quantised to `c_levels` log-spaced levels
-  so that repeated requests hit the cache;
-* admits work by device memory: before factoring, the peak footprint of the
-  factorisation (cpm_footprint_estimate) plus the request's vectors must fit in
-  the budget, else idle cached factors are evicted, else the request waits;
+  to pick the factors, so that repeated requests hit the cache, while the
+  operator and the implicit-step scale use the request's own c
+  (cpm_set_operator_c): the cached factors of the nearest level act as the
+  preconditioner and FGMRES stops on the true residual of the requested system;
+* admits work by device memory: a request's vectors, plus the peak footprint
+  of a factorisation (cpm_footprint_estimate) when its factors must be made,
+  are reserved in one step against the budget, evicting idle cached factors;
+  otherwise the request waits without holding anything, and fails with
+  MemoryError when nothing else runs that could free memory;
 * shares host set-up: the band and partition of a (surface, h) are built once
   on a host-only context and cloned onto the device for each c level;
 * records per-request arrival, start, finish, iteration counts and cache hits,
@@ -50,7 +55,8 @@ class Request:
 class Result:
     rid: int
     key: tuple
-    c_used: float
+    c: float          # the request's c (operator and step scale)
+    c_factor: float   # the quantised level whose factors precondition it
     arrival: float
     start: float = math.nan
     finish: float = math.nan
@@ -108,6 +114,7 @@ class Server:
         self._cache = {}          # key -> _Entry
         self._building = set()    # keys being factored
         self._claimed = set()     # keys of requests taken by a slot
+        self._active = 0          # requests holding a reservation
         self.evictions = 0
         self.factor_s = 0.0
         self.n_factor = 0
@@ -141,57 +148,98 @@ class Server:
             return self._bases[k]
 
     # ---- device memory ledger -----------------------------------------------------------
-    def _reserve(self, nbytes, evictable=True):
-        """Block until nbytes fit in the budget (evicting idle factors). Caller holds the lock."""
+    def _try_reserve(self, nbytes, keep=None):
+        """Reserve nbytes if they fit, evicting idle cached factors (least
+        recently used first, never `keep`). Caller holds the lock. Returns False
+        when they do not fit yet; raises MemoryError when they never can (more
+        than the budget, or no other request running that could free memory)."""
         if nbytes > self.budget:
             raise MemoryError(f"request needs {nbytes} bytes, budget {self.budget}")
         while self.used + nbytes > self.budget:
-            idle = [(e.last_used, k) for k, e in self._cache.items() if not e.busy]
-            if evictable and idle:
-                _, k = min(idle)
-                e = self._cache.pop(k)
-                e.ctx.close()
-                self.used -= e.resident
-                self.evictions += 1
-                continue
-            self._lock.wait(0.05)
+            idle = [(e.last_used, k) for k, e in self._cache.items() if not e.busy and k != keep]
+            if not idle:
+                break
+            _, k = min(idle)
+            e = self._cache.pop(k)
+            e.ctx.close()
+            self.used -= e.resident
+            self.evictions += 1
+        if self.used + nbytes > self.budget:
+            if self._active == 0:
+                raise MemoryError(f"request needs {nbytes} bytes; {self.used} of {self.budget} are held by "
+                                  "factors that cannot be evicted and no other request is running")
+            return False
         self.used += nbytes
         self.peak_used = max(self.peak_used, self.used)
+        return True
 
     def _release(self, nbytes):
         self.used -= nbytes
         self._lock.notify_all()
 
+    # ---- device work (separate methods so the scheduling can be tested on the host) ---------
+    def _make_factors(self, base, c_level):
+        """A device context with the factors of (base's band and partition, c_level)."""
+        ctx = base.clone(self.device)
+        try:
+            ctx.build_operator(c_level)
+            ctx.factor(self.prec)
+        except Exception:
+            ctx.close()
+            raise
+        return ctx
+
+    def _solve(self, ctx, req, res, f, na, stream):
+        """The request's implicit steps on torch stream `stream` (the context follows it)."""
+        torch = self.torch
+        with torch.cuda.stream(stream):
+            f_dev = torch.from_numpy(f).to(f"cuda:{self.device}", non_blocking=False)
+            u_dev = torch.empty((req.nsteps, na), dtype=torch.float64, device=f"cuda:{self.device}")
+            ctx.set_operator_c(req.c)
+            info, rc = ctx.solve_steps(f_dev, u_dev, req.c, tol=self.tol, max_iter=self.max_iter,
+                                       restart=self.restart)
+            res.iters = [q["iters"] for q in info]
+            res.relres = [q["relres_true"] for q in info]
+            res.status = rc
+            if self.keep:
+                res.u = u_dev.cpu().numpy()
+            del f_dev, u_dev
+
     # ---- one request ----------------------------------------------------------------------
-    def _acquire_entry(self, req, res):
+    def _admit(self, req, res, vec_bytes):
+        """Take the request's cached factors, or the right to make them, and reserve
+        its memory in the same step (vectors; plus the factorisation's peak when
+        making them). Returns (entry or None, peak, resident)."""
         k = res.key
+        base, _, _ = self._base(req.surface, req.h)
+        resident, peak = base.footprint_estimate(self.prec, self.restart)
         with self._lock:
             while True:
                 e = self._cache.get(k)
                 if e is not None and not e.busy:
-                    e.busy = True
-                    res.hit = True
-                    return e
-                if e is None and k not in self._building:
-                    self._building.add(k)
-                    break
+                    if self._try_reserve(vec_bytes, keep=k):
+                        e.busy = True
+                        res.hit = True
+                        self._active += 1
+                        return e, 0, 0
+                elif e is None and k not in self._building:
+                    if self._try_reserve(peak + vec_bytes):
+                        self._building.add(k)
+                        self._active += 1
+                        return None, peak, resident
                 self._lock.wait(0.05)
+
+    def _factor(self, req, res, peak, resident):
+        """Make and cache the factors of res.key (peak bytes reserved by _admit)."""
+        k = res.key
         try:
             base, _, _ = self._base(req.surface, req.h)
-            resident, peak = base.footprint_estimate(self.prec, self.restart)
-            with self._lock:
-                self._reserve(peak)
             t0 = time.perf_counter()
-            ctx = None
             try:
-                ctx = base.clone(self.device)
-                ctx.build_operator(k[2])
-                ctx.factor(self.prec)
+                ctx = self._make_factors(base, k[2])
             except Exception:
                 with self._lock:
                     self._release(peak)
-                if ctx is not None:
-                    ctx.close()
                 raise
             dt = time.perf_counter() - t0
             e = _Entry(ctx, resident)
@@ -208,28 +256,16 @@ class Server:
                 self._lock.notify_all()
 
     def _run(self, req, res, stream):
-        torch = self.torch
         _, cp, na = self._base(req.surface, req.h)
         _, rhs = self.surfaces[req.surface]
         f = np.ascontiguousarray(rhs(cp, req.seed), dtype=np.float64)
         vec_bytes = (req.nsteps + 1) * na * 8
-        with self._lock:
-            self._reserve(vec_bytes)
+        e, peak, resident = self._admit(req, res, vec_bytes)
         try:
-            e = self._acquire_entry(req, res)
+            if e is None:
+                e = self._factor(req, res, peak, resident)
             try:
-                with torch.cuda.stream(stream):
-                    f_dev = torch.from_numpy(f).to(f"cuda:{self.device}")
-                    u_dev = torch.empty((req.nsteps, na), dtype=torch.float64, device=f"cuda:{self.device}")
-                stream.synchronize()
-                info, rc = e.ctx.solve_steps(f_dev, u_dev, res.c_used, tol=self.tol, max_iter=self.max_iter,
-                                             restart=self.restart, sync=False)
-                res.iters = [q["iters"] for q in info]
-                res.relres = [q["relres_true"] for q in info]
-                res.status = rc
-                if self.keep:
-                    res.u = u_dev.cpu().numpy()
-                del f_dev, u_dev
+                self._solve(e.ctx, req, res, f, na, stream)
             finally:
                 with self._lock:
                     e.busy = False
@@ -238,6 +274,7 @@ class Server:
         finally:
             with self._lock:
                 self._release(vec_bytes)
+                self._active -= 1
 
     # ---- the loop ----------------------------------------------------------------------------
     def run(self, requests, realtime=True, progress=None):
@@ -246,7 +283,8 @@ class Server:
         called after each request. Returns a list of Result (request order)."""
         torch = self.torch
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        results = {r.rid: Result(r.rid, self.key(r), self.key(r)[2], r.arrival if realtime else 0.0) for r in reqs}
+        results = {r.rid: Result(r.rid, self.key(r), r.c, self.key(r)[2], r.arrival if realtime else 0.0)
+                   for r in reqs}
         pending = []
         state = {"next": 0, "done": 0, "error": None}
         t_start = time.perf_counter()
@@ -264,7 +302,7 @@ class Server:
             return None
 
         def worker(wid):
-            stream = torch.cuda.Stream(device=self.device)
+            stream = self._new_stream()
             while True:
                 with self._lock:
                     while True:
@@ -315,6 +353,9 @@ class Server:
         if state["error"] is not None:
             raise RuntimeError(f"serving stopped: {state['error']}")
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+    def _new_stream(self):
+        return self.torch.cuda.Stream(device=self.device)
 
     def close(self):
         with self._lock:

@@ -41,6 +41,47 @@ def test_binding_constants_match_header():
     for name in ("OK", "ENOTCONV", "EINVAL", "ESTATE", "ENOMEM", "ESINGULAR", "EDEVICE", "RAS", "ORAS", "FP64",
                  "FP32", "PART_OCTANT", "PART_RCB", "PART_GRAPH", "PART_ALIGN"):
         assert int(values[name]) == getattr(P, name), name
+    assert int(values["N_TIMERS"]) == P.TIMER_UPDATE + 1
+    # the solve record: 4 int32, 3 doubles, then the phase times
+    assert ctypes.sizeof(P.SolveInfo) == 16 + 3 * 8 + 4 * 8 and len(P.PHASES) == 4
+
+
+def test_failed_band_build_keeps_state_and_operator_constant_host_only():
+    """A failed cpm_build_band leaves band, operator and partition as they were;
+    cpm_set_operator_c changes c without leaving the partitioned state."""
+    ctx = P.Context(-1)
+    ctx.build_band(ci.Sphere(), 0.1, 3)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_RCB, 8, None, 2, P.ORAS, 3.0, 30.0)
+    lin = ctx.band_arrays(3)["lin"].copy()
+
+    class Broken:
+        def cp(self, x):
+            raise RuntimeError("no closest point")
+
+    with pytest.raises(P.CpmError) as e:
+        ctx.build_band(Broken(), 0.1, 3)
+    assert e.value.code == P.ECALLBACK
+    with pytest.raises(P.CpmError) as e:
+        ctx.build_band(ci.Sphere(), 0.1, 3, lo=(-1.1,) * 3, hi=(1.1,) * 3)
+    assert e.value.code == P.EINVAL
+    np.testing.assert_array_equal(ctx.band_arrays(3)["lin"], lin)
+    assert ctx.partition_info()[0] == 8
+    ctx.footprint_estimate(P.FP32, 30)  # still partitioned
+    ctx.set_operator_c(2.0)
+    assert ctx.partition_info()[0] == 8 and ctx.factor_c() == 0.0
+    for bad in (0.0, -1.0, float("nan")):
+        with pytest.raises(P.CpmError) as e:
+            ctx.set_operator_c(bad)
+        assert e.value.code == P.EINVAL
+    L = P.lib()
+    assert L.cpm_set_stream(ctx._h, 1, None) == P.EDEVICE  # host-only context
+    ctx.close()
+    fresh = P.Context(-1)
+    with pytest.raises(P.CpmError) as e:
+        fresh.set_operator_c(1.0)
+    assert e.value.code == P.ESTATE
+    fresh.close()
 
 
 CASES = [

@@ -117,7 +117,7 @@ def test_serving_mix_equals_alone_and_meets_tolerance():
     alone, st1 = _serve(reqs, slots=1, realtime=False)
     say("alone stats", st1)
     for a, m in zip(alone, mix):
-        assert a.rid == m.rid and a.c_used == m.c_used
+        assert a.rid == m.rid and a.c == m.c and a.c_factor == m.c_factor
         assert m.u.shape == (reqs[m.rid].nsteps, a.u.shape[1])
         np.testing.assert_array_equal(m.u, a.u)  # same kernels, same order: bit-identical
         assert max(m.relres) <= 1e-8
@@ -138,13 +138,20 @@ def test_serving_mix_equals_alone_and_meets_tolerance():
     assert st2["evictions"] > 0 and st2["peak_used"] <= budget
     for a, t in zip(alone, tight):
         np.testing.assert_array_equal(t.u, a.u)
-    # each implicit step solves A u_k = c u_{k-1} to the tolerance (oracle operator)
-    r = max(mix, key=lambda x: len(x.iters))
-    q = reqs[r.rid]
-    surf, rhs = SURFACES[q.surface]
-    b = oracle.build_band(surf, q.h, 3, [-2.0] * 3, [2.0] * 3)
-    A = oracle.stabilized_operator(b, r.c_used)
-    f = rhs(b.cp[: b.n_act], q.seed)
-    for k in range(q.nsteps):
-        assert np.linalg.norm(f - A @ r.u[k]) / np.linalg.norm(f) <= 1.05e-8, k
-        f = r.c_used * r.u[k]
+    # each implicit step solves A u_k = c u_{k-1} to the tolerance with the
+    # request's own c (oracle operator), though its factors are those of the
+    # nearest quantised level: the request with the most steps and the one
+    # whose c is farthest from its level
+    far = max(mix, key=lambda x: abs(np.log(x.c / x.c_factor)))
+    assert abs(np.log(far.c / far.c_factor)) > 0.1
+    for r in {max(mix, key=lambda x: len(x.iters)).rid: None, far.rid: None}:
+        r = mix[r]
+        q = reqs[r.rid]
+        assert r.c == q.c
+        surf, rhs = SURFACES[q.surface]
+        b = oracle.build_band(surf, q.h, 3, [-2.0] * 3, [2.0] * 3)
+        A = oracle.stabilized_operator(b, q.c)
+        f = rhs(b.cp[: b.n_act], q.seed)
+        for k in range(q.nsteps):
+            assert np.linalg.norm(f - A @ r.u[k]) / np.linalg.norm(f) <= 1.05e-8, (r.rid, k)
+            f = q.c * r.u[k]

@@ -44,7 +44,7 @@ def test_poisson_requests_reproducible_and_in_range():
 def test_summary_percentiles():
     res = []
     for i in range(100):
-        r = serve.Result(i, ("s", 0.1, 1.0), 1.0, arrival=0.0, start=0.0, finish=(i + 1) / 1000.0)
+        r = serve.Result(i, ("s", 0.1, 1.0), 1.0, 1.0, arrival=0.0, start=0.0, finish=(i + 1) / 1000.0)
         r.iters = [10, 12]
         r.relres = [1e-9, 5e-9]
         r.hit = i % 4 != 0
@@ -70,14 +70,96 @@ def test_ledger_evicts_least_recently_used_idle_entries():
         e.last_used, e.busy = last, busy
         s._cache[k] = e
         s.used += nb
+    s._active = 1  # another request runs ("c" is busy)
     with s._lock:
-        s._reserve(35)  # 90 + 35 > 100: evict "b" (oldest idle) only
+        assert s._try_reserve(35)  # 90 + 35 > 100: evict "b" (oldest idle) only
     assert set(s._cache) == {"a", "c"} and s.used == 95 and s.evictions == 1
     with s._lock:
         with pytest.raises(MemoryError):
-            s._reserve(101)
+            s._try_reserve(101)
+        assert not s._try_reserve(50, keep="a")  # must wait: "a" is kept, "c" busy
+        assert set(s._cache) == {"a", "c"}
         s._release(35)
     assert s.used == 60 and s.peak_used == 95
+    s._active = 0  # nothing else runs: waiting could never end
+    with s._lock:
+        with pytest.raises(MemoryError):
+            s._try_reserve(50, keep="a")
+
+
+class _FakeBase:
+    """Host set-up stand-in: every factorisation reserves `peak`, keeps `resident`."""
+
+    def __init__(self, resident, peak):
+        self.fp = (resident, peak)
+
+    def footprint_estimate(self, prec, restart):
+        return self.fp
+
+
+class _HostServer(serve.Server):
+    """The request loop with the device work replaced by short sleeps, to test
+    the scheduling and the memory ledger on the host."""
+
+    def __init__(self, resident, peak, na, **kw):
+        super().__init__({"s": (None, lambda cp, seed: np.zeros(len(cp)))}, **kw)
+        self.fake = (_FakeBase(resident, peak), np.zeros((na, 3)), na)
+        self.max_used = 0
+
+    def _base(self, surface, h):
+        return self.fake
+
+    def _new_stream(self):
+        return None
+
+    def _make_factors(self, base, c_level):
+        with self._lock:
+            self.max_used = max(self.max_used, self.used)
+            assert self.used <= self.budget
+        import time
+        time.sleep(0.01)
+        return _FakeCtx()
+
+    def _solve(self, ctx, req, res, f, na, stream):
+        import time
+        with self._lock:
+            self.max_used = max(self.max_used, self.used)
+            assert self.used <= self.budget
+        time.sleep(0.002)
+        res.iters = [1] * req.nsteps
+        res.relres = [0.0] * req.nsteps
+
+
+def test_admission_without_deadlock_under_a_tight_budget():
+    """Four slots, a budget just above one factorisation's peak plus the vectors
+    of one request: factorisations happen one at a time, cached factors are
+    evicted for new ones, and every request finishes."""
+    import threading
+    na = 1000
+    resident, peak = 4000, 10000
+    vec = 33 * na * 8  # the largest request: 32 steps + the right-hand side
+    s = _HostServer(resident, peak, na, slots=4, budget_bytes=peak + vec + 100, c_levels=4)
+    reqs = serve.poisson_requests(40, 0.0, ["s"], [0.1], seed=3)
+    out = {}
+    th = threading.Thread(target=lambda: out.setdefault("r", s.run(reqs, realtime=False)), daemon=True)
+    th.start()
+    th.join(60)
+    assert not th.is_alive(), "request loop did not finish"
+    res = out["r"]
+    by_id = sorted(reqs, key=lambda r: r.rid)
+    assert len(res) == 40 and all(len(r.iters) == q.nsteps for r, q in zip(res, by_id))
+    assert s.max_used <= s.budget and s._active == 0
+    assert s.used == sum(e.resident for e in s._cache.values())  # only cached factors stay
+    assert all(r.c_factor in s.c_grid and r.c == q.c for r, q in zip(res, by_id))
+    assert s.n_factor >= len({s.key(r) for r in reqs})
+
+
+def test_admission_fails_loudly_when_a_request_can_never_fit():
+    na = 1000
+    s = _HostServer(4000, 10000, na, slots=2, budget_bytes=5000)
+    reqs = serve.poisson_requests(3, 0.0, ["s"], [0.1], seed=3)
+    with pytest.raises(RuntimeError, match="MemoryError"):
+        s.run(reqs, realtime=False)
 
 
 def test_clone_and_footprint_estimate_host_only():
