@@ -15,7 +15,7 @@ precisions are measured: `value` is the plain FP64 form, the FP32-factor form
 A serving leg follows (`serving` in the output): a request loop over a mix of
 surfaces (unit sphere, torus R = 1, r = 0.4, bumpy icosphere with 20480
 triangles) and grid spacings h in {0.05, 0.025, 0.0125}, c log-normal on
-[0.1, 10], 1-32 implicit steps per request, cached FP32 factors of 16
+[0.1, 10], 1-32 implicit steps per request (FGMRES(60)), cached FP32 factors of 16
 quantised c levels preconditioning the operator of the request's own c,
 admission by device-memory footprint, Poisson arrivals at 80% of the capacity
 for the stream (its steps at the cached-factor rate plus one factorisation per
@@ -360,6 +360,9 @@ def _run_gpu(args, wl, torch, P):
 
 SERVE_HS = (0.05, 0.025, 0.0125)
 SERVE_SLOTS = 4
+# FGMRES(60): restarted GMRES(30) stagnates on some h = 0.0125 torus requests
+# (about 320 subdomains, small c); 60 converges on all of them in fewer iterations
+SERVE_RESTART = 60
 SERVE_REQUESTS = 48
 
 
@@ -383,7 +386,7 @@ def run_serving(n_requests, hs=SERVE_HS):
     from paper_1909_08734_amd import serve
 
     surfaces = serve_surfaces()
-    srv = serve.Server(surfaces, slots=SERVE_SLOTS, prec=P.FP32, restart=RESTART, tol=TOL)
+    srv = serve.Server(surfaces, slots=SERVE_SLOTS, prec=P.FP32, restart=SERVE_RESTART, tol=TOL)
     names = sorted(surfaces)
     t0 = time.time()
     pairs = [(name, h) for name in names for h in hs]
@@ -391,24 +394,29 @@ def run_serving(n_requests, hs=SERVE_HS):
         srv._base(name, h)
         log(f"serving: host set-up of {name} h={h:g} done ({time.time() - t0:.1f}s)")
     log(f"serving: host set-up of {len(pairs)} (surface, h) pairs {time.time() - t0:.1f}s")
-    # capacity: two steps per (surface, h) near c = 1, run once to factor and
-    # once more with the factors cached (the second run is the one measured)
-    calib = [serve.Request(rid=q, surface=n, h=h, c=1.0, nsteps=2, seed=100 + q, arrival=0.0)
-             for q, (n, h) in enumerate(pairs)]
-    srv.run(calib, realtime=False)
-    first = srv.makespan
-    srv.run(calib, realtime=False)
-    mean_step = srv.makespan / (2 * len(calib))  # device time per step with all slots busy
-    t_factor = max(first - srv.makespan, 0.0) / len(calib)  # device time per factorisation
+    # capacity per (surface, h): one request of two steps near c = 1 run alone,
+    # once to factor and once more with the factors cached; the step time is
+    # the second run's, the factorisation time the difference
+    t_step, t_fac = {}, {}
+    for q, (n, h) in enumerate(pairs):
+        req = [serve.Request(rid=q, surface=n, h=h, c=1.0, nsteps=2, seed=100 + q, arrival=0.0)]
+        srv.run(req, realtime=False)
+        first = srv.makespan
+        srv.run(req, realtime=False)
+        t_step[(n, h)] = srv.makespan / 2
+        t_fac[(n, h)] = max(first - srv.makespan, 0.0)
+        log(f"serving: calibration {n} h={h:g}: step {1e3 * t_step[(n, h)]:.0f} ms, "
+            f"factorisation {t_fac[(n, h)]:.2f} s")
     # arrivals at 80% of the capacity for this request stream: its steps at the
-    # cached-factor rate plus one factorisation per distinct (surface, h, c level)
+    # cached-factor rate of their (surface, h) plus one factorisation per new key
     probe = serve.poisson_requests(n_requests, 1.0, names, list(hs), seed=6)
-    keys = {srv.key(r) for r in probe} - {srv.key(r) for r in calib}
-    busy = sum(r.nsteps for r in probe) * mean_step + len(keys) * t_factor
+    calib_keys = {(n, float(h), srv.quantise(1.0)) for n, h in pairs}
+    new_keys = {srv.key(r) for r in probe} - calib_keys
+    busy = (sum(r.nsteps * t_step[(r.surface, r.h)] for r in probe)
+            + sum(t_fac[(k[0], k[1])] for k in new_keys))
     rate = 0.8 * n_requests / busy
     reqs = serve.poisson_requests(n_requests, rate, names, list(hs), seed=6)
-    log(f"serving: step {mean_step * 1e3:.1f} ms, factorisation {t_factor:.2f} s, {len(keys)} new keys "
-        f"-> rate {rate:.2f}/s, {n_requests} requests")
+    log(f"serving: {len(new_keys)} new keys, busy {busy:.1f} s -> rate {rate:.3f}/s, {n_requests} requests")
     torch.cuda.synchronize()
     def progress(done, total):
         if done % 10 == 0 or done == total:
@@ -430,11 +438,14 @@ def run_serving(n_requests, hs=SERVE_HS):
                      + ", ".join(f"{h:g}" for h in hs) + "}"),
         "by_h": by_h,
         "arrival_rate_per_s": rate, "slots": SERVE_SLOTS, "c_levels": 16, "steps_per_request": "1-32",
-        "factors": "fp32 (fp64 krylov)", "budget_GB": srv.budget / 1e9, "peak_reserved_GB": srv.peak_used / 1e9,
-        "evictions": srv.evictions, "factorisations": srv.n_factor - len(calib),
-        "factor_s_total": srv.factor_s, "calibration_step_ms": mean_step * 1e3,
-        "calibration_factor_s": t_factor, "load": 0.8,
+        "factors": "fp32 (fp64 krylov)", "restart": SERVE_RESTART, "budget_GB": srv.budget / 1e9,
+        "peak_reserved_GB": srv.peak_used / 1e9, "evictions": srv.evictions,
+        "factorisations": srv.n_factor - len(pairs), "factor_s_total": srv.factor_s,
+        "calibration_step_ms": {f"{n} {h:g}": 1e3 * v for (n, h), v in t_step.items()},
+        "calibration_factor_s": {f"{n} {h:g}": v for (n, h), v in t_fac.items()}, "load": 0.8,
         "failed": int(sum(1 for r in out if r.status != P.OK)),
+        "failed_requests": [{"rid": r.rid, "key": list(r.key), "c": r.c, "iters": r.iters, "relres": r.relres,
+                             "status": r.status} for r in out if r.status != P.OK],
     })
     srv.close()
     return st

@@ -220,6 +220,35 @@ int cpm_precond_tiling(const cpm_ctx* ctx);
 int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms);
 
 /*
+ * Tiling of the apply for several right-hand sides at once (the lockstep
+ * batches of cpm_solve_device): rows of W_j per wave and 16-byte chunks in
+ * flight per row, 0: 2, 2; 1: 4, 1; 2: 4, 2 (FP64 default after cpm_factor);
+ * 3: 8, 1 (FP32 default). Every tiling
+ * forms each right-hand side's sums as the single apply does, so results do
+ * not depend on it. cpm_autotune_multi times every tiling `reps` times on the
+ * resident factors with the widest batch that fits (ESTATE when none does),
+ * keeps the fastest, returns it in *best and the CPM_MULTI_TILINGS average
+ * apply times in ms (both may be NULL); kernel timers are left unchanged.
+ */
+#define CPM_MULTI_TILINGS 4
+int cpm_set_multi_tiling(cpm_ctx* ctx, int tiling);
+int cpm_multi_tiling(const cpm_ctx* ctx);
+int cpm_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms);
+
+/*
+ * Kernel of the operator apply's extension step (Section 2.1, e = E x over
+ * the band): 0 gathers each row's (p+1)^3 stencil values of x from device
+ * memory; 1 (default) groups the rows by the grid position of their stencils
+ * and stages each group's x values, p+1 contiguous intervals of band indices,
+ * in LDS first (used while the largest group's x fits in 64 KB, else 0).
+ * Both form every sum in the same order, so results do not depend on the
+ * choice. cpm_operator_kernel reports the kernel in use. EINVAL for other
+ * values.
+ */
+int cpm_set_operator_kernel(cpm_ctx* ctx, int kernel);
+int cpm_operator_kernel(const cpm_ctx* ctx);
+
+/*
  * FGMRES iterations as HIP graphs (off by default): each iteration's kernels
  * for a given position k in the restart cycle are captured once and replayed;
  * the graphs are dropped whenever the factors, the operator, the Krylov space
@@ -270,6 +299,20 @@ int cpm_solve_device(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nrhs,
  */
 int cpm_solve_steps(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nsteps, double scale,
                     double tol, int max_iter, int restart, cpm_solve_info* info);
+
+/*
+ * The paper's formulation (Section 2.2 preconditions on the left; Section 6
+ * stops when the residual norm has fallen by 10^6): GMRES(restart) on
+ * M^{-1} A u = M^{-1} f from u = 0 until ||M^{-1}(f - A u)|| <= tol
+ * ||M^{-1} f|| (use tol = 1e-6 for the paper's rule), CGS2 Arnoldi; device
+ * pointers, one right-hand side. info->relres_est is that preconditioned
+ * ratio at exit, info->relres_true = ||f - A u|| / ||f||; the true residual
+ * this rule leaves depends on M (and so on the factor precision), which is
+ * why cpm_solve stops on the true residual instead. Same errors as cpm_solve;
+ * CPM_ENOTCONV at max_iter.
+ */
+int cpm_solve_left(cpm_ctx* ctx, const double* f_dev, double* u_dev, double tol, int max_iter, int restart,
+                   cpm_solve_info* info);
 
 /* (O)RAS as a stationary solver (eq. algRAS): u <- u + M^{-1}(f - A u) from
  * u = 0 until ||f - A u|| <= tol ||f|| or max_iter updates; device pointers

@@ -23,5 +23,5 @@ from .operator import (  # noqa: F401
 )
 from .partition import octant_partition, rcb_partition, graph_partition, align_interfaces  # noqa: F401
 from .schwarz import Decomposition, decompose, local_matrix, Preconditioner  # noqa: F401
-from .gmres import fgmres  # noqa: F401
+from .gmres import fgmres, gmres_left  # noqa: F401
 from .stationary import stationary  # noqa: F401

@@ -25,6 +25,7 @@ FP64, FP32 = 0, 1
 PART_OCTANT, PART_RCB, PART_GRAPH = 0, 1, 2
 PART_ALIGN = 16
 PRECOND_TILINGS = 8  # CPM_PRECOND_TILINGS
+MULTI_TILINGS = 4  # CPM_MULTI_TILINGS
 TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM, TIMER_KRYLOV, TIMER_UPDATE = 0, 1, 2, 3, 4, 5
 PHASES = ("precond", "operator", "orthogonalisation", "update")  # cpm_solve_info.phase_ms
 
@@ -76,12 +77,19 @@ _SIGS = {
     "cpm_precond_tiling": (C.c_int, [C.c_void_p]),
     "cpm_autotune_precond": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "cpm_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_set_operator_kernel": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_set_multi_tiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_multi_tiling": (C.c_int, [C.c_void_p]),
+    "cpm_autotune_multi": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "cpm_operator_kernel": (C.c_int, [C.c_void_p]),
     "cpm_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int,
                             C.POINTER(SolveInfo)]),
     "cpm_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int,
                                    C.c_int, C.POINTER(SolveInfo)]),
     "cpm_solve_steps": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double,
                                   C.c_int, C.c_int, C.POINTER(SolveInfo)]),
+    "cpm_solve_left": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
+                                 C.POINTER(SolveInfo)]),
     "cpm_solve_stationary": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                        C.POINTER(SolveInfo)]),
     "cpm_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -267,6 +275,28 @@ class Context:
     def precond_tiling(self):
         return int(self._L.cpm_precond_tiling(self._h))
 
+    def set_multi_tiling(self, tiling):
+        self._check(self._L.cpm_set_multi_tiling(self._h, int(tiling)), "set_multi_tiling")
+
+    def multi_tiling(self):
+        return int(self._L.cpm_multi_tiling(self._h))
+
+    def autotune_multi(self, reps=3):
+        """Time the batched-apply tilings on the resident factors and keep the fastest.
+        Returns (best tiling, [ms per tiling])."""
+        best = C.c_int()
+        ms = (C.c_double * MULTI_TILINGS)()
+        self._bind_stream()
+        self._check(self._L.cpm_autotune_multi(self._h, int(reps), C.byref(best), ms), "autotune_multi")
+        return best.value, list(ms)
+
+    def set_operator_kernel(self, kernel):
+        """Extension kernel of the operator apply: 0 gathers, 1 LDS-staged groups."""
+        self._check(self._L.cpm_set_operator_kernel(self._h, int(kernel)), "set_operator_kernel")
+
+    def operator_kernel(self):
+        return int(self._L.cpm_operator_kernel(self._h))
+
     def set_graphs(self, on=True):
         """Replay captured FGMRES iterations (HIP graphs) or launch kernels one by one."""
         self._check(self._L.cpm_set_graphs(self._h, 1 if on else 0), "set_graphs")
@@ -312,6 +342,15 @@ class Context:
         rc = self._check(self._L.cpm_solve_steps(self._h, _dev_ptr(f), _dev_ptr(u), nsteps, float(scale),
                                                  float(tol), int(max_iter), int(restart), info), "solve_steps")
         return [info[q].as_dict() for q in range(nsteps)], rc
+
+    def solve_left(self, f, u, tol=1e-6, max_iter=1000, restart=30):
+        """The paper's left-preconditioned GMRES on torch float64 HIP tensors f, u (N_A),
+        stopping when the preconditioned residual has fallen by 1/tol."""
+        info = SolveInfo()
+        self._bind_stream()
+        rc = self._check(self._L.cpm_solve_left(self._h, _dev_ptr(f), _dev_ptr(u), float(tol), int(max_iter),
+                                                int(restart), C.byref(info)), "solve_left")
+        return info.as_dict(), rc
 
     def solve_stationary(self, f, u, tol=1e-8, max_iter=1000):
         """(O)RAS as a stationary solver on torch float64 HIP tensors f, u (N_A)."""

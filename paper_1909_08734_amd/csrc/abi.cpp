@@ -270,6 +270,22 @@ int cpm_solve_steps(cpm_ctx* ctx, const double* f_dev, double* u_dev, int nsteps
   });
 }
 
+int cpm_solve_left(cpm_ctx* ctx, const double* f_dev, double* u_dev, double tol, int max_iter, int restart,
+                   cpm_solve_info* info) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "solve_left: factor first");
+  if (!f_dev || !u_dev) return fail(ctx, CPM_EINVAL, "solve_left: null vector");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, CPM_EINVAL, "solve_left: tol must be positive");
+  if (max_iter < 1) return fail(ctx, CPM_EINVAL, "solve_left: max_iter must be >= 1");
+  if (restart < 1 || restart > 64) return fail(ctx, CPM_EINVAL, "solve_left: restart must be in [1, 64]");
+  return guarded(ctx, [&]() -> int {
+    cpm_solve_info tmp{};
+    const int rc = cpm::dev_solve_left(ctx, f_dev, u_dev, tol, max_iter, restart, &tmp);
+    if (info) *info = tmp;
+    return rc;
+  });
+}
+
 int cpm_solve_stationary(cpm_ctx* ctx, const double* f_dev, double* u_dev, double tol, int max_iter,
                          cpm_solve_info* info) {
   if (!ctx) return CPM_EINVAL;
@@ -412,6 +428,31 @@ int cpm_set_precond_tiling(cpm_ctx* ctx, int tiling) {
 }
 
 int cpm_precond_tiling(const cpm_ctx* ctx) { return ctx ? ctx->dev.tiling : 0; }
+
+int cpm_set_multi_tiling(cpm_ctx* ctx, int tiling) {
+  if (!ctx) return CPM_EINVAL;
+  return cpm::dev_set_multi_tiling(ctx, tiling);
+}
+
+int cpm_multi_tiling(const cpm_ctx* ctx) { return ctx ? ctx->dev.multi_tiling : 0; }
+
+int cpm_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "autotune_multi: factor first");
+  if (reps < 1) return fail(ctx, CPM_EINVAL, "autotune_multi: reps must be >= 1");
+  return guarded(ctx, [&]() -> int { return cpm::dev_autotune_multi(ctx, reps, best, ms); });
+}
+
+int cpm_set_operator_kernel(cpm_ctx* ctx, int kernel) {
+  if (!ctx) return CPM_EINVAL;
+  return cpm::dev_set_operator_kernel(ctx, kernel);
+}
+
+int cpm_operator_kernel(const cpm_ctx* ctx) {
+  if (!ctx) return -1;
+  const cpm::Dev& d = ctx->dev;
+  return d.op_kernel == 1 && !(d.n_ext_groups > 0 && d.ext_lds <= 64 * 1024) ? 0 : d.op_kernel;
+}
 
 int cpm_set_graphs(cpm_ctx* ctx, int on) {
   if (!ctx) return CPM_EINVAL;

@@ -69,6 +69,19 @@ struct SubDesc {
   int32_t rpb;       // rows of W_j per apply block
 };
 
+// A group of extension rows for the LDS-staged operator apply: rows whose
+// interpolation stencils start in grid plane i = bi and in a window of
+// columns j; the x values all their stencils read lie, plane by plane, in P+1
+// contiguous intervals of band indices [lo[a], lo[a] + off[a+1] - off[a]),
+// staged in LDS at off[a].
+struct ExtGroup {
+  int32_t row0;    // first row of the group in apply order
+  int32_t nrows;   // rows in the group
+  int32_t lo[4];   // first band index of each plane's interval
+  int32_t off[5];  // LDS offsets of the intervals; off[P+1] = values staged
+  int32_t pad;
+};
+
 enum {
   TIMER_PRECOND = 0,
   TIMER_EXTEND = 1,
@@ -90,9 +103,15 @@ struct Timer {
 
 // Device-resident state.
 struct Dev {
-  // operator
-  int32_t* lines = nullptr;   // N_T x (p+1)^2
-  double* wts = nullptr;      // N_T x 3(p+1)
+  // operator (extension rows stored in apply order: grouped by stencil base)
+  int32_t* lines = nullptr;   // N_T x (p+1)^2, apply order
+  double* wts = nullptr;      // N_T x 3(p+1), apply order
+  int32_t* ext_perm = nullptr;  // apply position -> band row
+  int32_t* ext_pos = nullptr;   // band row -> apply position
+  ExtGroup* ext_groups = nullptr;
+  int n_ext_groups = 0;
+  size_t ext_lds = 0;           // LDS bytes of the largest group
+  int op_kernel = 1;            // 0: gathers from device memory, 1: LDS-staged groups
   int32_t* nbr = nullptr;     // 6 x N_A (structure of arrays)
   double* e = nullptr;        // N_T extension scratch
   // preconditioner
@@ -107,6 +126,7 @@ struct Dev {
   int n_groups = 0;             // subdomain groups of the last factorisation
   int chunk = 0;                // 0: v|Sigma_j staged whole; else columns per pass (chunked apply)
   int tiling = 0;               // tiling of the unchunked apply (see dev_set_tiling)
+  int multi_tiling = 0;         // tiling of the several-right-hand-side apply
   std::vector<SubDesc> hdesc;   // host copy of the apply descriptors
   int chunk_req = 0;            // requested chunk (0: only when v|Sigma_j exceeds LDS)
   size_t ws_limit = size_t(64) << 30;  // factor workspace per group, bytes
@@ -167,11 +187,16 @@ int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y);
 int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);
 int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
               cpm_solve_info* info);
+int dev_solve_left(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
+                   cpm_solve_info* info);
 int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, cpm_solve_info* info);
 int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol, int max_iter, int restart,
                     cpm_solve_info* info);
 int dev_batch_width(cpm_ctx* ctx, int nrhs);
 int dev_set_tiling(cpm_ctx* ctx, int t);
+int dev_set_operator_kernel(cpm_ctx* ctx, int k);
+int dev_set_multi_tiling(cpm_ctx* ctx, int t);
+int dev_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms);
 void drop_graphs(Dev& d);
 int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms);
 int dev_solve_steps(cpm_ctx* ctx, const double* f, double* u, int nsteps, double scale, double tol, int max_iter,

@@ -160,7 +160,78 @@ void dev_free_all(cpm_ctx* ctx) {
   dfree(d.wts);
   dfree(d.nbr);
   dfree(d.e);
+  dfree(d.ext_perm);
+  dfree(d.ext_pos);
+  dfree(d.ext_groups);
+  d.n_ext_groups = 0;
+  d.ext_lds = 0;
   d.op_bytes = 0;
+}
+
+// Apply order of the extension rows and their groups for the LDS-staged
+// apply: rows sorted by (stencil base plane, window of EXT_JW stencil base
+// columns), band order inside; a run of equal keys is cut into groups of at
+// most EXT_ROWS rows. The stencils of a group's rows read, in plane
+// bi + a, only columns j0 .. j0 + EXT_JW - 1 + p, whose active nodes are one
+// contiguous interval of band indices (band order is sorted by
+// L = (i n1 + j) n2 + k).
+constexpr int EXT_JW = 8;
+constexpr int EXT_ROWS = 512;
+constexpr size_t EXT_LDS_MAX = 64 * 1024;  // larger groups use the gathering kernel
+struct ExtPlan {
+  std::vector<int32_t> perm, pos;
+  std::vector<ExtGroup> groups;
+  size_t lds = 0;
+};
+
+static bool plan_extension(const Band& b, ExtPlan& E) {
+  const int P1 = b.p + 1, NL = P1 * P1;
+  const int64_t nt = b.total(), n1 = b.n[1], n2 = b.n[2];
+  const int64_t nw = (n1 + EXT_JW - 1) / EXT_JW;
+  std::vector<int64_t> key(nt);
+  for (int64_t r = 0; r < nt; ++r) key[r] = (int64_t)b.base[3 * r] * nw + b.base[3 * r + 1] / EXT_JW;
+  E.perm.resize(nt);
+  for (int64_t r = 0; r < nt; ++r) E.perm[r] = (int32_t)r;
+  std::stable_sort(E.perm.begin(), E.perm.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+  E.pos.assign(nt, 0);
+  for (int64_t q = 0; q < nt; ++q) E.pos[E.perm[q]] = (int32_t)q;
+  const int64_t* lin = b.lin.data();
+  const int64_t na = b.n_act;
+  for (int64_t q0 = 0; q0 < nt;) {
+    int64_t q1 = q0;
+    while (q1 < nt && key[E.perm[q1]] == key[E.perm[q0]]) ++q1;
+    const int32_t r0 = E.perm[q0];
+    const int64_t bi = b.base[3 * r0];
+    const int64_t j0 = b.base[3 * r0 + 1] / EXT_JW * EXT_JW;
+    const int64_t j1 = std::min<int64_t>(j0 + EXT_JW - 1 + b.p, n1 - 1);
+    ExtGroup g{};
+    g.off[0] = 0;
+    for (int a = 0; a < P1; ++a) {
+      const int64_t i = bi + a;
+      const int64_t L0 = (i * n1 + j0) * n2, L1 = (i * n1 + j1 + 1) * n2;
+      const int64_t lo = std::lower_bound(lin, lin + na, L0) - lin;
+      const int64_t hi = std::lower_bound(lin, lin + na, L1) - lin;
+      g.lo[a] = (int32_t)lo;
+      g.off[a + 1] = g.off[a] + (int32_t)(hi - lo);
+    }
+    // every z-line of every row of the run lies inside its plane's interval
+    for (int64_t q = q0; q < q1; ++q) {
+      const int32_t r = E.perm[q];
+      for (int a = 0; a < P1; ++a)
+        for (int bb = 0; bb < P1; ++bb) {
+          const int32_t s = b.lines[(int64_t)r * NL + a * P1 + bb];
+          if (s < g.lo[a] || s + b.p >= g.lo[a] + (g.off[a + 1] - g.off[a])) return false;
+        }
+    }
+    E.lds = std::max(E.lds, (size_t)g.off[P1] * sizeof(double));
+    for (int64_t c = q0; c < q1; c += EXT_ROWS) {
+      g.row0 = (int32_t)c;
+      g.nrows = (int32_t)std::min<int64_t>(EXT_ROWS, q1 - c);
+      E.groups.push_back(g);
+    }
+    q0 = q1;
+  }
+  return true;
 }
 
 int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
@@ -169,17 +240,43 @@ int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
   double* wts = nullptr;
   int32_t* nbr = nullptr;
   double* e = nullptr;
+  int32_t *perm = nullptr, *pos = nullptr;
+  ExtGroup* groups = nullptr;
   auto undo = [&](int code) {
     hipStreamSynchronize(ctx->stream);
     dfree(lines);
     dfree(wts);
     dfree(nbr);
     dfree(e);
+    dfree(perm);
+    dfree(pos);
+    dfree(groups);
     return code;
   };
   int rc;
-  if ((rc = upload(ctx, &lines, b.lines)) != CPM_OK) return undo(rc);
-  if ((rc = upload(ctx, &wts, b.wts)) != CPM_OK) return undo(rc);
+  ExtPlan E;
+  if (!plan_extension(b, E)) {
+    ctx->err = "operator upload: an interpolation stencil leaves its group's staged x (internal error)";
+    return CPM_EINVAL;
+  }
+  {  // extension rows in apply order, structure of arrays
+    const int P1 = b.p + 1, NL = P1 * P1, NW = 3 * P1;
+    const int64_t nt = b.total();
+    std::vector<int32_t> lp((size_t)nt * NL);
+    std::vector<double> wp((size_t)nt * NW);
+    for (int64_t q = 0; q < nt; ++q) {
+      const int64_t r = E.perm[q];
+      for (int l = 0; l < NL; ++l) lp[l * nt + q] = b.lines[r * NL + l];
+      for (int c = 0; c < NW; ++c) wp[c * nt + q] = b.wts[r * NW + c];
+    }
+    if ((rc = upload(ctx, &lines, lp)) != CPM_OK) return undo(rc);
+    if ((rc = upload(ctx, &wts, wp)) != CPM_OK) return undo(rc);
+    // the uploads read pageable host memory: finished before the vectors go
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  if ((rc = upload(ctx, &perm, E.perm)) != CPM_OK) return undo(rc);
+  if ((rc = upload(ctx, &pos, E.pos)) != CPM_OK) return undo(rc);
+  if ((rc = upload(ctx, &groups, E.groups)) != CPM_OK) return undo(rc);
   std::vector<int32_t> soa(b.n_act * 6);
   for (int64_t i = 0; i < b.n_act; ++i)
     for (int q = 0; q < 6; ++q) soa[q * b.n_act + i] = b.nbr[i * 6 + q];
@@ -197,7 +294,13 @@ int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
   d.wts = wts;
   d.nbr = nbr;
   d.e = e;
-  d.op_bytes = b.lines.size() * 4 + b.wts.size() * 8 + soa.size() * 4 + b.total() * 8;
+  d.ext_perm = perm;
+  d.ext_pos = pos;
+  d.ext_groups = groups;
+  d.n_ext_groups = (int)E.groups.size();
+  d.ext_lds = E.lds;
+  d.op_bytes = b.lines.size() * 4 + b.wts.size() * 8 + soa.size() * 4 + b.total() * 8 +
+               2 * E.perm.size() * 4 + E.groups.size() * sizeof(ExtGroup);
   return CPM_OK;
 }
 
@@ -208,25 +311,37 @@ static void launch_extend(cpm_ctx* ctx, const double* x, double* e, int nb = 1, 
   const Band& b = ctx->band;
   Dev& d = ctx->dev;
   const int64_t nt = b.total();
-  const dim3 grid(nblk(nt * 2, 256), nb);
+  if (d.op_kernel == 1 && d.n_ext_groups > 0 && d.ext_lds <= EXT_LDS_MAX) {
+    const dim3 grid(d.n_ext_groups, nb);
+    if (b.p == 3)
+      launch(ctx, TIMER_EXTEND, k_extend_lds<3>, grid, dim3(256), d.ext_lds, (const ExtGroup*)d.ext_groups, nt,
+             (const int32_t*)d.lines, (const double*)d.wts, (const int32_t*)d.ext_perm, x, e, x_stride, e_stride);
+    else
+      launch(ctx, TIMER_EXTEND, k_extend_lds<2>, grid, dim3(256), d.ext_lds, (const ExtGroup*)d.ext_groups, nt,
+             (const int32_t*)d.lines, (const double*)d.wts, (const int32_t*)d.ext_perm, x, e, x_stride, e_stride);
+    return;
+  }
+  const dim3 grid(nblk(nt, 256), nb);
   if (b.p == 3)
-    launch(ctx, TIMER_EXTEND, k_extend<3>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts, x,
-           e, x_stride, e_stride);
+    launch(ctx, TIMER_EXTEND, k_extend<3>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts,
+           (const int32_t*)d.ext_perm, x, e, x_stride, e_stride);
   else
-    launch(ctx, TIMER_EXTEND, k_extend<2>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts, x,
-           e, x_stride, e_stride);
+    launch(ctx, TIMER_EXTEND, k_extend<2>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts,
+           (const int32_t*)d.ext_perm, x, e, x_stride, e_stride);
 }
 
-// e = E x, y = A x (or y = f - A x when f != nullptr)
-static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const double* f) {
+// e = E x, y = A x (or y = f - A x when f != nullptr); e in the context's
+// extension scratch unless another buffer of N_T values is given
+static void launch_operator(cpm_ctx* ctx, const double* x, double* y, const double* f, double* e = nullptr) {
   const Band& b = ctx->band;
   Dev& d = ctx->dev;
   const double ih2 = 1.0 / (b.h * b.h);
   const double diag = ctx->c + 6.0 * ih2;
   const int64_t na = b.n_act;
-  launch_extend(ctx, x, d.e);
+  if (!e) e = d.e;
+  launch_extend(ctx, x, e);
   launch(ctx, TIMER_STENCIL, k_stencil, dim3(nblk(na, 256)), dim3(256), 0, na, diag, ih2, (const int32_t*)d.nbr, x,
-         (const double*)d.e, f, y);
+         (const double*)e, f, y);
 }
 
 // Tilings of the single-right-hand-side apply: rows per wave, 16-byte chunks
@@ -546,11 +661,11 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
     {
       dim3 grid(nblk(max_rows, 256), gn);
       if (b.p == 3)
-        k_assemble<T, 3><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
-                                                        gbx, gbs, gba, gtpos, diag, ih2, D.kind == CPM_ORAS, dA);
+        k_assemble<T, 3><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, b.total(), dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
+                                                        gbx, gbs, gba, gtpos, dv.ext_pos, diag, ih2, D.kind == CPM_ORAS, dA);
       else
-        k_assemble<T, 2><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
-                                                        gbx, gbs, gba, gtpos, diag, ih2, D.kind == CPM_ORAS, dA);
+        k_assemble<T, 2><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, b.total(), dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
+                                                        gbx, gbs, gba, gtpos, dv.ext_pos, diag, ih2, D.kind == CPM_ORAS, dA);
       FHIP(hipGetLastError());
     }
 
@@ -686,6 +801,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   dv.desc = ddesc;
   dv.hdesc = P.desc;
   dv.tiling = 0;
+  dv.multi_tiling = prec == CPM_FP64 ? 2 : 3;  // the measured best at the benchmark size
   dv.sig_idx = dU;
   dv.tilde_idx = dtidx;
   dv.blk_sub = dblk;
@@ -954,6 +1070,166 @@ int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter
 }
 
 // ---------------------------------------------------------------------------
+// GMRES(m) on the left-preconditioned system M^{-1} A u = M^{-1} f, the form
+// the paper gives (Section 2.2), with its stopping rule (Section 6): the
+// preconditioned residual ||M^{-1}(f - A u)|| reduced to tol ||M^{-1} f||.
+// x0 = 0, CGS2 Arnoldi, Givens; the basis vector V[k] is normalised on the fly
+// (M^{-1} A is linear: M^{-1} A (V[k] / ||V[k]||) is formed from the raw V[k]
+// with the scale folded into the preconditioner apply), and the solution is
+// u += V y. Z[0] holds A V[k] and the residual f - A u.
+// ---------------------------------------------------------------------------
+int dev_solve_left(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int m, cpm_solve_info* info) {
+  HIPCHK(hipSetDevice(ctx->device));
+  int rc = ensure_krylov(ctx, m);
+  if (rc != CPM_OK) return rc;
+  Dev& d = ctx->dev;
+  const int64_t na = ctx->band.n_act;
+  const SmallLayout L{m};
+  double* sm = d.small;
+  double* scal = sm + L.scal();
+  double* T = d.Z;
+  hipStream_t st = ctx->stream;
+  const unsigned gv = nblk(na, 256);
+  const int rb = red_blocks(na);
+  const double ih2 = 1.0 / (ctx->band.h * ctx->band.h);
+  const double diag = ctx->c + 6.0 * ih2;
+  PhaseClock clock;
+  clock.start(ctx);
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, st));
+  HostSlot* slots = d.slots;
+  std::vector<unsigned long long> expect(m + 2, 0);
+  auto ticket_for = [&](int slot) -> unsigned long long {
+    expect[slot] = ++d.ticket;
+    return expect[slot];
+  };
+  auto wait = [&](int slot, const double** out) -> int {
+    volatile unsigned long long* tk = &slots[slot].ticket;
+    for (long spin = 0;; ++spin) {
+      if (*tk == expect[slot]) break;
+      if ((spin & 1023) == 1023) {
+        const hipError_t q = hipStreamQuery(st);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+          ctx->err = std::string("solve_left: device error ") + hipGetErrorString(q);
+          return CPM_EDEVICE;
+        }
+        if (q == hipSuccess && *tk != expect[slot]) {
+          ctx->err = "solve_left: stream idle but the step's result never arrived";
+          return CPM_EDEVICE;
+        }
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *out = (const double*)slots[slot].v;
+    return CPM_OK;
+  };
+  // ||x|| of a device vector (its S_INV lands in the scalars, as for a basis vector)
+  auto norm_of = [&](const double* x, double* out) -> int {
+    launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, const_cast<double*>(x), (int64_t)0, 1, x,
+           d.part, -1, (const double*)nullptr);
+    launch(ctx, TIMER_KRYLOV, k_norm_finish, dim3(1), dim3(RED_THREADS), 0, (const double*)d.part, rb, L, sm,
+           d.slots_dev + (m + 1), ticket_for(m + 1));
+    const double* hv = nullptr;
+    const int r = wait(m + 1, &hv);
+    if (r == CPM_OK) *out = hv[S_BETA];
+    return r;
+  };
+  auto finish = [&](int code, int iters, int cycles, double rel_true, double rel_est) -> int {
+    hipEventRecord(t1, st);
+    hipEventSynchronize(t1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, t0, t1);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (info) {
+      info->iters = iters;
+      info->cycles = cycles;
+      info->status = code;
+      info->relres_true = rel_true;
+      info->relres_est = rel_est;
+      info->ms = ms;
+      clock.stop(ctx, info->phase_ms);
+    }
+    return code;
+  };
+  launch(ctx, TIMER_UPDATE, k_fill, dim3(gv), dim3(256), 0, na, u, 0.0);
+  double fnorm = 0.0, beta0 = 0.0;
+  if ((rc = norm_of(f, &fnorm)) != CPM_OK) return rc;
+  if (!std::isfinite(fnorm)) {
+    finish(CPM_EINVAL, 0, 0, NAN, NAN);
+    ctx->err = "solve_left: right-hand side is not finite";
+    return CPM_EINVAL;
+  }
+  if (fnorm == 0.0) return finish(CPM_OK, 0, 0, 0.0, 0.0);
+  launch_precond(ctx, f, d.V);  // V[0] = M^{-1} f (x0 = 0)
+  if ((rc = norm_of(d.V, &beta0)) != CPM_OK) return rc;
+  if (!(beta0 > 0.0) || !std::isfinite(beta0)) {
+    finish(CPM_EINVAL, 0, 0, NAN, NAN);
+    ctx->err = "solve_left: preconditioned right-hand side is zero or not finite";
+    return CPM_EINVAL;
+  }
+  int iters = 0, cycles = 0;
+  double rel = 1.0;
+  int status = CPM_ENOTCONV;
+  auto enqueue_iteration = [&](int k) {
+    double* vk = d.V + (size_t)k * d.ld;
+    double* w = d.V + (size_t)(k + 1) * d.ld;
+    const BatchStrides one{};
+    launch_extend(ctx, vk, d.e);  // T = A V[k] (raw), then w = M^{-1} T / ||V[k]||
+    launch(ctx, TIMER_STENCIL, k_stencil, dim3(gv), dim3(256), 0, na, diag, ih2, (const int32_t*)d.nbr,
+           (const double*)vk, (const double*)d.e, (const double*)nullptr, T);
+    launch_precond(ctx, T, w, scal + S_INV);
+    // CGS pass 1 (normalising V[k] in place), pass 2, ||w|| and the Givens update
+    launch(ctx, TIMER_KRYLOV, k_dots, dim3(rb), dim3(RED_THREADS), 0, na, d.V, d.ld, k + 1, (const double*)w, d.part,
+           k, (const double*)(scal + S_INV));
+    launch(ctx, TIMER_KRYLOV, k_reduce_cols, dim3(k + 1), dim3(RED_THREADS), 0, (const double*)d.part, rb,
+           sm + L.h1(), one);
+    launch(ctx, TIMER_KRYLOV, k_axpy_dots, dim3(rb), dim3(RED_THREADS), 0, na, (const double*)d.V, d.ld, k,
+           (const double*)(sm + L.h1()), w, d.part, 0, one);
+    launch(ctx, TIMER_KRYLOV, k_reduce_cols, dim3(k + 1), dim3(RED_THREADS), 0, (const double*)d.part, rb,
+           sm + L.h2(), one);
+    launch(ctx, TIMER_KRYLOV, k_axpy_dots, dim3(rb), dim3(RED_THREADS), 0, na, (const double*)d.V, d.ld, k,
+           (const double*)(sm + L.h2()), w, d.part, 1, one);
+    launch(ctx, TIMER_KRYLOV, k_arnoldi, dim3(1), dim3(RED_THREADS), 0, (const double*)d.part, rb, k, L, sm,
+           d.slots_dev + k, ticket_for(k), one);
+  };
+  for (;;) {
+    int kk = 0;
+    enqueue_iteration(0);
+    for (int k = 0; k < m; ++k) {
+      // iteration k+1 is queued before iteration k is checked
+      const bool more = k + 1 < m && iters + 1 < max_iter;
+      if (more) enqueue_iteration(k + 1);
+      const double* hs = nullptr;
+      if ((rc = wait(k, &hs)) != CPM_OK) return rc;
+      ++iters;
+      kk = k + 1;
+      if (!(hs[S_EST] > tol * beta0) || hs[S_HK1] == 0.0 || !more) break;
+    }
+    launch(ctx, TIMER_KRYLOV, k_backsolve, dim3(1), dim3(64), 0, kk, L, sm);
+    launch(ctx, TIMER_UPDATE, k_update_x, dim3(gv), dim3(256), 0, na, (const double*)d.V, d.ld, kk,
+           (const double*)(sm + L.y()), u);
+    launch_operator(ctx, u, T, f);  // T = f - A u
+    launch_precond(ctx, T, d.V);    // V[0] = M^{-1}(f - A u)
+    double beta = 0.0;
+    if ((rc = norm_of(d.V, &beta)) != CPM_OK) return rc;
+    ++cycles;
+    rel = beta / beta0;
+    if (rel <= tol) {
+      status = CPM_OK;
+      break;
+    }
+    if (iters >= max_iter || !std::isfinite(rel)) break;
+  }
+  double rnorm = 0.0;  // ||f - A u||: T still holds it
+  if ((rc = norm_of(T, &rnorm)) != CPM_OK) return rc;
+  HIPCHK(hipGetLastError());
+  return finish(status, iters, cycles, rnorm / fnorm, rel);
+}
+
+// ---------------------------------------------------------------------------
 // Several right-hand sides in lockstep: the per-iteration kernels run for the
 // whole batch in one launch each (blockIdx.y = right-hand side) and the
 // preconditioner streams W once for all of them. Each right-hand side follows
@@ -1003,26 +1279,43 @@ int dev_batch_width(cpm_ctx* ctx, int nrhs) {
   return 0;
 }
 
+// Tilings of the several-right-hand-side apply (rows per wave, chunks in
+// flight per row); every one gives the single apply's sums bit for bit.
+// Tiling t = (rows per wave, chunks in flight): 0 = (2, 2), 1 = (4, 1),
+// 2 = (4, 2), 3 = (8, 1).
+constexpr int N_MULTI_TILINGS = CPM_MULTI_TILINGS;
+
+template <typename T, int NB, int RPW, int UNR>
+static void launch_multi_t(cpm_ctx* ctx, size_t lds, const double* v, int64_t v_stride, const double* scale,
+                           int64_t scale_stride, double* z, int64_t z_stride) {
+  Dev& d = ctx->dev;
+  auto fn = k_precond_multi<T, NB, RPW, UNR>;
+  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  launch(ctx, TIMER_PRECOND, fn, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds, (const SubDesc*)d.desc,
+         (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx, (const int32_t*)d.tilde_idx, (const T*)d.W, v, v_stride,
+         scale, scale_stride, z, z_stride);
+}
+
+template <typename T, int NB>
+static void launch_multi_nb(cpm_ctx* ctx, size_t lds, const double* v, int64_t v_stride, const double* scale,
+                            int64_t scale_stride, double* z, int64_t z_stride) {
+  switch (ctx->dev.multi_tiling) {
+    case 1: launch_multi_t<T, NB, 4, 1>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
+    case 2: launch_multi_t<T, NB, 4, 2>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
+    case 3: launch_multi_t<T, NB, 8, 1>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
+    default: launch_multi_t<T, NB, 2, 2>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
+  }
+}
+
 template <int NB>
 static void launch_precond_multi(cpm_ctx* ctx, const double* v, int64_t v_stride, const double* scale,
                                  int64_t scale_stride, double* z, int64_t z_stride) {
   Dev& d = ctx->dev;
   const size_t lds = (size_t)NB * d.max_m * sizeof(double);
-  if (d.prec == CPM_FP64) {
-    if (lds > 64 * 1024)
-      hipFuncSetAttribute((const void*)k_precond_multi<double, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds);
-    launch(ctx, TIMER_PRECOND, k_precond_multi<double, NB>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
-           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
-           (const int32_t*)d.tilde_idx, (const double*)d.W, v, v_stride, scale, scale_stride, z, z_stride);
-  } else {
-    if (lds > 64 * 1024)
-      hipFuncSetAttribute((const void*)k_precond_multi<float, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds);
-    launch(ctx, TIMER_PRECOND, k_precond_multi<float, NB>, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds,
-           (const SubDesc*)d.desc, (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx,
-           (const int32_t*)d.tilde_idx, (const float*)d.W, v, v_stride, scale, scale_stride, z, z_stride);
-  }
+  if (d.prec == CPM_FP64)
+    launch_multi_nb<double, NB>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride);
+  else
+    launch_multi_nb<float, NB>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride);
 }
 
 int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol, int max_iter, int m,
@@ -1321,7 +1614,10 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
   const Decomp& D = ctx->dec;
   const bool oras = D.kind == CPM_ORAS;
   const size_t esz = prec == CPM_FP64 ? 8 : 4;
-  const size_t op = b.lines.size() * 4 + b.wts.size() * 8 + (size_t)b.n_act * 6 * 4 + (size_t)b.total() * 8;
+  ExtPlan E;
+  plan_extension(b, E);
+  const size_t op = b.lines.size() * 4 + b.wts.size() * 8 + (size_t)b.n_act * 6 * 4 + (size_t)b.total() * 8 +
+                    2 * E.perm.size() * 4 + E.groups.size() * sizeof(ExtGroup);
   int64_t w_elems = 0, u_total = 0, t_total = 0;
   std::vector<SubDesc> desc(D.n_sub);
   for (int j = 0; j < D.n_sub; ++j) {
@@ -1393,6 +1689,18 @@ int dev_set_tiling(cpm_ctx* ctx, int t) {
   return CPM_OK;
 }
 
+// Operator-apply kernel: 0 gathers x from device memory, 1 stages each
+// group's x in LDS (when the largest group fits); results are identical.
+int dev_set_operator_kernel(cpm_ctx* ctx, int k) {
+  if (k != 0 && k != 1) {
+    ctx->err = "operator kernel must be 0 or 1";
+    return CPM_EINVAL;
+  }
+  ctx->dev.op_kernel = k;
+  drop_graphs(ctx->dev);
+  return CPM_OK;
+}
+
 // Time every tiling on the resident factors (one warm-up and `reps` applies
 // each, HIP events on the context stream) and keep the fastest.
 int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms) {
@@ -1455,6 +1763,84 @@ int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms) {
   if (rc != CPM_OK) return rc;
   if (best) *best = arg;
   return dev_set_tiling(ctx, arg);
+}
+
+// Tiling of the several-right-hand-side apply; autotune times each on the
+// resident factors with the widest batch that fits (vectors an operator
+// apply has just written), keeping the caller's kernel timers unchanged.
+int dev_set_multi_tiling(cpm_ctx* ctx, int t) {
+  if (t < 0 || t >= N_MULTI_TILINGS) {
+    ctx->err = "multi tiling out of range";
+    return CPM_EINVAL;
+  }
+  ctx->dev.multi_tiling = t;
+  return CPM_OK;
+}
+
+int dev_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms) {
+  Dev& dv = ctx->dev;
+  const int nb = dev_batch_width(ctx, 4);
+  if (nb < 2) {
+    ctx->err = "autotune_multi: no batched apply for these factors";
+    return CPM_ESTATE;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t na = ctx->band.n_act;
+  double *v = nullptr, *z = nullptr;
+  HIPCHK(hipMalloc((void**)&v, (size_t)nb * na * sizeof(double)));
+  if (hipMalloc((void**)&z, (size_t)nb * na * sizeof(double)) != hipSuccess) {
+    dfree(v);
+    ctx->err = "autotune_multi: device allocation failed";
+    return CPM_ENOMEM;
+  }
+  k_fill<<<nblk((int64_t)nb * na, 256), 256, 0, ctx->stream>>>((int64_t)nb * na, z, 1.0);
+  Timer& tm = ctx->timer;
+  timer_harvest(ctx);
+  const bool was_on = tm.on;
+  double ms0[N_TIMERS];
+  int64_t n0[N_TIMERS];
+  for (int q = 0; q < N_TIMERS; ++q) {
+    ms0[q] = tm.ms[q];
+    n0[q] = tm.count[q];
+  }
+  auto pass = [&]() {
+    for (int q = 0; q < nb; ++q) launch_operator(ctx, z + (size_t)q * na, v + (size_t)q * na, nullptr);
+    if (nb == 4)
+      launch_precond_multi<4>(ctx, v, na, nullptr, 0, z, na);
+    else
+      launch_precond_multi<2>(ctx, v, na, nullptr, 0, z, na);
+  };
+  int arg = 0;
+  double tbest = 0.0;
+  for (int t = 0; t < N_MULTI_TILINGS; ++t) {
+    dv.multi_tiling = t;
+    tm.on = false;
+    pass();
+    timer_harvest(ctx);
+    const double m0 = tm.ms[TIMER_PRECOND];
+    const int64_t c0 = tm.count[TIMER_PRECOND];
+    tm.on = true;
+    for (int r = 0; r < reps; ++r) pass();
+    timer_harvest(ctx);
+    const int64_t n = tm.count[TIMER_PRECOND] - c0;
+    const double per = n > 0 ? (tm.ms[TIMER_PRECOND] - m0) / n : 0.0;
+    if (ms) ms[t] = per;
+    if (t == 0 || per < tbest) {
+      tbest = per;
+      arg = t;
+    }
+  }
+  tm.on = was_on;
+  for (int q = 0; q < N_TIMERS; ++q) {  // the caller's totals as they were
+    tm.ms[q] = ms0[q];
+    tm.count[q] = n0[q];
+  }
+  hipStreamSynchronize(ctx->stream);
+  dfree(v);
+  dfree(z);
+  dv.multi_tiling = arg;
+  if (best) *best = arg;
+  return CPM_OK;
 }
 
 // Implicit steps with resident factors: u_0 = A^{-1} f, u_k = A^{-1}(scale u_{k-1}).

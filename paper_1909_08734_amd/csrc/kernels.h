@@ -32,60 +32,139 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
 // ---------------------------------------------------------------------------
 // Operator apply (Section 2.1): e = E x over all band rows, then
 // y = (c + 6/h^2) x - (1/h^2) sum_{6 neighbours} e.
-// Extension: 2 lanes per row; lane h takes the stencil planes x = base_x + a
-// for a = 2h, 2h + 1 (a <= p), interpolates each of their p+1 z-lines (p+1
-// consecutive band entries) with w_z, combines them with w_y and w_x[a]; the
-// two lanes then add. (Few lanes per row keep many independent gathers in
-// flight per lane and need a single shuffle.)
+// The extension rows are stored in apply order (grouped by the grid position
+// of their interpolation stencil, see ExtGroup); perm[q] is the band row of
+// apply position q, and e is written in band order.
+//
+// Blocks are mapped to work XCD by XCD: the hardware hands consecutive block
+// indices to the eight XCDs in turn, so block b runs work item
+// xcd_item(b, n), which gives each XCD one contiguous eighth of the items and
+// keeps the x values its L2 serves to that eighth of the band.
 // ---------------------------------------------------------------------------
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int q = n / N_XCD, r = n % N_XCD, x = b % N_XCD;
+  return x * q + min(x, r) + b / N_XCD;
+}
+
+// One row's extension value from z-line starts s (P1 x P1) and its weights w
+// (3 x P1: x, y, z), x read through rd(index). Sum order: per plane a,
+// sum_b wy[b] (sum_c wz[c] x), then w[a] times that; planes (0,1) and (2,3)
+// summed apart and added, as the two-lane form does.
+template <int P, class RD>
+__device__ __forceinline__ double ext_plane(const double* __restrict__ w, const int32_t* s, RD rd) {
+  constexpr int P1 = P + 1;
+  double pa = 0.0;
+#pragma unroll
+  for (int b = 0; b < P1; ++b) {
+    double lz = 0.0;
+#pragma unroll
+    for (int c = 0; c < P1; ++c) lz += w[2 * P1 + c] * rd(s[b] + c);
+    pa += w[P1 + b] * lz;
+  }
+  return pa;
+}
+
+// The same sum with each z-line's p+1 values read as 16-byte loads from its
+// 8-byte aligned start (half the load instructions of single values).
+typedef double d2u __attribute__((ext_vector_type(2))) __attribute__((aligned(8)));
 template <int P>
-__global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
-                                                const double* __restrict__ wts,
-                                                const double* __restrict__ x, double* __restrict__ e,
-                                                int64_t x_stride, int64_t e_stride) {
-  constexpr int P1 = P + 1, NL = P1 * P1, NW = 3 * P1;
-  x += blockIdx.y * x_stride;  // right-hand side blockIdx.y of a batch
-  e += blockIdx.y * e_stride;
-  static_assert(P1 <= 4, "two planes per lane");
-  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
-  const int hl = threadIdx.x & 1;
-  double acc = 0.0;
-  if (row < n_rows) {
-    const double* w = wts + row * NW;
-    double wy[P1], wz[P1];
+__device__ __forceinline__ double ext_plane_vec(const double* __restrict__ w, const int32_t* s,
+                                                const double* __restrict__ x) {
+  constexpr int P1 = P + 1;
+  double v[P1][P1];
 #pragma unroll
-    for (int c = 0; c < P1; ++c) {
-      wy[c] = w[P1 + c];
-      wz[c] = w[2 * P1 + c];
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int a = 2 * hl + q;
-      if (a < P1) {
-        int32_t s[P1];
-        if constexpr (P1 == 4) {
-          typedef int32_t i4v __attribute__((ext_vector_type(4)));
-          const i4v v = *reinterpret_cast<const i4v*>(lines + row * NL + a * P1);
-#pragma unroll
-          for (int b = 0; b < P1; ++b) s[b] = v[b];
-        } else {
-#pragma unroll
-          for (int b = 0; b < P1; ++b) s[b] = lines[row * NL + a * P1 + b];
-        }
-        double pa = 0.0;
-#pragma unroll
-        for (int b = 0; b < P1; ++b) {
-          double lz = 0.0;
-#pragma unroll
-          for (int c = 0; c < P1; ++c) lz += wz[c] * x[s[b] + c];
-          pa += wy[b] * lz;
-        }
-        acc += w[a] * pa;
-      }
+  for (int b = 0; b < P1; ++b) {
+    const d2u a0 = *reinterpret_cast<const d2u*>(x + s[b]);
+    v[b][0] = a0.x;
+    v[b][1] = a0.y;
+    if constexpr (P1 == 4) {
+      const d2u a1 = *reinterpret_cast<const d2u*>(x + s[b] + 2);
+      v[b][2] = a1.x;
+      v[b][3] = a1.y;
+    } else {
+      v[b][2] = x[s[b] + 2];
     }
   }
-  acc += __shfl_xor(acc, 1, 2);
-  if (row < n_rows && hl == 0) e[row] = acc;
+  double pa = 0.0;
+#pragma unroll
+  for (int b = 0; b < P1; ++b) {
+    double lz = 0.0;
+#pragma unroll
+    for (int c = 0; c < P1; ++c) lz += w[2 * P1 + c] * v[b][c];
+    pa += w[P1 + b] * lz;
+  }
+  return pa;
+}
+
+// Row data layout (apply order q, N_T rows): weights as structure of arrays,
+// wts[c * n + q] for c < 3(p+1) (x, y, z weights), z-line starts
+// lines[l * n + q] for l = a (p+1) + b < (p+1)^2, so that the lanes of a wave,
+// one row each, read every component of their rows with one coalesced load.
+// Extension by gathers from device memory, one lane per row.
+template <int P>
+__global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* __restrict__ lines,
+                                                const double* __restrict__ wts, const int32_t* __restrict__ perm,
+                                                const double* __restrict__ x, double* __restrict__ e,
+                                                int64_t x_stride, int64_t e_stride) {
+  constexpr int P1 = P + 1, NW = 3 * P1;
+  x += blockIdx.y * x_stride;  // right-hand side blockIdx.y of a batch
+  e += blockIdx.y * e_stride;
+  const int64_t row = (int64_t)xcd_item(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (row >= n_rows) return;
+  double wl[NW];
+#pragma unroll
+  for (int c = 0; c < NW; ++c) wl[c] = wts[c * n_rows + row];
+  double half[2] = {0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < P1; ++a) {
+    int32_t s[P1];
+#pragma unroll
+    for (int b = 0; b < P1; ++b) s[b] = lines[(a * P1 + b) * n_rows + row];
+    half[a >> 1] += wl[a] * ext_plane_vec<P>(wl, s, x);
+  }
+  e[perm[row]] = half[0] + half[1];
+}
+
+// Extension with x staged in LDS: block b serves ExtGroup xcd_item(b, n); the
+// group's P+1 intervals of x (contiguous band indices, one per stencil plane)
+// are copied to LDS with coalesced loads, then each row (one lane) reads its
+// (P+1)^3 stencil values from LDS. Same sums in the same order as k_extend.
+template <int P>
+__global__ __launch_bounds__(256) void k_extend_lds(const ExtGroup* __restrict__ groups, int64_t n_rows,
+                                                    const int32_t* __restrict__ lines,
+                                                    const double* __restrict__ wts,
+                                                    const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ x, double* __restrict__ e,
+                                                    int64_t x_stride, int64_t e_stride) {
+  constexpr int P1 = P + 1, NW = 3 * P1;
+  extern __shared__ double xs[];
+  x += blockIdx.y * x_stride;
+  e += blockIdx.y * e_stride;
+  const ExtGroup g = groups[xcd_item(blockIdx.x, gridDim.x)];
+#pragma unroll
+  for (int a = 0; a < P1; ++a) {
+    const double* src = x + g.lo[a];
+    double* dst = xs + g.off[a];
+    const int len = g.off[a + 1] - g.off[a];
+    for (int q = threadIdx.x; q < len; q += blockDim.x) dst[q] = src[q];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < g.nrows; r += blockDim.x) {
+    const int64_t row = (int64_t)g.row0 + r;
+    double wl[NW];
+#pragma unroll
+    for (int c = 0; c < NW; ++c) wl[c] = wts[c * n_rows + row];
+    double half[2] = {0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < P1; ++a) {
+      int32_t s[P1];
+#pragma unroll
+      for (int b = 0; b < P1; ++b) s[b] = lines[(a * P1 + b) * n_rows + row] - g.lo[a] + g.off[a];
+      half[a >> 1] += wl[a] * ext_plane<P>(wl, s, [&](int32_t i) { return xs[i]; });
+    }
+    e[perm[row]] = half[0] + half[1];
+  }
 }
 
 // y = diag x - ih2 * sum_nb e[nb]           (f == nullptr)
@@ -95,7 +174,7 @@ __global__ __launch_bounds__(256) void k_stencil(int64_t na, double diag, double
                                                  const double* __restrict__ x,
                                                  const double* __restrict__ e,
                                                  const double* __restrict__ f, double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)xcd_item(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= na) return;
   const double s = (e[nbr[i]] + e[nbr[na + i]]) + (e[nbr[2 * na + i]] + e[nbr[3 * na + i]]) +
                    (e[nbr[4 * na + i]] + e[nbr[5 * na + i]]);
@@ -353,12 +432,19 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
 // conflicts), each W element multiplied by all of them. For every
 // right-hand side the sums are formed in the order of k_precond, so a batched
 // apply equals NB single applies bit for bit.
-constexpr int MULTI_RPW = 2;
-// register budget (waves per SIMD) without spills
-constexpr int multi_waves(int nb, int vn) { return nb >= 4 ? (vn >= 4 ? 4 : 6) : (vn >= 4 ? 7 : 8); }
+// RPW rows per wave and UNR 16-byte chunks in flight per row are tunable as
+// in k_precond (the sums do not depend on them).
+// Register budget (waves per SIMD) without spills: accumulators, loads in
+// flight and the v values of a chunk for every right-hand side.
+// (Values from the compiler's register counts for each instance.)
+constexpr int multi_waves(int nb, int vn, int rpw, int unr) {
+  return (rpw == 2 && unr == 2) ? (nb >= 4 ? (vn >= 4 ? 4 : 6) : (vn >= 4 ? 7 : 8))
+         : vn >= 4 ? (rpw * unr <= 4 ? 4 : rpw == 8 ? 2 : 3)
+                   : (rpw * unr <= 4 ? (nb >= 4 ? 4 : 5) : (nb >= 4 && rpw == 8) ? 3 : 4);
+}
 
-template <typename T, int NB>
-__global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n)) void k_precond_multi(const SubDesc* __restrict__ desc,
+template <typename T, int NB, int MULTI_RPW, int UNR>
+__global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n, MULTI_RPW, UNR)) void k_precond_multi(const SubDesc* __restrict__ desc,
                                                                    const int32_t* __restrict__ blk_sub,
                                                                    const int32_t* __restrict__ sig_idx,
                                                                    const int32_t* __restrict__ tilde_idx,
@@ -370,7 +456,6 @@ __global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n)) void
   extern __shared__ double vs[];  // vs[q * ldw + c]
   typedef typename VecOf<T>::type VT;
   constexpr int VN = VecOf<T>::n;
-  constexpr int UNR = VecOf<T>::unroll;
   constexpr int CW = W_CW<T>;
   constexpr int64_t KS = (int64_t)W_TILE * CW;
   constexpr int NWAVE = PRECOND_THREADS / 64;
@@ -504,7 +589,7 @@ __device__ __forceinline__ int local_pos(const int32_t* __restrict__ srt, const 
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ desc, int64_t na,
+__global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ desc, int64_t na, int64_t n_rows,
                                                   const int32_t* __restrict__ lines,
                                                   const double* __restrict__ wts,
                                                   const int32_t* __restrict__ nbr,
@@ -515,8 +600,9 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
                                                   const double* __restrict__ bs,
                                                   const double* __restrict__ ba,
                                                   const int32_t* __restrict__ tilde_pos,
+                                                  const int32_t* __restrict__ ext_pos,
                                                   double diag, double ih2, int oras, T* __restrict__ A) {
-  constexpr int P1 = P + 1, NL = P1 * P1;
+  constexpr int P1 = P + 1;
   const int j = blockIdx.y;
   const SubDesc d = desc[j];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,14 +611,15 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
   const int32_t* srt = usrt + d.u_off;
   const int32_t* ps = upos + d.u_off;
   auto add_ext = [&](int32_t node, double scale) {
-    const double* w = wts + (int64_t)node * 3 * P1;
+    const int64_t at = ext_pos[node];  // the row's position in apply order (structure of arrays)
+    auto w = [&](int c) { return wts[c * n_rows + at]; };
     for (int a = 0; a < P1; ++a)
       for (int b = 0; b < P1; ++b) {
-        const int32_t s = lines[(int64_t)node * NL + a * P1 + b];
-        const double wab = w[a] * w[P1 + b];
+        const int32_t s = lines[(a * P1 + b) * n_rows + at];
+        const double wab = w(a) * w(P1 + b);
         for (int c = 0; c < P1; ++c) {
           const int q = local_pos(srt, ps, d.n, s + c);
-          if (q >= 0) row[q] = (T)((double)row[q] - scale * (wab * w[2 * P1 + c]));
+          if (q >= 0) row[q] = (T)((double)row[q] - scale * (wab * w(2 * P1 + c)));
         }
       }
   };

@@ -38,6 +38,7 @@ def test_binding_constants_match_header():
     enums = dict(re.findall(r"\bCPM_([A-Z0-9_]+)\s*=\s*(-?\d+)", text))
     values = {**enums, **defines}
     assert int(values["PRECOND_TILINGS"]) == P.PRECOND_TILINGS
+    assert int(values["MULTI_TILINGS"]) == P.MULTI_TILINGS
     for name in ("OK", "ENOTCONV", "EINVAL", "ESTATE", "ENOMEM", "ESINGULAR", "EDEVICE", "RAS", "ORAS", "FP64",
                  "FP32", "PART_OCTANT", "PART_RCB", "PART_GRAPH", "PART_ALIGN"):
         assert int(values[name]) == getattr(P, name), name

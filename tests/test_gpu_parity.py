@@ -169,6 +169,40 @@ def test_solve_matches_direct_solution(direct_cfg1, kind, prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("kind", ["RAS", "ORAS"])
+def test_left_preconditioned_solve_follows_oracle(direct_cfg1, kind):
+    """The paper's formulation: GMRES on M^{-1} A u = M^{-1} f stopping on a 10^6
+    reduction of the preconditioned residual, against the oracle's gmres_left
+    with the oracle's Schwarz preconditioner; at tol 1e-12 both reach the
+    direct solution."""
+    say("left-preconditioned solve", kind)
+    b, A, f, u_ref = direct_cfg1
+    alpha = 1 / np.sqrt(0.1)
+    ctx = P.Context(0)
+    ctx.build_band(ci.Sphere(), 0.1, 3)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_OCTANT, 8, None, 2, getattr(P, kind), alpha, 0.0)
+    ctx.factor(P.FP64)
+    dec = schwarz.decompose(b, oracle.octant_partition(b), 2, kind, alpha=alpha)
+    M = schwarz.Preconditioner(b, dec, 1.0)
+    for tol, slack in ((1e-6, 2), (1e-12, 3)):
+        fd = dev(f)
+        u = torch.zeros_like(fd)
+        info, rc = ctx.solve_left(fd, u, tol=tol, max_iter=500, restart=30)
+        x, oinfo = oracle.gmres_left(lambda v: A @ v, f, M.apply, tol=tol, restart=30, max_iter=500)
+        say("  tol", tol, "gpu", info["iters"], info["relres_est"], info["relres_true"], "oracle", oinfo["iters"],
+            oinfo["relres"], oinfo["relres_true"])
+        assert rc == P.OK and info["relres_est"] <= tol
+        assert abs(info["iters"] - oinfo["iters"]) <= slack
+        ug = u.cpu().numpy()
+        assert info["relres_true"] == pytest.approx(np.linalg.norm(f - A @ ug) / np.linalg.norm(f), rel=1e-6)
+        err = np.linalg.norm(ug - u_ref) / np.linalg.norm(u_ref)
+        assert err < (1e-4 if tol == 1e-6 else 1e-8), err
+    info, rc = ctx.solve_left(dev(np.zeros_like(f)), torch.zeros(b.n_act, dtype=torch.float64, device="cuda"))
+    assert rc == P.OK and info["iters"] == 0
+    ctx.close()
+
+
 def test_restarted_solve_follows_oracle(direct_cfg1):
     # short restart cycles: the restart path (update, true residual, new basis) is exercised
     say("restarted solve")
