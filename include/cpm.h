@@ -326,6 +326,19 @@ int cpm_solve_stationary(cpm_ctx* ctx, const double* f_dev, double* u_dev, doubl
 int cpm_apply_operator(cpm_ctx* ctx, const double* x_dev, double* y_dev);
 int cpm_apply_precond(cpm_ctx* ctx, const double* v_dev, double* z_dev);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): y = A x
+ * exactly as cpm_apply_operator, with the extension values E x held in a
+ * static device array of the library (one per device, 2^21 rows = 16 MiB,
+ * held until the process ends) instead of the context's scratch. Calls no
+ * allocating routine. EINVAL if the band has more than 2^21 rows (N_A + N_G).
+ * All contexts on a device share its array, so calls that overlap on one
+ * device (from different threads or streams) race; calls on one stream are
+ * ordered and every call writes all the rows it reads.
+ */
+int cpm_apply_operator_noalloc(cpm_ctx* ctx, const double* x_dev, double* y_dev);
+
 /* ---- queries (host copies of the set-up; any pointer may be NULL) ---- */
 int cpm_band_sizes(const cpm_ctx* ctx, int64_t* n_act, int64_t* n_ghost, int64_t shape[3]);
 /* lin: N_T linear indices (actives then ghosts); cp, nrm: N_T x 3; nbr: N_A x 6

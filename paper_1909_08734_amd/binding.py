@@ -94,6 +94,7 @@ _SIGS = {
                                        C.POINTER(SolveInfo)]),
     "cpm_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cpm_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cpm_apply_operator_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cpm_band_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64)]),
     "cpm_band_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
@@ -363,6 +364,11 @@ class Context:
     def apply_operator(self, x, y):
         self._bind_stream()
         self._check(self._L.cpm_apply_operator(self._h, _dev_ptr(x), _dev_ptr(y)), "apply_operator")
+
+    def apply_operator_noalloc(self, x, y):
+        """y = A x with the library's static extension scratch (no allocation)."""
+        self._bind_stream()
+        self._check(self._L.cpm_apply_operator_noalloc(self._h, _dev_ptr(x), _dev_ptr(y)), "apply_operator_noalloc")
 
     def apply_precond(self, v, z):
         self._bind_stream()

@@ -52,6 +52,11 @@ int cpm_create(cpm_ctx** out, int device) {
     ctx->stream = ctx->own_stream;
     ctx->device = device;
     ctx->host_only = false;
+    if (cpm::dev_init_context(ctx) != CPM_OK) {
+      hipStreamDestroy(ctx->own_stream);
+      delete ctx;
+      return CPM_EDEVICE;
+    }
   }
   *out = ctx;
   return CPM_OK;
@@ -307,6 +312,14 @@ int cpm_apply_operator(cpm_ctx* ctx, const double* x_dev, double* y_dev) {
   if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "apply_operator: host-only context");
   if (!x_dev || !y_dev) return fail(ctx, CPM_EINVAL, "apply_operator: null vector");
   return cpm::dev_apply_operator(ctx, x_dev, y_dev);
+}
+
+int cpm_apply_operator_noalloc(cpm_ctx* ctx, const double* x_dev, double* y_dev) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 2) return fail(ctx, CPM_ESTATE, "apply_operator_noalloc: build the operator first");
+  if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "apply_operator_noalloc: host-only context");
+  if (!x_dev || !y_dev) return fail(ctx, CPM_EINVAL, "apply_operator_noalloc: null vector");
+  return cpm::dev_apply_operator_noalloc(ctx, x_dev, y_dev);
 }
 
 int cpm_apply_precond(cpm_ctx* ctx, const double* v_dev, double* z_dev) {

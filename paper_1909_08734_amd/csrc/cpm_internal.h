@@ -114,6 +114,7 @@ struct Dev {
   int op_kernel = 1;            // 0: gathers from device memory, 1: LDS-staged groups
   int32_t* nbr = nullptr;     // 6 x N_A (structure of arrays)
   double* e = nullptr;        // N_T extension scratch
+  double* static_e = nullptr; // device address of the static extension scratch (no-allocation apply)
   // preconditioner
   SubDesc* desc = nullptr;
   int32_t* blk_sub = nullptr;   // apply block -> subdomain
@@ -184,6 +185,10 @@ namespace cpm {
 int dev_upload_operator(cpm_ctx* ctx, const Band& b);
 int dev_factor(cpm_ctx* ctx, int prec);
 int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y);
+// Rows of the static extension scratch used by dev_apply_operator_noalloc.
+constexpr int64_t NOALLOC_ROWS = int64_t(1) << 21;
+int dev_init_context(cpm_ctx* ctx);  // once per context, device current
+int dev_apply_operator_noalloc(cpm_ctx* ctx, const double* x, double* y);
 int dev_apply_precond(cpm_ctx* ctx, const double* v, double* z);
 int dev_solve(cpm_ctx* ctx, const double* f, double* u, double tol, int max_iter, int restart,
               cpm_solve_info* info);

@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include <hip/hip_ext.h>
 
 #include "kernels.h"
@@ -412,6 +414,47 @@ static void launch_precond(cpm_ctx* ctx, const double* v, double* z, const doubl
 int dev_apply_operator(cpm_ctx* ctx, const double* x, double* y) {
   HIPCHK(hipSetDevice(ctx->device));
   launch_operator(ctx, x, y, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return CPM_OK;
+}
+
+// Extension scratch of cpm_apply_operator_noalloc: a static device array
+// (each device holds its own copy for the life of the process). Host code
+// uses only the device address looked up per device, never the array's name.
+static __device__ __align__(256) double scratch[NOALLOC_ROWS];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_ptr;  // per device
+
+int dev_init_context(cpm_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= ctx->device) g_scratch_ptr.resize(ctx->device + 1, nullptr);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      ctx->err = std::string("device scratch lookup: ") + hipGetErrorString(e);
+      return CPM_EDEVICE;
+    }
+    g_scratch_ptr[ctx->device] = (double*)p;
+  }
+  ctx->dev.static_e = g_scratch_ptr[ctx->device];
+  return CPM_OK;
+}
+
+int dev_apply_operator_noalloc(cpm_ctx* ctx, const double* x, double* y) {
+  const int64_t nt = ctx->band.total();
+  if (nt > NOALLOC_ROWS) {
+    ctx->err = "apply_operator_noalloc: the band has " + std::to_string(nt) + " rows, the static scratch holds " +
+               std::to_string(NOALLOC_ROWS);
+    return CPM_EINVAL;
+  }
+  if (!ctx->dev.static_e) {
+    ctx->err = "apply_operator_noalloc: no device scratch";
+    return CPM_EDEVICE;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_operator(ctx, x, y, nullptr, ctx->dev.static_e);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return CPM_OK;
