@@ -159,20 +159,32 @@ def pmc_traffic(kind, source_hash, tiling):
     return by[tiling] if tiling < len(by) else None
 
 
+def operator_bytes(ctx, na, ng, degree=3):
+    """Algorithmic bytes of one operator apply with the extension kernel in use:
+    N_A (x 8 + y 8 + neighbour indices 24) + N_T times the stored row: compact
+    rows (kernel 0: stencil coordinates 24, plane starts 4(p+1), increments
+    2 p(p+1)) or full rows (weights 24(p+1), z-line starts 4(p+1)^2)."""
+    nt = na + ng
+    p1 = degree + 1
+    compact = nt * (3 * 8 + 4 * p1 + 2 * p1 * degree)
+    full = nt * (8 * 3 * p1 + 4 * p1 * p1)
+    row = compact if ctx.operator_kernel() == 0 else full
+    return na * (8 + 8 + 24) + row, na * (8 + 8 + 24) + full
+
+
 def operator_roofline(ctx, torch, P, na, ng, reps=50, degree=3):
     """Operator apply (extension + stencil) timed by HIP events: warm (repeated
     applies, band data resident in the 256 MB last-level cache) and cold (a
     1 GiB copy between applies evicts it, as the preconditioner's stream does
-    inside a solve). Algorithmic bytes: N_A (x 8 + y 8 + neighbour indices 24)
-    + N_T (weights 24(p+1) + z-line starts 4(p+1)^2)."""
-    nt = na + ng
-    p1 = degree + 1
-    nbytes = na * (8 + 8 + 24) + nt * (8 * 3 * p1 + 4 * p1 * p1)
+    inside a solve). `GBs` uses the bytes of the row form in use,
+    `GBs_full_rows` the bytes of the full stored rows (weights and every z-line
+    start) that the compact form replaces."""
+    nbytes, full = operator_bytes(ctx, na, ng, degree)
     x = torch.randn(na, dtype=torch.float64, device="cuda")
     y = torch.zeros_like(x)
     big = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     big2 = torch.empty_like(big)
-    out = {"bytes_per_apply": nbytes}
+    out = {"kernel": ctx.operator_kernel(), "N_A": na, "bytes_per_apply": nbytes, "bytes_full_rows": full}
     for mode in ("warm", "cold"):
         ctx.apply_operator(x, y)
         ctx.set_timing(True)
@@ -184,9 +196,24 @@ def operator_roofline(ctx, torch, P, na, ng, reps=50, degree=3):
         st_ms, st_n = ctx.kernel_time(P.TIMER_STENCIL)
         ctx.set_timing(False)
         t = ext_ms / ext_n + st_ms / st_n
-        out[mode] = {"extend_us": 1e3 * ext_ms / ext_n, "stencil_us": 1e3 * st_ms / st_n,
-                     "GBs": nbytes / (t * 1e-3) / 1e9, "frac_of_8TBs": nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[mode] = {"extend_us": 1e3 * ext_ms / ext_n, "stencil_us": 1e3 * st_ms / st_n, "apply_us": 1e3 * t,
+                     "GBs": nbytes / (t * 1e-3) / 1e9, "frac_of_8TBs": nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "GBs_full_rows": full / (t * 1e-3) / 1e9}
     del big, big2
+    return out
+
+
+def operator_roofline_torus(torch, P):
+    """The operator apply on the largest band of the configurations: torus
+    R = 1, r = 0.4, h = 0.0125 (N_A = 700,664)."""
+    import cpm_inputs as ci
+    ctx = P.Context(0)
+    ctx.build_band(ci.Torus(1.0, 0.4), 0.0125, 3)
+    ctx.build_operator(0.5)
+    na, ng, _ = ctx.band_sizes()
+    out = operator_roofline(ctx, torch, P, na, ng)
+    out["workload"] = "torus R=1 r=0.4 h=0.0125"
+    ctx.close()
     return out
 
 
@@ -236,6 +263,9 @@ def _run_gpu(args, wl, torch, P):
     torch.cuda.synchronize()
     op = operator_roofline(ctx, torch, P, na, ng)
     log(f"operator apply: {json.dumps(op)}")
+    if args.workload == DEFAULT_WORKLOAD:
+        op["torus_h0.0125"] = operator_roofline_torus(torch, P)
+        log(f"operator apply, torus: {json.dumps(op['torus_h0.0125'])}")
     kind = P.ORAS if wl["kind"] == "ORAS" else P.RAS
     method = P.PART_OCTANT if wl["method"] == "octant" else P.PART_RCB
     weights = wl["weights"]() if wl["weights"] else None

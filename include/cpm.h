@@ -220,6 +220,26 @@ int cpm_precond_tiling(const cpm_ctx* ctx);
 int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms);
 
 /*
+ * Tile of the LU's matrix-core trailing updates (the Schur-complement update
+ * after each outer block of 128 columns): rows x 64 columns with rows = 64 or
+ * 128; 0 (default) takes the tile cpm_autotune_factor chose for this device
+ * architecture and precision in this process, else 128. Both tiles form every
+ * element's sum in the same order, so the factors are identical; only the
+ * speed differs. Takes effect at the next cpm_factor. cpm_factor_tile reports
+ * the tile of the resident factors (0 before any). EINVAL for other values.
+ *
+ * cpm_autotune_factor factors the partitioned problem in `prec` once with
+ * each tile, times the update launches (HIP events; kernel timers left
+ * unchanged), caches the faster for the architecture and precision (used by
+ * later factorisations with tile 0, any context) and leaves the factors of the
+ * faster resident, as cpm_factor would. *best (may be NULL) receives its rows,
+ * ms (may be NULL) the two update times in ms (64, then 128).
+ */
+int cpm_set_factor_tile(cpm_ctx* ctx, int rows);
+int cpm_factor_tile(const cpm_ctx* ctx);
+int cpm_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms);
+
+/*
  * Tiling of the apply for several right-hand sides at once (the lockstep
  * batches of cpm_solve_device): rows of W_j per wave and 16-byte chunks in
  * flight per row, 0: 2, 2; 1: 4, 1; 2: 4, 2 (FP64 default after cpm_factor);
@@ -237,10 +257,15 @@ int cpm_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms);
 
 /*
  * Kernel of the operator apply's extension step (Section 2.1, e = E x over
- * the band): 0 gathers each row's (p+1)^3 stencil values of x from device
- * memory; 1 (default) groups the rows by the grid position of their stencils
- * and stages each group's x values, p+1 contiguous intervals of band indices,
- * in LDS first (used while the largest group's x fits in 64 KB, else 0).
+ * the band): 0 (default) reads each row in a compact form (its local stencil
+ * coordinates, from which the Lagrange weights are formed, and its z-line
+ * starts as 16-bit increments: 64 bytes a row for degree 3) and gathers its
+ * (p+1)^3 stencil values of x from device memory; 1 groups the rows by the
+ * grid position of their stencils and stages each group's x values, p+1
+ * contiguous intervals of band indices, in LDS first (used while the largest
+ * group's x fits in 64 KB); 2 reads the full stored rows (weights and every
+ * z-line start, 160 bytes a row for degree 3) and gathers. A kernel that
+ * cannot be used falls back to 2.
  * Both form every sum in the same order, so results do not depend on the
  * choice. cpm_operator_kernel reports the kernel in use. EINVAL for other
  * values.

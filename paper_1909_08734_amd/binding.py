@@ -78,6 +78,9 @@ _SIGS = {
     "cpm_autotune_precond": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "cpm_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_set_operator_kernel": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_set_factor_tile": (C.c_int, [C.c_void_p, C.c_int]),
+    "cpm_factor_tile": (C.c_int, [C.c_void_p]),
+    "cpm_autotune_factor": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "cpm_set_multi_tiling": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_multi_tiling": (C.c_int, [C.c_void_p]),
     "cpm_autotune_multi": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
@@ -275,6 +278,22 @@ class Context:
 
     def precond_tiling(self):
         return int(self._L.cpm_precond_tiling(self._h))
+
+    def set_factor_tile(self, rows=0):
+        """Rows of the LU trailing-update tile (64, 128; 0: the tuned one)."""
+        self._check(self._L.cpm_set_factor_tile(self._h, int(rows)), "set_factor_tile")
+
+    def factor_tile(self):
+        return int(self._L.cpm_factor_tile(self._h))
+
+    def autotune_factor(self, prec=FP64):
+        """Factor with each trailing-update tile, keep (and cache) the faster.
+        Returns (rows, [ms with 64, ms with 128])."""
+        best = C.c_int()
+        ms = (C.c_double * 2)()
+        self._bind_stream()
+        self._check(self._L.cpm_autotune_factor(self._h, int(prec), C.byref(best), ms), "autotune_factor")
+        return best.value, list(ms)
 
     def set_multi_tiling(self, tiling):
         self._check(self._L.cpm_set_multi_tiling(self._h, int(tiling)), "set_multi_tiling")

@@ -442,6 +442,28 @@ int cpm_set_precond_tiling(cpm_ctx* ctx, int tiling) {
 
 int cpm_precond_tiling(const cpm_ctx* ctx) { return ctx ? ctx->dev.tiling : 0; }
 
+int cpm_set_factor_tile(cpm_ctx* ctx, int rows) {
+  if (!ctx) return CPM_EINVAL;
+  if (rows != 0 && rows != 64 && rows != 128) return fail(ctx, CPM_EINVAL, "set_factor_tile: rows must be 0, 64 or 128");
+  ctx->dev.factor_tile = rows;
+  return CPM_OK;
+}
+
+int cpm_factor_tile(const cpm_ctx* ctx) { return ctx && ctx->state >= 4 ? ctx->dev.factor_tile_used : 0; }
+
+int cpm_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 3) return fail(ctx, CPM_ESTATE, "autotune_factor: partition first");
+  if (prec != CPM_FP64 && prec != CPM_FP32) return fail(ctx, CPM_EINVAL, "autotune_factor: precision must be FP64 or FP32");
+  if (ctx->host_only) return fail(ctx, CPM_EDEVICE, "autotune_factor: host-only context");
+  return guarded(ctx, [&]() -> int {
+    const int rc = cpm::dev_autotune_factor(ctx, prec, best, ms);
+    ctx->state = rc == CPM_OK ? 4 : 3;
+    ctx->c_factor = rc == CPM_OK ? ctx->c : 0.0;
+    return rc;
+  });
+}
+
 int cpm_set_multi_tiling(cpm_ctx* ctx, int tiling) {
   if (!ctx) return CPM_EINVAL;
   return cpm::dev_set_multi_tiling(ctx, tiling);
@@ -464,7 +486,9 @@ int cpm_set_operator_kernel(cpm_ctx* ctx, int kernel) {
 int cpm_operator_kernel(const cpm_ctx* ctx) {
   if (!ctx) return -1;
   const cpm::Dev& d = ctx->dev;
-  return d.op_kernel == 1 && !(d.n_ext_groups > 0 && d.ext_lds <= 64 * 1024) ? 0 : d.op_kernel;
+  if (d.op_kernel == 1 && !(d.n_ext_groups > 0 && d.ext_lds <= 64 * 1024)) return 2;  // falls back to gathers
+  if (d.op_kernel == 0 && !d.compact) return 2;
+  return d.op_kernel;
 }
 
 int cpm_set_graphs(cpm_ctx* ctx, int on) {

@@ -111,7 +111,11 @@ struct Dev {
   ExtGroup* ext_groups = nullptr;
   int n_ext_groups = 0;
   size_t ext_lds = 0;           // LDS bytes of the largest group
-  int op_kernel = 1;            // 0: gathers from device memory, 1: LDS-staged groups
+  int op_kernel = 0;            // 0: compact rows, gathers; 1: LDS-staged groups; 2: full rows, gathers
+  double* ext_s = nullptr;      // compact rows: 3 x N_T local stencil coordinates (apply order)
+  int32_t* ext_start = nullptr; // (p+1) x N_T first z-line start of each stencil plane
+  uint16_t* ext_step = nullptr; // (p+1) p x N_T increments between a plane's z-line starts
+  bool compact = false;         // the compact rows exist (increments fit 16 bits)
   int32_t* nbr = nullptr;     // 6 x N_A (structure of arrays)
   double* e = nullptr;        // N_T extension scratch
   double* static_e = nullptr; // device address of the static extension scratch (no-allocation apply)
@@ -128,6 +132,8 @@ struct Dev {
   int chunk = 0;                // 0: v|Sigma_j staged whole; else columns per pass (chunked apply)
   int tiling = 0;               // tiling of the unchunked apply (see dev_set_tiling)
   int multi_tiling = 0;         // tiling of the several-right-hand-side apply
+  int factor_tile = 0;          // rows of the LU trailing-update tile: 0 = tuned (or 128), 64 or 128
+  int factor_tile_used = 0;     // the tile of the resident factors
   std::vector<SubDesc> hdesc;   // host copy of the apply descriptors
   int chunk_req = 0;            // requested chunk (0: only when v|Sigma_j exceeds LDS)
   size_t ws_limit = size_t(64) << 30;  // factor workspace per group, bytes
@@ -201,6 +207,8 @@ int dev_batch_width(cpm_ctx* ctx, int nrhs);
 int dev_set_tiling(cpm_ctx* ctx, int t);
 int dev_set_operator_kernel(cpm_ctx* ctx, int k);
 int dev_set_multi_tiling(cpm_ctx* ctx, int t);
+int tuned_factor_tile(cpm_ctx* ctx, int prec);
+int dev_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms);
 int dev_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms);
 void drop_graphs(Dev& d);
 int dev_autotune(cpm_ctx* ctx, int reps, int* best, double* ms);

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include <map>
 #include <mutex>
 
 #include <hip/hip_ext.h>
@@ -165,6 +166,10 @@ void dev_free_all(cpm_ctx* ctx) {
   dfree(d.ext_perm);
   dfree(d.ext_pos);
   dfree(d.ext_groups);
+  dfree(d.ext_s);
+  dfree(d.ext_start);
+  dfree(d.ext_step);
+  d.compact = false;
   d.n_ext_groups = 0;
   d.ext_lds = 0;
   d.op_bytes = 0;
@@ -244,6 +249,9 @@ int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
   double* e = nullptr;
   int32_t *perm = nullptr, *pos = nullptr;
   ExtGroup* groups = nullptr;
+  double* ext_s = nullptr;
+  int32_t* ext_start = nullptr;
+  uint16_t* ext_step = nullptr;
   auto undo = [&](int code) {
     hipStreamSynchronize(ctx->stream);
     dfree(lines);
@@ -253,6 +261,9 @@ int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
     dfree(perm);
     dfree(pos);
     dfree(groups);
+    dfree(ext_s);
+    dfree(ext_start);
+    dfree(ext_step);
     return code;
   };
   int rc;
@@ -275,6 +286,38 @@ int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
     if ((rc = upload(ctx, &wts, wp)) != CPM_OK) return undo(rc);
     // the uploads read pageable host memory: finished before the vectors go
     HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  // compact rows: local stencil coordinates s = t - base, t = (cp - lo) / h
+  // (as the host set-up forms them), z-line starts as plane starts and
+  // 16-bit increments (band order is sorted by L, so they are positive)
+  bool compact = true;
+  {
+    const int P1 = b.p + 1, NL = P1 * P1;
+    const int64_t nt = b.total();
+    std::vector<double> sv((size_t)nt * 3);
+    std::vector<int32_t> stv((size_t)nt * P1);
+    std::vector<uint16_t> dv((size_t)nt * P1 * b.p);
+    for (int64_t q = 0; q < nt && compact; ++q) {
+      const int64_t r = E.perm[q];
+      for (int a = 0; a < 3; ++a) {
+        const double t = (b.cp[r * 3 + a] - b.lo[a]) / b.h;
+        sv[a * nt + q] = t - (double)b.base[r * 3 + a];
+      }
+      for (int a = 0; a < P1; ++a) {
+        stv[a * nt + q] = b.lines[r * NL + a * P1];
+        for (int bb = 1; bb < P1; ++bb) {
+          const int64_t inc = (int64_t)b.lines[r * NL + a * P1 + bb] - b.lines[r * NL + a * P1 + bb - 1];
+          if (inc < 0 || inc > 65535) compact = false;
+          dv[(a * b.p + bb - 1) * nt + q] = (uint16_t)inc;
+        }
+      }
+    }
+    if (compact) {
+      if ((rc = upload(ctx, &ext_s, sv)) != CPM_OK) return undo(rc);
+      if ((rc = upload(ctx, &ext_start, stv)) != CPM_OK) return undo(rc);
+      if ((rc = upload(ctx, &ext_step, dv)) != CPM_OK) return undo(rc);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
   }
   if ((rc = upload(ctx, &perm, E.perm)) != CPM_OK) return undo(rc);
   if ((rc = upload(ctx, &pos, E.pos)) != CPM_OK) return undo(rc);
@@ -301,8 +344,13 @@ int dev_upload_operator(cpm_ctx* ctx, const Band& b) {
   d.ext_groups = groups;
   d.n_ext_groups = (int)E.groups.size();
   d.ext_lds = E.lds;
+  d.ext_s = ext_s;
+  d.ext_start = ext_start;
+  d.ext_step = ext_step;
+  d.compact = compact;
   d.op_bytes = b.lines.size() * 4 + b.wts.size() * 8 + soa.size() * 4 + b.total() * 8 +
-               2 * E.perm.size() * 4 + E.groups.size() * sizeof(ExtGroup);
+               2 * E.perm.size() * 4 + E.groups.size() * sizeof(ExtGroup) +
+               (compact ? (size_t)b.total() * (3 * 8 + (b.p + 1) * 4 + (b.p + 1) * b.p * 2) : 0);
   return CPM_OK;
 }
 
@@ -324,6 +372,17 @@ static void launch_extend(cpm_ctx* ctx, const double* x, double* e, int nb = 1, 
     return;
   }
   const dim3 grid(nblk(nt, 256), nb);
+  if (d.op_kernel == 0 && d.compact) {
+    if (b.p == 3)
+      launch(ctx, TIMER_EXTEND, k_extend_compact<3>, grid, dim3(256), 0, nt, (const double*)d.ext_s,
+             (const int32_t*)d.ext_start, (const uint16_t*)d.ext_step, (const int32_t*)d.ext_perm, x, e, x_stride,
+             e_stride);
+    else
+      launch(ctx, TIMER_EXTEND, k_extend_compact<2>, grid, dim3(256), 0, nt, (const double*)d.ext_s,
+             (const int32_t*)d.ext_start, (const uint16_t*)d.ext_step, (const int32_t*)d.ext_perm, x, e, x_stride,
+             e_stride);
+    return;
+  }
   if (b.p == 3)
     launch(ctx, TIMER_EXTEND, k_extend<3>, grid, dim3(256), 0, nt, (const int32_t*)d.lines, (const double*)d.wts,
            (const int32_t*)d.ext_perm, x, e, x_stride, e_stride);
@@ -603,7 +662,7 @@ std::vector<std::pair<int, int>> factor_groups(const std::vector<SubDesc>& desc,
 }
 
 template <typename T>
-int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
+int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   const Band& b = ctx->band;
   const Decomp& D = ctx->dec;
   Dev& dv = ctx->dev;
@@ -777,7 +836,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
         sw.push_back({jb, cdiv(d.cols - K1, TRSM_COLS)});
         li.push_back({LuJob{j, K0, K1 - K0, 0, 0, LU_KMAX}, LU_KMAX / TRSM_COLS});
         gu.push_back({LuJob{j, K0, K1 - K0, K0, K1, d.cols}, cdiv(d.cols - K1, GEMM_TILE)});
-        gm.push_back({jb, cdiv(d.rows - K1, GEMM_TILE_R) * cdiv(d.cols - K1, GEMM_TILE)});
+        gm.push_back({jb, cdiv(d.rows - K1, tile_r) * cdiv(d.cols - K1, GEMM_TILE)});
       }
       add(L_SWAP, K0, sw);
       add(L_LINV, K0, li);
@@ -815,8 +874,12 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
           k_lu_gemm_u<T><<<L.units, 256, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm);
           break;
         case L_GEMM_TRAIL:
-          launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE_R, GEMM_TILE>, dim3(L.units), dim3(256), 0,
-                 (const SubDesc*)gdesc, dA, jb, pre, L.n_jobs);
+          if (tile_r == GEMM_TILE_R)
+            launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE_R, GEMM_TILE>, dim3(L.units), dim3(256), 0,
+                   (const SubDesc*)gdesc, dA, jb, pre, L.n_jobs);
+          else
+            launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE, GEMM_TILE>, dim3(L.units), dim3(256), 0,
+                   (const SubDesc*)gdesc, dA, jb, pre, L.n_jobs);
           break;
         case L_GEMM:
           launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(L.units), dim3(256), 0, (const SubDesc*)gdesc, dA, jb, pre,
@@ -843,6 +906,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec) {
   cleanup();
   dv.desc = ddesc;
   dv.hdesc = P.desc;
+  dv.factor_tile_used = tile_r;
   dv.tiling = 0;
   dv.multi_tiling = prec == CPM_FP64 ? 2 : 3;  // the measured best at the benchmark size
   dv.sig_idx = dU;
@@ -899,7 +963,80 @@ int dev_factor(cpm_ctx* ctx, int prec) {
   FactorPlan P;
   make_plan(ctx, P, dv.chunk > 0 ? n_cu * per_cu : n_cu * per_cu * kTilings[0].over2 / 2,
             dv.chunk > 0 ? PRECOND_RPB_MAX : 0);
-  return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec) : run_factor<float>(ctx, P, prec);
+  const int tile_r = dv.factor_tile ? dv.factor_tile : tuned_factor_tile(ctx, prec);
+  return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec, tile_r) : run_factor<float>(ctx, P, prec, tile_r);
+}
+
+// Rows of the trailing-update tile chosen by cpm_autotune_factor, per device
+// architecture and precision, for the life of the process (128 until tuned).
+static std::mutex g_tile_mu;
+static std::map<std::pair<std::string, int>, int> g_tile_cache;
+
+static std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  return prop.gcnArchName;
+}
+
+int tuned_factor_tile(cpm_ctx* ctx, int prec) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  const auto it = g_tile_cache.find({arch_name(ctx->device), prec});
+  return it == g_tile_cache.end() ? GEMM_TILE_R : it->second;
+}
+
+// Factor with each trailing-update tile (64 x 64, 128 x 64), time the
+// matrix-core update launches (HIP events; the caller's kernel timers are
+// left as they were), cache the faster for this architecture and precision,
+// and leave the factors of the faster in place. Both tiles form every
+// element's sum in the same order, so the factors are identical.
+int dev_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms) {
+  Dev& dv = ctx->dev;
+  Timer& tm = ctx->timer;
+  timer_harvest(ctx);
+  const bool was_on = tm.on;
+  double ms0[N_TIMERS];
+  int64_t n0[N_TIMERS];
+  for (int q = 0; q < N_TIMERS; ++q) {
+    ms0[q] = tm.ms[q];
+    n0[q] = tm.count[q];
+  }
+  const int saved = dv.factor_tile;
+  const int tiles[2] = {GEMM_TILE, GEMM_TILE_R};
+  double t[2] = {0, 0};
+  int rc = CPM_OK;
+  for (int q = 0; q < 2 && rc == CPM_OK; ++q) {
+    dv.factor_tile = tiles[q];
+    tm.on = true;
+    const double m0 = tm.ms[TIMER_LU_GEMM];
+    rc = dev_factor(ctx, prec);
+    timer_harvest(ctx);
+    t[q] = tm.ms[TIMER_LU_GEMM] - m0;
+  }
+  tm.on = was_on;
+  for (int q = 0; q < N_TIMERS; ++q) {
+    tm.ms[q] = ms0[q];
+    tm.count[q] = n0[q];
+  }
+  if (rc == CPM_OK) {
+    const int arg = t[0] < t[1] ? 0 : 1;
+    {
+      std::lock_guard<std::mutex> lk(g_tile_mu);
+      g_tile_cache[{arch_name(ctx->device), prec}] = tiles[arg];
+    }
+    if (best) *best = tiles[arg];
+    if (ms) {
+      ms[0] = t[0];
+      ms[1] = t[1];
+    }
+    dv.factor_tile = saved;
+    if (arg == 0) {  // the last factorisation used the other tile
+      dv.factor_tile = tiles[0];
+      rc = dev_factor(ctx, prec);
+      dv.factor_tile = saved;
+    }
+  }
+  dv.factor_tile = saved;
+  return rc;
 }
 
 int dev_export_w(cpm_ctx* ctx, int j, double* w) {
@@ -1660,7 +1797,8 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
   ExtPlan E;
   plan_extension(b, E);
   const size_t op = b.lines.size() * 4 + b.wts.size() * 8 + (size_t)b.n_act * 6 * 4 + (size_t)b.total() * 8 +
-                    2 * E.perm.size() * 4 + E.groups.size() * sizeof(ExtGroup);
+                    2 * E.perm.size() * 4 + E.groups.size() * sizeof(ExtGroup) +
+                    (size_t)b.total() * (3 * 8 + (b.p + 1) * 4 + (b.p + 1) * b.p * 2);
   int64_t w_elems = 0, u_total = 0, t_total = 0;
   std::vector<SubDesc> desc(D.n_sub);
   for (int j = 0; j < D.n_sub; ++j) {
@@ -1732,11 +1870,12 @@ int dev_set_tiling(cpm_ctx* ctx, int t) {
   return CPM_OK;
 }
 
-// Operator-apply kernel: 0 gathers x from device memory, 1 stages each
-// group's x in LDS (when the largest group fits); results are identical.
+// Operator-apply kernel: 0 compact rows with gathers of x from device memory
+// (when the increments fit 16 bits), 1 stages each group's x in LDS (when the
+// largest group fits), 2 full rows with gathers; results are identical.
 int dev_set_operator_kernel(cpm_ctx* ctx, int k) {
-  if (k != 0 && k != 1) {
-    ctx->err = "operator kernel must be 0 or 1";
+  if (k < 0 || k > 2) {
+    ctx->err = "operator kernel must be 0, 1 or 2";
     return CPM_EINVAL;
   }
   ctx->dev.op_kernel = k;

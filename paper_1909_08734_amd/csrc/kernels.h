@@ -126,6 +126,81 @@ __global__ __launch_bounds__(256) void k_extend(int64_t n_rows, const int32_t* _
   e[perm[row]] = half[0] + half[1];
 }
 
+// Lagrange basis on the nodes 0..P at s: l_m(s) = prod_{q != m} (s - q) /
+// prod_{q != m} (m - q), the products formed in q order and the denominator
+// exact, as the host set-up forms the stored weights (so both agree bit for
+// bit).
+// A denominator that is a power of two (+-1, +-2) divides exactly as a
+// product with its reciprocal; the others (+-6 for p = 3) are divided.
+constexpr int lagrange_den(int p, int m) {
+  int d = 1;
+  for (int q = 0; q <= p; ++q)
+    if (q != m) d *= m - q;
+  return d;
+}
+constexpr bool power_of_two(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <int P>
+__device__ __forceinline__ void lagrange_basis(double s, double* w) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    double num = 1.0;
+#pragma unroll
+    for (int q = 0; q <= P; ++q) {
+      if (q == m) continue;
+      num *= (s - (double)q);
+    }
+    constexpr int dd[4] = {lagrange_den(P, 0), lagrange_den(P, 1), lagrange_den(P, 2), P >= 3 ? lagrange_den(P, 3) : 1};
+    const int den = dd[m];
+    if (power_of_two(den < 0 ? -den : den))
+      w[m] = num * (1.0 / (double)den);
+    else
+      w[m] = num / (double)den;
+  }
+}
+
+// Extension from the compact row form: per row the local stencil coordinates
+// s (3 doubles; the weights are the Lagrange basis at s, formed here) and the
+// z-line starts as the first start of each stencil plane (int32) plus the
+// p increments to the next columns' starts (uint16): 64 bytes a row for
+// p = 3 instead of 160. Same sums in the same order as k_extend.
+template <int P>
+__global__ __launch_bounds__(256) void k_extend_compact(int64_t n_rows, const double* __restrict__ sloc,
+                                                        const int32_t* __restrict__ starts,
+                                                        const uint16_t* __restrict__ steps,
+                                                        const int32_t* __restrict__ perm,
+                                                        const double* __restrict__ x, double* __restrict__ e,
+                                                        int64_t x_stride, int64_t e_stride) {
+  constexpr int P1 = P + 1, NW = 3 * P1;
+  x += blockIdx.y * x_stride;
+  e += blockIdx.y * e_stride;
+  const int64_t row = (int64_t)xcd_item(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (row >= n_rows) return;
+  double sl[3];
+  int32_t st[P1];
+  uint16_t dz[P1 * P];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) sl[a] = sloc[a * n_rows + row];
+#pragma unroll
+  for (int a = 0; a < P1; ++a) st[a] = starts[a * n_rows + row];
+#pragma unroll
+  for (int q = 0; q < P1 * P; ++q) dz[q] = steps[q * n_rows + row];
+  double wl[NW];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) lagrange_basis<P>(sl[a], wl + a * P1);
+  double half[2] = {0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < P1; ++a) {
+    int32_t s[P1];
+    s[0] = st[a];
+#pragma unroll
+    for (int b = 1; b < P1; ++b) s[b] = s[b - 1] + (int32_t)dz[a * P + b - 1];
+    half[a >> 1] += wl[a] * ext_plane_vec<P>(wl, s, x);
+  }
+  e[perm[row]] = half[0] + half[1];
+}
+
 // Extension with x staged in LDS: block b serves ExtGroup xcd_item(b, n); the
 // group's P+1 intervals of x (contiguous band indices, one per stencil plane)
 // are copied to LDS with coalesced loads, then each row (one lane) reads its

@@ -66,9 +66,16 @@ def test_operator_apply(name, p):
     ctx.build_band(surf, h, p)
     ctx.build_operator(c)
     x = np.random.default_rng(1).standard_normal(b.n_act)
-    y = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
-    ctx.apply_operator(dev(x), y)
-    assert rel(y.cpu().numpy(), A @ x) < 1e-12
+    ys = []
+    for kernel in (0, 1, 2):  # compact rows, LDS-staged groups, full rows
+        ctx.set_operator_kernel(kernel)
+        assert ctx.operator_kernel() == kernel
+        y = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
+        ctx.apply_operator(dev(x), y)
+        ys.append(y.cpu().numpy())
+        assert rel(ys[-1], A @ x) < 1e-12
+    np.testing.assert_array_equal(ys[1], ys[0])  # same sums in the same order
+    np.testing.assert_array_equal(ys[2], ys[0])
     ctx.close()
 
 
@@ -367,6 +374,41 @@ def test_grouped_factorisation_is_identical(prec):
     assert r1 == r0 and p1 < p0
     for ctx in ctxs:
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
+def test_factor_tiles_are_identical_and_autotune_caches_the_faster(prec):
+    """Both trailing-update tiles give the same W_j bit for bit; the autotuner
+    keeps the faster and later factorisations (any context) use it."""
+    say("factor tiles", prec)
+    b, dec, ctx = _setup("torus", 3, "rcb", 16, 3, "ORAS", 4.47, 20.0)
+    js = (0, 7, 15)
+    got = {}
+    for rows in (64, 128):
+        ctx.set_factor_tile(rows)
+        ctx.factor(prec)
+        assert ctx.factor_tile() == rows
+        got[rows] = [ctx.factor_export(j) for j in js]
+    for a, c in zip(got[64], got[128]):
+        np.testing.assert_array_equal(a, c)
+    ctx.set_factor_tile(0)
+    best, ms = ctx.autotune_factor(prec)
+    say("  autotune", best, ms)
+    assert best in (64, 128) and ctx.factor_tile() == best and min(ms) > 0
+    for a, j in zip(got[64], js):
+        np.testing.assert_array_equal(ctx.factor_export(j), a)
+    other = P.Context(0)
+    other.build_band(SURF["torus"][0], SURF["torus"][1], 3)
+    other.build_operator(1.0)
+    other.partition(P.PART_RCB, 16, None, 3, P.ORAS, 4.47, 20.0)
+    other.factor(prec)
+    assert other.factor_tile() == best
+    np.testing.assert_array_equal(other.factor_export(0), got[64][0])
+    with pytest.raises(P.CpmError) as e:
+        ctx.set_factor_tile(32)
+    assert e.value.code == P.EINVAL
+    other.close()
+    ctx.close()
 
 
 @pytest.mark.parametrize("chunk", [8, 264, 1024])
