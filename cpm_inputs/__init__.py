@@ -235,7 +235,9 @@ def bumpy_icosphere(level: int = 5, amplitude: float = 0.05, lmax: int = 6, seed
 
 def _closest_on_triangles(p, a, b, c):
     """Closest points to p on triangles (a, b, c) (all (..., 3)), by the Voronoi
-    region of p with respect to the triangle's vertices and edges."""
+    region of p with respect to the triangle's vertices and edges (the published
+    point-triangle method of C. Ericson, Real-Time Collision Detection, 2005,
+    Section 5.1.5, whose names d1..d6 and va, vb, vc it keeps)."""
     ab = b - a
     ac = c - a
     ap = p - a
