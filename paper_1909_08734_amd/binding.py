@@ -117,11 +117,21 @@ EXPORTED = tuple(_SIGS)
 
 
 def lib():
-    """Load libcpm.so (raises if it has not been built)."""
+    """Load libcpm.so (raises if it has not been built).
+
+    torch is imported first when it is installed: its bundled HIP runtime has
+    the same soname as the one libcpm.so was linked against, so the library
+    then binds to that runtime and the process holds one HIP runtime (whose
+    streams the library can use). Loaded the other way round, the process
+    would hold two, and torch's could not open the device."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1909_08734_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

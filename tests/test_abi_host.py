@@ -31,6 +31,23 @@ def test_library_exports_every_declared_symbol():
     assert sorted(P.EXPORTED) == names
 
 
+def test_one_hip_runtime_in_the_process():
+    """Loading the library binds it to torch's HIP runtime (same soname), so a
+    fresh process that loads the library before touching torch holds one HIP
+    runtime, not two (two cannot both open the device)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1909_08734_amd as P\n"
+            "P.lib()\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "print(sorted(set(l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l)))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
+
+
 def test_binding_constants_match_header():
     """Every #define and enum value of the header is mirrored by the binding."""
     text = open(os.path.join(ROOT, "include", "cpm.h")).read()
