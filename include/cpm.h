@@ -224,8 +224,8 @@ int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms);
  * after each outer block of 128 columns): rows x 64 columns with rows = 64 or
  * 128; 0 (default) takes the tile cpm_autotune_factor chose for this device
  * architecture and precision in this process, else 128. Both tiles form every
- * element's sum in the same order, so the factors are identical; only the
- * speed differs. Takes effect at the next cpm_factor. cpm_factor_tile reports
+ * element's sum in the same order, so the factors have the same values; only
+ * the speed differs. Takes effect at the next cpm_factor. cpm_factor_tile reports
  * the tile of the resident factors (0 before any). EINVAL for other values.
  *
  * cpm_autotune_factor factors the partitioned problem in `prec` once with
@@ -238,6 +238,16 @@ int cpm_autotune_precond(cpm_ctx* ctx, int reps, int* best, double* ms);
 int cpm_set_factor_tile(cpm_ctx* ctx, int rows);
 int cpm_factor_tile(const cpm_ctx* ctx);
 int cpm_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms);
+
+/*
+ * Matrix-core work of the resident factorisation's Schur-complement updates
+ * (Section 5, LU of the local problems): 2 x rows x cols x k flops for every
+ * update tile computed, whole tiles as the matrix cores run them. Tiles whose
+ * multipliers or U12 block are exactly zero are not computed (they would
+ * change nothing), so this is well below the dense count of the bordered
+ * matrices. *flops receives it; ESTATE before cpm_factor.
+ */
+int cpm_factor_flops(const cpm_ctx* ctx, double* flops);
 
 /*
  * Tiling of the apply for several right-hand sides at once (the lockstep
@@ -377,6 +387,14 @@ int cpm_subdomain_sizes(const cpm_ctx* ctx, int j, int64_t sizes[5]);
 /* sorted band indices of each set; xstar, s, alpha are per B node (ORAS). */
 int cpm_subdomain_sets(const cpm_ctx* ctx, int j, int32_t* tilde, int32_t* sigma, int32_t* fin,
                        int32_t* ghost, int32_t* bnd, int32_t* xstar, double* s, double* alpha);
+/* Elimination order of the local unknowns used by cpm_factor (Section 5: the
+ * local problems are solved by LU): *n_unk receives n_j (|Sigma_j| + |B_j| for
+ * ORAS, |Sigma_j| for RAS) and order[p] the local unknown at position p, an
+ * index into [Sigma_j ; B_j] (either pointer may be NULL). Reverse
+ * Cuthill-McKee on the symmetrised pattern of A_j, computed by cpm_partition;
+ * it decides which products of the bordered LU are exactly zero, and leaves
+ * W_j as it is up to rounding. */
+int cpm_subdomain_order(const cpm_ctx* ctx, int j, int64_t* n_unk, int32_t* order);
 /* W_j (|Sigma~_j| x |Sigma_j|, row-major) copied to host as float64. */
 int cpm_factor_export(cpm_ctx* ctx, int j, double* w);
 /* Device bytes held for the band, operator, factors and Krylov workspace. */

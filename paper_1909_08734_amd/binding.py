@@ -104,6 +104,8 @@ _SIGS = {
     "cpm_partition_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p]),
     "cpm_subdomain_sizes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
     "cpm_subdomain_sets": (C.c_int, [C.c_void_p, C.c_int] + [C.c_void_p] * 8),
+    "cpm_factor_flops": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "cpm_subdomain_order": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "cpm_factor_export": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "cpm_footprint_bytes": (C.c_size_t, [C.c_void_p]),
     "cpm_footprint_estimate": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_size_t),
@@ -296,6 +298,13 @@ class Context:
     def factor_tile(self):
         return int(self._L.cpm_factor_tile(self._h))
 
+    def factor_flops(self):
+        """Matrix-core flops of the resident factorisation's updates (tiles
+        computed; exactly-zero tiles are skipped)."""
+        f = C.c_double()
+        self._check(self._L.cpm_factor_flops(self._h, C.byref(f)), "factor_flops")
+        return f.value
+
     def autotune_factor(self, prec=FP64):
         """Factor with each trailing-update tile, keep (and cache) the faster.
         Returns (rows, [ms with 64, ms with 128])."""
@@ -441,6 +450,10 @@ class Context:
         self._check(self._L.cpm_subdomain_sets(self._h, int(j), *[_ptr(out[k]) for k in
                                                                    ("tilde", "sigma", "final", "ghost", "bnd",
                                                                     "xstar", "s", "alpha")]), "subdomain_sets")
+        nu = C.c_int64(0)
+        self._check(self._L.cpm_subdomain_order(self._h, int(j), C.byref(nu), None), "subdomain_order")
+        out["order"] = np.empty(nu.value, np.int32)
+        self._check(self._L.cpm_subdomain_order(self._h, int(j), None, _ptr(out["order"])), "subdomain_order")
         return out
 
     def factor_export(self, j):

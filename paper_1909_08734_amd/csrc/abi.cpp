@@ -395,6 +395,16 @@ int cpm_subdomain_sets(const cpm_ctx* ctx, int j, int32_t* tilde, int32_t* sigma
   return CPM_OK;
 }
 
+int cpm_subdomain_order(const cpm_ctx* ctx, int j, int64_t* n_unk, int32_t* order) {
+  if (!ctx) return CPM_EINVAL;
+  if (ctx->state < 3) return CPM_ESTATE;
+  if (j < 0 || j >= ctx->dec.n_sub) return CPM_EINVAL;
+  const std::vector<int32_t>& o = ctx->dec.subs[j].order;
+  if (n_unk) *n_unk = (int64_t)o.size();
+  if (order && !o.empty()) std::memcpy(order, o.data(), o.size() * sizeof(int32_t));
+  return CPM_OK;
+}
+
 int cpm_factor_export(cpm_ctx* ctx, int j, double* w) {
   if (!ctx || !w) return CPM_EINVAL;
   if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "factor_export: factor first");
@@ -450,6 +460,13 @@ int cpm_set_factor_tile(cpm_ctx* ctx, int rows) {
 }
 
 int cpm_factor_tile(const cpm_ctx* ctx) { return ctx && ctx->state >= 4 ? ctx->dev.factor_tile_used : 0; }
+
+int cpm_factor_flops(const cpm_ctx* ctx, double* flops) {
+  if (!ctx || !flops) return CPM_EINVAL;
+  if (ctx->state < 4) return CPM_ESTATE;
+  *flops = ctx->dev.factor_flops;
+  return CPM_OK;
+}
 
 int cpm_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms) {
   if (!ctx) return CPM_EINVAL;

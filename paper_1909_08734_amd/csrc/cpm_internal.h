@@ -35,6 +35,11 @@ struct Band {
 struct Sub {
   std::vector<int32_t> tilde, sigma, fin, ghost, bnd, xstar;
   std::vector<double> s, alpha;
+  // Elimination order of the local unknowns for the factorisation: position p
+  // holds local unknown order[p] (an index into [Sigma_j ; B_j]); reverse
+  // Cuthill-McKee on the pattern of A_j, so that the LU factors stay inside a
+  // narrow profile and most of the bordered update is exactly zero.
+  std::vector<int32_t> order;
 };
 
 struct Decomp {
@@ -134,6 +139,7 @@ struct Dev {
   int multi_tiling = 0;         // tiling of the several-right-hand-side apply
   int factor_tile = 0;          // rows of the LU trailing-update tile: 0 = tuned (or 128), 64 or 128
   int factor_tile_used = 0;     // the tile of the resident factors
+  double factor_flops = 0;      // matrix-core flops of the last factorisation's Schur-complement updates
   std::vector<SubDesc> hdesc;   // host copy of the apply descriptors
   int chunk_req = 0;            // requested chunk (0: only when v|Sigma_j exceeds LDS)
   size_t ws_limit = size_t(64) << 30;  // factor workspace per group, bytes

@@ -534,7 +534,13 @@ namespace {
 
 struct FactorPlan {
   std::vector<SubDesc> desc;
-  std::vector<int32_t> U, usrt, upos, bx, tilde_pos, tilde_idx, blk_sub;
+  // U: [Sigma_j ; B_j] in band order (the apply reads Sigma_j from it); the
+  // factorisation's unknowns in elimination order: fU (band index), rcol
+  // (right-hand column of a Sigma_j unknown, -1 for B_j), usrt/upos (sorted
+  // lookup of fU), bx/bs/ba (B_j data by position); border rows: tilde_pos
+  // (position of the unit entry); W maps: wrow (W row -> border row), wcol
+  // (W column -> right-hand column, indexed like U).
+  std::vector<int32_t> U, fU, rcol, wrow, wcol, usrt, upos, bx, tilde_pos, tilde_idx, blk_sub;
   std::vector<double> bs, ba;
   int64_t a_elems = 0, w_elems = 0, u_total = 0;
   int max_m = 0, max_n = 0, max_rows = 0, n_blocks = 0;
@@ -601,28 +607,53 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) 
     blk += nb;
     a_off += (int64_t)d.rows * d.lda;
     w_off += w_rows_stored(d.t) * d.ldw;
-    // unknowns [Sigma_j ; B_j] and their sorted lookup
+    // unknowns [Sigma_j ; B_j]; the factorisation takes them in the
+    // subdomain's elimination order (identity when none is set)
     std::vector<int32_t> u(s.sigma);
     if (oras) u.insert(u.end(), s.bnd.begin(), s.bnd.end());
-    std::vector<int32_t> order(u.size());
-    for (size_t q = 0; q < u.size(); ++q) order[q] = (int32_t)q;
-    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return u[x] < u[y]; });
-    for (size_t q = 0; q < u.size(); ++q) {
+    std::vector<int32_t> ord(s.order);
+    if ((int)ord.size() != d.n) {
+      ord.resize(d.n);
+      for (int q = 0; q < d.n; ++q) ord[q] = q;
+    }
+    std::vector<int32_t> fu(d.n), pos_of(d.n), rc_of(d.m, 0);
+    for (int q = 0; q < d.n; ++q) {
+      fu[q] = u[ord[q]];
+      pos_of[ord[q]] = q;
+    }
+    std::vector<int32_t> srt(d.n);
+    for (int q = 0; q < d.n; ++q) srt[q] = q;
+    std::sort(srt.begin(), srt.end(), [&](int32_t x, int32_t y) { return fu[x] < fu[y]; });
+    int32_t rank = 0;
+    for (int q = 0; q < d.n; ++q) {
+      const int32_t li = ord[q];
+      const bool isb = li >= d.m;
       P.U.push_back(u[q]);
-      P.usrt.push_back(u[order[q]]);
-      P.upos.push_back(order[q]);
-      const bool isb = (int)q >= d.m;
-      P.bx.push_back(isb ? s.xstar[q - d.m] : 0);
-      P.bs.push_back(isb ? s.s[q - d.m] : 0.0);
-      P.ba.push_back(isb ? s.alpha[q - d.m] : 0.0);
+      P.fU.push_back(fu[q]);
+      P.usrt.push_back(fu[srt[q]]);
+      P.upos.push_back(srt[q]);
+      P.rcol.push_back(isb ? -1 : rank);
+      if (!isb) rc_of[li] = rank++;
+      P.bx.push_back(isb ? s.xstar[li - d.m] : 0);
+      P.bs.push_back(isb ? s.s[li - d.m] : 0.0);
+      P.ba.push_back(isb ? s.alpha[li - d.m] : 0.0);
     }
-    // positions of Sigma~_j inside Sigma_j (both sorted)
+    for (int q = 0; q < d.n; ++q) P.wcol.push_back(q < d.m ? rc_of[q] : 0);
+    // border rows: Sigma~_j (a subset of Sigma_j, both in band order) by position
+    std::vector<std::pair<int32_t, int32_t>> brow;
     size_t p = 0;
-    for (int32_t x : s.tilde) {
-      while (s.sigma[p] != x) ++p;
-      P.tilde_pos.push_back((int32_t)p);
-      P.tilde_idx.push_back(x);
+    for (size_t q = 0; q < s.tilde.size(); ++q) {
+      while (s.sigma[p] != s.tilde[q]) ++p;
+      brow.push_back({pos_of[p], (int32_t)q});
+      P.tilde_idx.push_back(s.tilde[q]);
     }
+    std::sort(brow.begin(), brow.end());
+    std::vector<int32_t> wrow(brow.size());
+    for (size_t i = 0; i < brow.size(); ++i) {
+      P.tilde_pos.push_back(brow[i].first);
+      wrow[brow[i].second] = (int32_t)i;
+    }
+    P.wrow.insert(P.wrow.end(), wrow.begin(), wrow.end());
     u_off += d.n;
     t_off += d.t;
     P.max_m = std::max(P.max_m, (int)d.ldw);
@@ -672,7 +703,10 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
 
   SubDesc *ddesc = nullptr, *gdesc = nullptr;
   int32_t *dU = nullptr, *dsrt = nullptr, *dpos = nullptr, *dbx = nullptr, *dtpos = nullptr, *dtidx = nullptr,
-          *dblk = nullptr, *dipiv = nullptr, *dinfo = nullptr, *dpre = nullptr;
+          *dblk = nullptr, *dipiv = nullptr, *dinfo = nullptr, *dpre = nullptr, *dfu = nullptr, *drc = nullptr,
+          *dwrow = nullptr, *dwcol = nullptr, *drowhi = nullptr, *dntile = nullptr;
+  int2* dlist = nullptr;
+  unsigned long long* dflops = nullptr;
   double *dbs = nullptr, *dba = nullptr;
   int64_t* dscr_off = nullptr;
   LuJob* jobs_buf = nullptr;
@@ -684,11 +718,12 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   auto free_group = [&]() {
     hipStreamSynchronize(ctx->stream);
     dfree(gdesc); dfree(dA); dfree(dscr); dfree(dscr_off); dfree(jobs_buf); dfree(dpre); dfree(dlm);
+    dfree(drowhi); dfree(dlist);
   };
   auto cleanup = [&]() {
     free_group();
     dfree(dsrt); dfree(dpos); dfree(dbx); dfree(dtpos); dfree(dipiv); dfree(dinfo);
-    dfree(dbs); dfree(dba);
+    dfree(dbs); dfree(dba); dfree(dfu); dfree(drc); dfree(dwrow); dfree(dwcol); dfree(dntile); dfree(dflops);
   };
   auto bail = [&](int code) {
     cleanup();
@@ -719,6 +754,13 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   FCHK(upload(ctx, &dtpos, P.tilde_pos));
   FCHK(upload(ctx, &dtidx, P.tilde_idx));
   FCHK(upload(ctx, &dblk, P.blk_sub));
+  FCHK(upload(ctx, &dfu, P.fU));
+  FCHK(upload(ctx, &drc, P.rcol));
+  FCHK(upload(ctx, &dwrow, P.wrow));
+  FCHK(upload(ctx, &dwcol, P.wcol));
+  FHIP(hipMalloc((void**)&dntile, sizeof(int32_t)));
+  FHIP(hipMalloc((void**)&dflops, sizeof(unsigned long long)));
+  FHIP(hipMemsetAsync(dflops, 0, sizeof(unsigned long long), ctx->stream));
   FHIP(hipMalloc((void**)&dipiv, P.u_total * sizeof(int32_t)));
   FHIP(hipMalloc((void**)&dinfo, ns * sizeof(int32_t)));
   FHIP(hipMemsetAsync(dinfo, 0, ns * sizeof(int32_t), ctx->stream));
@@ -730,6 +772,17 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   // rebased descriptors (a_off, u_off, t_off relative to the group; w_off
   // global, into the resident W arena).
   const std::vector<std::pair<int, int>> groups = factor_groups(P.desc, sizeof(T), dv.ws_limit);
+  // resident blocks of the listed trailing update
+  int trail_grid = 0;
+  {
+    int n_cu = 0, per_cu = 0;
+    FHIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    if (tile_r == GEMM_TILE_R)
+      FHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_gemm_list<T, GEMM_TILE_R, GEMM_TILE>, 256, 0));
+    else
+      FHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_gemm_list<T, GEMM_TILE, GEMM_TILE>, 256, 0));
+    trail_grid = std::max(1, n_cu * std::max(1, per_cu));
+  }
   for (const auto& gr : groups) {
     const int g0 = gr.first, gn = gr.second - gr.first;
     std::vector<SubDesc> gd(P.desc.begin() + g0, P.desc.begin() + gr.second);
@@ -746,7 +799,8 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
       max_rows = std::max(max_rows, (int)d.rows);
       tmax = std::max(tmax, (int)d.t);
     }
-    int32_t* gU = dU + u0;
+    int32_t* gU = dfu + u0;
+    int32_t* grc = drc + u0;
     int32_t* gsrt = dsrt + u0;
     int32_t* gpos = dpos + u0;
     int32_t* gbx = dbx + u0;
@@ -764,10 +818,12 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
       dim3 grid(nblk(max_rows, 256), gn);
       if (b.p == 3)
         k_assemble<T, 3><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, b.total(), dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
-                                                        gbx, gbs, gba, gtpos, dv.ext_pos, diag, ih2, D.kind == CPM_ORAS, dA);
+                                                        gbx, gbs, gba, gtpos, grc, dv.ext_pos, diag, ih2,
+                                                        D.kind == CPM_ORAS, dA);
       else
         k_assemble<T, 2><<<grid, 256, 0, ctx->stream>>>(gdesc, b.n_act, b.total(), dv.lines, dv.wts, dv.nbr, gU, gsrt, gpos,
-                                                        gbx, gbs, gba, gtpos, dv.ext_pos, diag, ih2, D.kind == CPM_ORAS, dA);
+                                                        gbx, gbs, gba, gtpos, grc, dv.ext_pos, diag, ih2,
+                                                        D.kind == CPM_ORAS, dA);
       FHIP(hipGetLastError());
     }
 
@@ -855,12 +911,18 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
     FCHK(upload(ctx, &dscr_off, scr_off));
     FHIP(hipMalloc((void**)&dscr, scr_total * sizeof(T)));
     FHIP(hipMalloc((void**)&dlm, (size_t)gn * LU_KMAX * LU_KMAX * sizeof(T)));
+    FHIP(hipMalloc((void**)&drowhi, (size_t)gn * 2 * sizeof(int32_t)));
+    int list_cap = 1;
+    for (const Launch& L : lplan)
+      if (L.kind == L_GEMM_TRAIL) list_cap = std::max(list_cap, L.units);
+    FHIP(hipMalloc((void**)&dlist, (size_t)list_cap * sizeof(int2)));
+    const LuJob* ujobs = nullptr;  // the jobs of the last U12 launch
     for (const Launch& L : lplan) {
       const LuJob* jb = jobs_buf + L.job_off;
       const int32_t* pre = dpre + L.job_off;
       switch (L.kind) {
         case L_PANEL:
-          k_lu_panel<T><<<gn, PANEL_THREADS, 0, ctx->stream>>>(gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off);
+          k_lu_panel<T><<<gn, PANEL_THREADS, 0, ctx->stream>>>(gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off, drowhi);
           break;
         case L_SWAP_TRSM:
         case L_SWAP:
@@ -868,36 +930,41 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
                                                                      L.kind == L_SWAP_TRSM ? 1 : 0);
           break;
         case L_LINV:
-          k_lu_linv<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm);
+          k_lu_linv<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm, dntile);
           break;
         case L_GEMM_U:  // not in the LU-update timer, which covers the Schur-complement updates
-          k_lu_gemm_u<T><<<L.units, 256, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm);
+          k_lu_gemm_u<T><<<L.units, 256, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm, drowhi, tile_r, dlist,
+                                                           dntile, dflops);
+          ujobs = jb;
           break;
-        case L_GEMM_TRAIL:
+        case L_GEMM_TRAIL:  // the tiles k_lu_gemm_u listed, on a grid of resident blocks
           if (tile_r == GEMM_TILE_R)
-            launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE_R, GEMM_TILE>, dim3(L.units), dim3(256), 0,
-                   (const SubDesc*)gdesc, dA, jb, pre, L.n_jobs);
+            launch(ctx, TIMER_LU_GEMM, k_lu_gemm_list<T, GEMM_TILE_R, GEMM_TILE>, dim3(trail_grid), dim3(256), 0,
+                   (const SubDesc*)gdesc, dA, ujobs, (const int2*)dlist, (const int32_t*)dntile);
           else
-            launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T, GEMM_TILE, GEMM_TILE>, dim3(L.units), dim3(256), 0,
-                   (const SubDesc*)gdesc, dA, jb, pre, L.n_jobs);
+            launch(ctx, TIMER_LU_GEMM, k_lu_gemm_list<T, GEMM_TILE, GEMM_TILE>, dim3(trail_grid), dim3(256), 0,
+                   (const SubDesc*)gdesc, dA, ujobs, (const int2*)dlist, (const int32_t*)dntile);
           break;
         case L_GEMM:
           launch(ctx, TIMER_LU_GEMM, k_lu_gemm<T>, dim3(L.units), dim3(256), 0, (const SubDesc*)gdesc, dA, jb, pre,
-                 L.n_jobs);
+                 L.n_jobs, (const int32_t*)drowhi, dflops);
           break;
       }
     }
     FHIP(hipGetLastError());
     {
       dim3 grid(tmax, gn);
-      k_extract_w<T><<<grid, 256, 0, ctx->stream>>>(gdesc, dA, dW);
+      k_extract_w<T><<<grid, 256, 0, ctx->stream>>>(gdesc, dA, dwrow + t0, dwcol + u0, dW);
       FHIP(hipGetLastError());
     }
     free_group();
   }
   std::vector<int32_t> info(ns);
+  unsigned long long flops = 0;
   FHIP(hipMemcpyAsync(info.data(), dinfo, ns * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  FHIP(hipMemcpyAsync(&flops, dflops, sizeof(flops), hipMemcpyDeviceToHost, ctx->stream));
   FHIP(hipStreamSynchronize(ctx->stream));
+  dv.factor_flops = (double)flops;
   for (int j = 0; j < ns; ++j)
     if (info[j] != 0) {
       ctx->err = "factor: zero pivot in subdomain " + std::to_string(j) + " at column " + std::to_string(info[j] - 1);

@@ -650,6 +650,13 @@ __global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n, MULTI
 // a neighbour in B_j (ORAS), 0 for RAS (T_j = [0 I] with u_b = 0). B rows
 // (ORAS), where the local Laplacian has no row:
 // (c + 6/h^2) u_b - (6/h^2) T_b u = 0.
+// The unknowns sit in the subdomain's elimination order (reverse
+// Cuthill-McKee); rcol marks the Sigma_j unknowns with their right-hand
+// column (in order of position) and the B_j unknowns with -1; border row i
+// selects the i-th Sigma~_j node in order of position (tilde_pos). A
+// right-hand column then keeps its single unit entry until that row is chosen
+// as a pivot, and a border row stays zero left of its unit entry, so the
+// blocks the elimination has not reached yet are exactly zero.
 // Column lookup: binary search of the band index in the sorted unknown list.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int local_pos(const int32_t* __restrict__ srt, const int32_t* __restrict__ pos,
@@ -675,6 +682,7 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
                                                   const double* __restrict__ bs,
                                                   const double* __restrict__ ba,
                                                   const int32_t* __restrict__ tilde_pos,
+                                                  const int32_t* __restrict__ rcol,
                                                   const int32_t* __restrict__ ext_pos,
                                                   double diag, double ih2, int oras, T* __restrict__ A) {
   constexpr int P1 = P + 1;
@@ -698,14 +706,15 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
         }
       }
   };
-  if (r < d.m) {
+  const int rc = r < d.n ? rcol[d.u_off + r] : -1;
+  if (rc >= 0) {  // a Sigma_j unknown; its right-hand column is d.n + rc
     const int32_t x = U[d.u_off + r];
     row[r] = (T)((double)row[r] + diag);
     for (int e = 0; e < 6; ++e) {
       const int32_t y = nbr[e * na + x];
       if (y < na) {
         const int q = local_pos(srt, ps, d.n, y);
-        if (q >= d.m) {  // ORAS transmission node: its Robin extension row
+        if (q >= 0 && rcol[d.u_off + q] < 0) {  // ORAS transmission node: its Robin extension row
           const int32_t k = d.u_off + q;
           add_ext(bx[k], ih2 / (1.0 + ba[k] * bs[k]));
           continue;
@@ -714,7 +723,7 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
       }
       add_ext(y, ih2);
     }
-    row[d.n + r] = (T)1;
+    row[d.n + rc] = (T)1;
   } else if (r < d.n) {
     const int32_t k = d.u_off + r;
     row[r] = (T)((double)row[r] + diag);
@@ -729,6 +738,8 @@ __global__ __launch_bounds__(256) void k_assemble(const SubDesc* __restrict__ de
 // (pivots searched in the first n_j rows only), panel width NB.
 // ---------------------------------------------------------------------------
 constexpr int LU_NB = 32;  // panel width
+constexpr int LU_KMAX = 128;  // outer block width (panels caught up left-looking inside it)
+static_assert(LU_KMAX % LU_NB == 0, "whole panels per outer block");
 constexpr int PANEL_THREADS = 1024;
 // columns of a row updated together in the panel (fewer in FP64: registers)
 template <typename T>
@@ -764,17 +775,24 @@ __device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int
 // subdomain (one block each). The panel is moved to a column-major scratch so
 // that every pass is coalesced; the pass that eliminates column jj also finds
 // the pivot of column jj+1. Pivots are searched in the A_j rows only.
+// Only the rows up to the last one holding a nonzero panel entry, among the
+// A_j rows and among the border rows, take part: every row below is zero in
+// the panel, so its multipliers are zero and eliminating it changes nothing.
+// Those bounds (absolute rows) are kept in rowhi[2j], rowhi[2j+1], as maxima
+// over the panels of the current outer block of LU_KMAX columns.
 template <typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                             int k, int32_t* __restrict__ ipiv,
                                                             int32_t* __restrict__ info, T* __restrict__ scratch,
-                                                            const int64_t* __restrict__ scr_off) {
+                                                            const int64_t* __restrict__ scr_off,
+                                                            int32_t* __restrict__ rowhi) {
   constexpr int NW = PANEL_THREADS / 64;
   __shared__ T tile[PANEL_TB * 32][33];
   __shared__ T prow[LU_NB];
   __shared__ double rv[NW];
   __shared__ int ri[NW];
   __shared__ int piv_s;
+  __shared__ int hi_s[2][NW];
   const int j = blockIdx.x;
   const SubDesc d = desc[j];
   if (k >= d.n) return;
@@ -786,7 +804,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
   T* P = scratch + scr_off[j];  // column c at P + c * rows
   const int t = threadIdx.x;
   // gather the panel (PANEL_TB 32-row tiles per round, transposed through LDS;
-  // a round's loads are in flight together)
+  // a round's loads are in flight together), noting the last nonzero rows
+  int hia = 0, hib = np;
   for (int r0 = 0; r0 < rows; r0 += PANEL_TB * 32) {
     {
       const int rl = t >> 5, c = t & 31;
@@ -797,7 +816,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
         g[b] = (r < rows && c < kb) ? a[(int64_t)r * lda + c] : (T)0;
       }
 #pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) tile[b * 32 + rl][c] = g[b];
+      for (int b = 0; b < PANEL_TB; ++b) {
+        tile[b * 32 + rl][c] = g[b];
+        const int r = r0 + b * 32 + rl;
+        if (g[b] != (T)0) {
+          if (r < np) hia = r + 1;
+          else hib = r + 1;
+        }
+      }
     }
     __syncthreads();
     {
@@ -810,10 +836,41 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
     }
     __syncthreads();
   }
+  // active rows: A_j rows [0, ea) and border rows [np, eb), numbered
+  // i = 0 .. na_ - 1 in that order
+  {
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      hia = max(hia, __shfl_xor(hia, o, 64));
+      hib = max(hib, __shfl_xor(hib, o, 64));
+    }
+    if (lane == 0) {
+      hi_s[0][wave] = hia;
+      hi_s[1][wave] = hib;
+    }
+    __syncthreads();
+  }
+  int ea = kb, eb = np;
+  for (int w = 0; w < NW; ++w) {
+    ea = max(ea, hi_s[0][w]);
+    eb = max(eb, hi_s[1][w]);
+  }
+  const int na_ = ea + (eb - np);
+  if (t == 0) {
+    int32_t* lv = rowhi + 2 * j;
+    if (k % LU_KMAX == 0) {
+      lv[0] = k + ea;
+      lv[1] = k + eb;
+    } else {
+      lv[0] = max(lv[0], k + ea);
+      lv[1] = max(lv[1], k + eb);
+    }
+  }
   // pivot of column 0
   double best = -1.0;
   int bi = INT32_MAX;
-  for (int r = t; r < np; r += PANEL_THREADS) {
+  for (int r = t; r < ea; r += PANEL_THREADS) {
     const double v = fabs((double)P[r]);
     if (v > best) { best = v; bi = r; }
   }
@@ -846,9 +903,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
       // is conditional (a column outside jj < c < kb is written back
       // unchanged; the scratch has LU_NB columns), so the loads of both rows
       // are in flight together with no wait between them
-      for (int r = jj + 1 + t; r < rows; r += 2 * PANEL_THREADS) {
-        const bool two = r + PANEL_THREADS < rows;
-        const int r2 = two ? r + PANEL_THREADS : r;
+      for (int i = jj + 1 + t; i < na_; i += 2 * PANEL_THREADS) {
+        const bool two = i + PANEL_THREADS < na_;
+        const int r = i < ea ? i : np + (i - ea);
+        const int i2 = i + PANEL_THREADS;
+        const int r2 = two ? (i2 < ea ? i2 : np + (i2 - ea)) : r;
         T* pa = P + r;
         T* pb = P + r2;
         const T la = pj[r] / pv, lb = pj[r2] / pv;
@@ -870,11 +929,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
             pa[(int64_t)c * rows] = na;
             pb[(int64_t)c * rows] = nb;
             if (live && c == jj + 1) {
-              if (r < np) {
+              if (i < ea) {
                 const double av = fabs((double)na);
                 if (av > best) { best = av; bi = r; }
               }
-              if (two && r2 < np) {
+              if (two && i2 < ea) {
                 const double av = fabs((double)nb);
                 if (av > best) { best = av; bi = r2; }
               }
@@ -884,7 +943,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
       }
     } else if (jj + 1 < kb) {  // singular column: nothing eliminated, search the next one
       const T* pn = P + (int64_t)(jj + 1) * rows;
-      for (int r = jj + 1 + t; r < np; r += PANEL_THREADS) {
+      for (int r = jj + 1 + t; r < ea; r += PANEL_THREADS) {
         const double av = fabs((double)pn[r]);
         if (av > best) { best = av; bi = r; }
       }
@@ -892,29 +951,32 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
     if (jj + 1 < kb) piv = block_argmax(best, bi, rv, ri, &piv_s);
     else __syncthreads();
   }
-  // write the factored panel back (same rounds)
-  for (int r0 = 0; r0 < rows; r0 += PANEL_TB * 32) {
-    {
-      const int c = t >> 5, rl = t & 31;
-      T g[PANEL_TB];
+  // write the active rows of the factored panel back (same rounds)
+  for (int seg = 0; seg < 2; ++seg) {
+    const int s0 = seg ? np : 0, s1 = seg ? eb : ea;
+    for (int r0 = s0; r0 < s1; r0 += PANEL_TB * 32) {
+      {
+        const int c = t >> 5, rl = t & 31;
+        T g[PANEL_TB];
 #pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) {
-        const int r = r0 + b * 32 + rl;
-        g[b] = (r < rows && c < kb) ? P[(int64_t)c * rows + r] : (T)0;
+        for (int b = 0; b < PANEL_TB; ++b) {
+          const int r = r0 + b * 32 + rl;
+          g[b] = (r < s1 && c < kb) ? P[(int64_t)c * rows + r] : (T)0;
+        }
+#pragma unroll
+        for (int b = 0; b < PANEL_TB; ++b) tile[b * 32 + rl][c] = g[b];
       }
+      __syncthreads();
+      {
+        const int rl = t >> 5, c = t & 31;
 #pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) tile[b * 32 + rl][c] = g[b];
-    }
-    __syncthreads();
-    {
-      const int rl = t >> 5, c = t & 31;
-#pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) {
-        const int r = r0 + b * 32 + rl;
-        if (r < rows && c < kb) a[(int64_t)r * lda + c] = tile[b * 32 + rl][c];
+        for (int b = 0; b < PANEL_TB; ++b) {
+          const int r = r0 + b * 32 + rl;
+          if (r < s1 && c < kb) a[(int64_t)r * lda + c] = tile[b * 32 + rl][c];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -935,8 +997,6 @@ struct LuJob {
   int32_t j, kstart, kdim, r_lo, c_lo, c_hi;
 };
 
-constexpr int LU_KMAX = 128;  // outer block width (panels caught up left-looking inside it)
-static_assert(LU_KMAX % LU_NB == 0, "whole panels per outer block");
 constexpr int TRSM_COLS = 64;
 
 // Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
@@ -1013,9 +1073,9 @@ constexpr int GEMM_TILE_R = 128;  // rows of the trailing-update tile (columns: 
 // TM x TN tile of C; four waves in a 2 x 2 arrangement, each (TM/2) x (TN/2)
 // as (TM/32) x (TN/32) blocks of 16 x 16. Every C element accumulates the same
 // MFMA steps in the same order whatever the tile shape, so all shapes give
-// the same bits.
+// the same bits. Returns whether this thread wrote a nonzero.
 template <typename T, int TM = GEMM_TILE, int TN = GEMM_TILE>
-__device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int cols, int kdim,
+__device__ __forceinline__ bool tile_update(T* a, int64_t lda, int rows, int cols, int kdim,
                                             int r0, int c0, const T* __restrict__ lsrc, int64_t lld,
                                             const T* usrc, int64_t uld) {
   // C[r0.., c0..] -= Lsrc[r0.., 0..kdim) * Usrc[0..kdim, c0..]   (C = a, rows x cols in view).
@@ -1029,6 +1089,7 @@ __device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int col
   const int wr = (wave >> 1) * (TM / 2), wc = (wave & 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
   AT acc[NBR][NBC];
+  bool nz = false;
 #pragma unroll
   for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
@@ -1094,16 +1155,30 @@ __device__ __forceinline__ void tile_update(T* a, int64_t lda, int rows, int col
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
-        if (rr < rows && cc < cols) a[(int64_t)rr * lda + cc] = acc[bi][bj][i];
+        if (rr < rows && cc < cols) {
+          a[(int64_t)rr * lda + cc] = acc[bi][bj][i];
+          nz |= acc[bi][bj][i] != (T)0;
+        }
       }
+  return nz;
+}
+
+// Whether rows [r, r + rows_n) meet the rows whose multipliers in the current
+// outer block may be nonzero: A_j rows below hi[0] and border rows below hi[1]
+// (hi[1] == n: none).
+__device__ __forceinline__ bool rows_live(const int32_t* hi, int n, int r, int rows_n) {
+  return r < hi[0] || (r + rows_n > n && r < hi[1] && hi[1] > n);
 }
 
 // One tile of a job's update per block (jobs located through the prefix of
 // their tile counts); TM x TN the tile shape the host planned the job with.
+// Tiles whose rows carry only zero multipliers (rowhi, as left by the
+// panels) leave C as it is and return at once.
 template <typename T, int TM = GEMM_TILE, int TN = GEMM_TILE>
 __global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                  const LuJob* __restrict__ jobs, const int32_t* __restrict__ prefix,
-                                                 int n_jobs) {
+                                                 int n_jobs, const int32_t* __restrict__ rowhi,
+                                                 unsigned long long* __restrict__ flops) {
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
@@ -1111,6 +1186,8 @@ __global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ des
   const int ntc = (ncol + TN - 1) / TN;
   const int tile = blockIdx.x - prefix[q];
   const int tr = tile / ntc, tc = tile - (tile / ntc) * ntc;
+  if (!rows_live(rowhi + 2 * jb.j, d.n, jb.r_lo + tr * TM, TM)) return;
+  if (threadIdx.x == 0) atomicAdd(flops, 2ull * TM * TN * (unsigned long long)jb.kdim);
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
   // view with origin (r_lo, c_lo)
@@ -1127,8 +1204,9 @@ template <typename T>
 __global__ __launch_bounds__(TRSM_COLS) void k_lu_linv(const SubDesc* __restrict__ desc, const T* __restrict__ A,
                                                        const LuJob* __restrict__ jobs,
                                                        const int32_t* __restrict__ prefix, int n_jobs,
-                                                       T* __restrict__ lm) {
+                                                       T* __restrict__ lm, int32_t* __restrict__ n_tiles) {
   __shared__ T X[LU_KMAX][TRSM_COLS];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_tiles = 0;  // the trailing-tile list of this outer block starts empty
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
@@ -1147,19 +1225,72 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_linv(const SubDesc* __restrict
     out[(int64_t)i * LU_KMAX + col] = (i < kd && col < kd && i > col) ? -X[i][t] : (T)0;
 }
 
+// U12 = L11^{-1} U12 for one GEMM_TILE-column tile. When the tile is not all
+// zero, the tiles of the trailing update below it whose rows may carry nonzero
+// multipliers (rowhi) are appended to `list` as (job, tile) pairs: tile =
+// tr * ntc + tc for TR-row tiles. The trailing update of a tile with a zero
+// U12 or zero multipliers changes nothing, so only listed tiles are computed.
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_gemm_u(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                    const LuJob* __restrict__ jobs,
                                                    const int32_t* __restrict__ prefix, int n_jobs,
-                                                   const T* __restrict__ lm) {
+                                                   const T* __restrict__ lm, const int32_t* __restrict__ rowhi,
+                                                   int TR, int2* __restrict__ list, int32_t* __restrict__ n_tiles,
+                                                   unsigned long long* __restrict__ flops) {
+  __shared__ int base_s;
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
   const int ncol = jb.c_hi - jb.c_lo;
   const int tc = blockIdx.x - prefix[q];
   T* u = A + d.a_off + (int64_t)jb.kstart * d.lda + jb.c_lo;  // the U12 block, rows [kstart, kstart + kdim)
-  tile_update<T, LU_KMAX, GEMM_TILE>(u, d.lda, jb.kdim, ncol, jb.kdim, 0, tc * GEMM_TILE,
-                                     lm + (int64_t)jb.j * LU_KMAX * LU_KMAX, LU_KMAX, u, d.lda);
+  const bool nz = tile_update<T, LU_KMAX, GEMM_TILE>(u, d.lda, jb.kdim, ncol, jb.kdim, 0, tc * GEMM_TILE,
+                                                     lm + (int64_t)jb.j * LU_KMAX * LU_KMAX, LU_KMAX, u, d.lda);
+  if (!__syncthreads_or(nz)) return;
+  // trailing rows [K1, rows), K1 = c_lo, in TR-row tiles: A_j rows below
+  // rowhi[0] and border rows below rowhi[1]
+  const int K1 = jb.c_lo;
+  const int ntr = (d.rows - K1 + TR - 1) / TR;
+  const int ntc = (ncol + GEMM_TILE - 1) / GEMM_TILE;
+  const int hia = rowhi[2 * jb.j], hib = rowhi[2 * jb.j + 1];
+  const int a_hi = hia > K1 ? min(ntr, (hia - K1 + TR - 1) / TR) : 0;
+  const int b_lo = max(a_hi, (d.n - K1) / TR);
+  const int b_hi = hib > d.n ? min(ntr, (hib - K1 + TR - 1) / TR) : 0;
+  const int cnt = a_hi + max(0, b_hi - b_lo);
+  if (threadIdx.x == 0) {
+    base_s = atomicAdd(n_tiles, cnt);
+    // matrix-core work of the listed tiles (whole tiles, as computed)
+    atomicAdd(flops, (unsigned long long)cnt * 2ull * TR * GEMM_TILE * (unsigned long long)jb.kdim);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int tr = e < a_hi ? e : b_lo + (e - a_hi);
+    list[base_s + e] = make_int2(q, tr * ntc + tc);
+  }
+}
+
+// Trailing update A22 -= L21 U12 of an outer block over the listed tiles
+// (k_lu_gemm_u), a persistent grid taking every gridDim.x-th entry; `jobs`
+// are the U12 jobs (rows of the trailing update start at K1 = c_lo).
+template <typename T, int TM, int TN>
+__global__ __launch_bounds__(256) void k_lu_gemm_list(const SubDesc* __restrict__ desc, T* __restrict__ A,
+                                                      const LuJob* __restrict__ jobs,
+                                                      const int2* __restrict__ list,
+                                                      const int32_t* __restrict__ n_tiles) {
+  const int nt = *n_tiles;
+  for (int e = blockIdx.x; e < nt; e += gridDim.x) {
+    const int2 it = list[e];
+    const LuJob jb = jobs[it.x];
+    const SubDesc d = desc[jb.j];
+    const int K1 = jb.c_lo;
+    const int ncol = jb.c_hi - K1;
+    const int ntc = (ncol + TN - 1) / TN;
+    const int tr = it.y / ntc, tc = it.y - (it.y / ntc) * ntc;
+    T* a = A + d.a_off;
+    const int64_t lda = d.lda;
+    tile_update<T, TM, TN>(a + (int64_t)K1 * lda + K1, lda, d.rows - K1, ncol, jb.kdim, tr * TM, tc * TN,
+                           a + (int64_t)K1 * lda + jb.kstart, lda, a + (int64_t)jb.kstart * lda + K1, lda);
+  }
 }
 
 // Self-test of the matrix-core tile: C (64x64) -= A (64 x kdim) B (kdim x 64), row-major.
@@ -1170,16 +1301,21 @@ __global__ __launch_bounds__(256) void k_tile_selftest(T* C, const T* Am, const 
 
 // W_j = -(lower-right block) of the eliminated augmented matrix, written in the
 // tiled layout of the apply kernels (w_tile_index).
+// Row q of W_j (Sigma~_j in band order) is border row wrow[q]; column c
+// (Sigma_j in band order) is right-hand column wcol[c].
 template <typename T>
 __global__ __launch_bounds__(256) void k_extract_w(const SubDesc* __restrict__ desc, const T* __restrict__ A,
+                                                   const int32_t* __restrict__ wrow, const int32_t* __restrict__ wcol,
                                                    T* __restrict__ W) {
   const int j = blockIdx.y;
   const SubDesc d = desc[j];
   const int q = blockIdx.x;
   if (q >= d.t) return;
-  const T* src = A + d.a_off + (int64_t)(d.n + q) * d.lda + d.n;
+  const T* src = A + d.a_off + (int64_t)(d.n + wrow[d.t_off + q]) * d.lda + d.n;
+  const int32_t* wc = wcol + d.u_off;
   T* dst = W + d.w_off;
-  for (int c = threadIdx.x; c < d.ldw; c += 256) dst[w_tile_index(d.ldw, W_CW<T>, q, c)] = c < d.m ? -src[c] : (T)0;
+  for (int c = threadIdx.x; c < d.ldw; c += 256)
+    dst[w_tile_index(d.ldw, W_CW<T>, q, c)] = c < d.m ? -src[wc[c]] : (T)0;
 }
 
 // ---------------------------------------------------------------------------

@@ -201,6 +201,116 @@ void sort_unique(std::vector<int32_t>& v) {
   v.erase(std::unique(v.begin(), v.end()), v.end());
 }
 
+
+// Reverse Cuthill-McKee order of the local unknowns [Sigma_j ; B_j] (B_j only
+// for ORAS) on the symmetrised pattern of A_j (eq. localOP): a Sigma row holds
+// its own node and the interpolation stencils of its neighbours' extension rows
+// (a transmission neighbour contributes the stencil of its Robin row, at x*(b),
+// eq. robfo; for RAS an active neighbour outside Sigma_j contributes nothing); a
+// B row holds its node and the stencil at x*(b). Breadth-first from the
+// lowest-degree node of each component, neighbours visited in increasing
+// degree (ties: lower local index), the whole order reversed. Stencil nodes
+// whose interpolation weight is exactly zero (a closest point on a grid
+// plane) are not entries. `lpos` is an all -1 scratch of N_T entries and is
+// left that way.
+std::vector<int32_t> rcm_order(const Band& b, const Sub& sd, bool oras, std::vector<int32_t>& lpos) {
+  const int64_t na = b.n_act;
+  const int P1 = b.p + 1, P2 = P1 * P1;
+  const int m = (int)sd.sigma.size();
+  const int n = m + (oras ? (int)sd.bnd.size() : 0);
+  for (int q = 0; q < m; ++q) lpos[sd.sigma[q]] = q;
+  if (oras)
+    for (int q = 0; q < n - m; ++q) lpos[sd.bnd[q]] = m + q;
+  // pattern rows without the diagonal, duplicates removed
+  std::vector<int32_t> stamp(n, -1), off(n + 1, 0), col;
+  col.reserve((size_t)n * 96);
+  auto add_ext = [&](int row, int32_t node) {
+    const double* w = &b.wts[(size_t)node * 3 * P1];  // x, y, z weights
+    for (int a = 0; a < P2; ++a) {
+      const int32_t first = b.lines[(size_t)node * P2 + a];
+      const double wab = w[a / P1] * w[P1 + a % P1];
+      for (int c = 0; c < P1; ++c) {
+        const int32_t q = lpos[first + c];
+        if (wab * w[2 * P1 + c] != 0.0 && q >= 0 && q != row && stamp[q] != row) {
+          stamp[q] = row;
+          col.push_back(q);
+        }
+      }
+    }
+  };
+  for (int r = 0; r < n; ++r) {
+    if (r < m) {
+      const int32_t x = sd.sigma[r];
+      for (int e = 0; e < 6; ++e) {
+        const int32_t y = b.nbr[(size_t)x * 6 + e];
+        if (y < na) {
+          const int32_t q = lpos[y];
+          if (q >= m) add_ext(r, sd.xstar[q - m]);
+          else if (q >= 0) add_ext(r, y);
+        } else {
+          add_ext(r, y);
+        }
+      }
+    } else {
+      add_ext(r, sd.xstar[r - m]);
+    }
+    off[r + 1] = (int32_t)col.size();
+  }
+  for (int q = 0; q < m; ++q) lpos[sd.sigma[q]] = -1;
+  if (oras)
+    for (int q = 0; q < n - m; ++q) lpos[sd.bnd[q]] = -1;
+  // symmetrise: rows of the transpose, then the union of both per node
+  std::vector<int32_t> toff(n + 1, 0), tcol(col.size());
+  for (int32_t q : col) toff[q + 1]++;
+  for (int r = 0; r < n; ++r) toff[r + 1] += toff[r];
+  {
+    std::vector<int32_t> fill(toff.begin(), toff.end() - 1);
+    for (int r = 0; r < n; ++r)
+      for (int32_t e = off[r]; e < off[r + 1]; ++e) tcol[fill[col[e]]++] = r;
+  }
+  std::vector<int32_t> soff(n + 1, 0), scol;
+  scol.reserve(col.size() * 2);
+  std::fill(stamp.begin(), stamp.end(), -1);
+  for (int r = 0; r < n; ++r) {
+    for (int32_t e = off[r]; e < off[r + 1]; ++e) {
+      stamp[col[e]] = r;
+      scol.push_back(col[e]);
+    }
+    for (int32_t e = toff[r]; e < toff[r + 1]; ++e)
+      if (stamp[tcol[e]] != r) {
+        stamp[tcol[e]] = r;
+        scol.push_back(tcol[e]);
+      }
+    soff[r + 1] = (int32_t)scol.size();
+  }
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<uint8_t> seen(n, 0);
+  auto deg = [&](int32_t q) { return soff[q + 1] - soff[q]; };
+  auto by_degree = [&](int32_t x, int32_t y) { return deg(x) != deg(y) ? deg(x) < deg(y) : x < y; };
+  std::vector<int32_t> fresh;
+  while ((int)order.size() < n) {
+    int32_t start = -1;
+    for (int q = 0; q < n; ++q)
+      if (!seen[q] && (start < 0 || deg(q) < deg(start))) start = q;
+    seen[start] = 1;
+    order.push_back(start);
+    for (size_t h = order.size() - 1; h < order.size(); ++h) {
+      const int32_t v = order[h];
+      fresh.clear();
+      for (int32_t e = soff[v]; e < soff[v + 1]; ++e)
+        if (!seen[scol[e]]) {
+          seen[scol[e]] = 1;
+          fresh.push_back(scol[e]);
+        }
+      std::sort(fresh.begin(), fresh.end(), by_degree);
+      order.insert(order.end(), fresh.begin(), fresh.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
 }  // namespace
 
 int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const double* weights,
@@ -294,7 +404,7 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
   const int P1 = b.p + 1, NS = P1 * P1 * P1;
   std::vector<int> fail(n_sub, 0);
 
-  auto build_one = [&](int j, std::vector<uint8_t>& mark) {
+  auto build_one = [&](int j, std::vector<uint8_t>& mark, std::vector<int32_t>& lpos) {
     Sub& sd = nd.subs[j];
     sd.tilde = members[j];
     // Breadth-first overlap layers inside the active set.
@@ -339,7 +449,10 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
     sd.bnd = bnd;
     (void)NS;
     for (int32_t q : sd.sigma) mark[q] = 0;
-    if (kind != CPM_ORAS) return;
+    if (kind != CPM_ORAS) {
+      sd.order = rcm_order(b, sd, false, lpos);
+      return;
+    }
     const size_t nbd = sd.bnd.size();
     sd.xstar.resize(nbd);
     sd.s.resize(nbd);
@@ -369,6 +482,7 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
         if (near_cross[(size_t)(((int64_t)x[0] * b.n[1] + x[1]) * b.n[2] + x[2])]) sd.alpha[q] = alpha_cross;
       }
     }
+    sd.order = rcm_order(b, sd, true, lpos);
   };
 
   const int nth = std::max(1, std::min<int>(n_sub, (int)std::thread::hardware_concurrency()));
@@ -376,7 +490,8 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
   for (int t = 0; t < nth; ++t)
     pool.emplace_back([&, t]() {
       std::vector<uint8_t> mark(na, 0);
-      for (int j = t; j < n_sub; j += nth) build_one(j, mark);
+      std::vector<int32_t> lpos(b.total(), -1);
+      for (int j = t; j < n_sub; j += nth) build_one(j, mark, lpos);
     });
   for (auto& th : pool) th.join();
   for (int j = 0; j < n_sub; ++j)

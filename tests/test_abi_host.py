@@ -156,10 +156,111 @@ def test_host_setup_matches_oracle(case, kind):
         o = dec.subs[j]
         for k in ("tilde", "sigma", "final", "ghost", "bnd"):
             np.testing.assert_array_equal(s[k], getattr(o, k), err_msg=f"{k} of part {j}")
+        n_unk = len(o.sigma) + (len(o.bnd) if kind == "ORAS" else 0)
+        np.testing.assert_array_equal(np.sort(s["order"]), np.arange(n_unk))
         if kind == "ORAS":
             np.testing.assert_array_equal(s["xstar"], o.xstar)
             np.testing.assert_array_equal(s["alpha"], o.alpha)
             np.testing.assert_allclose(s["s"], o.s, rtol=0, atol=1e-15)
+
+
+def _cm_violations(S, order):
+    """Checks that reversing `order` gives a Cuthill-McKee order of the
+    symmetric pattern S (no diagonal): breadth-first, each component started
+    at a remaining node of least degree (lowest index on ties), the nodes
+    found from one parent in increasing degree (then index). Returns a list
+    of violations (empty if none)."""
+    n = S.shape[0]
+    deg = np.diff(S.indptr)
+    cm = np.asarray(order[::-1])
+    pos = np.empty(n, np.int64)
+    pos[cm] = np.arange(n)
+    bad = []
+    last_parent = -1
+    prev = None  # (parent, degree, index) of the previous node
+    for i, v in enumerate(cm):
+        nb = S.indices[S.indptr[v]:S.indptr[v + 1]]
+        earlier = pos[nb][pos[nb] < i]
+        if earlier.size == 0:  # a component start
+            rest = cm[i:]
+            best = rest[np.lexsort((rest, deg[rest]))[0]]
+            if best != v:
+                bad.append(("start", i, int(v), int(best)))
+            last_parent = -1
+            prev = None
+            continue
+        par = int(earlier.min())
+        if par < last_parent:
+            bad.append(("parent order", i))
+        if prev is not None and prev[0] == par and (prev[1], prev[2]) > (deg[v], v):
+            bad.append(("degree order", i))
+        last_parent = par
+        prev = (par, deg[v], v)
+    return bad
+
+
+def _envelope(S, order):
+    inv = np.empty(len(order), np.int64)
+    inv[order] = np.arange(len(order))
+    C = S.tocoo()
+    first = np.arange(len(order))
+    np.minimum.at(first, inv[C.row], inv[C.col])
+    return int((np.arange(len(order)) - first).sum())
+
+
+@pytest.mark.parametrize("case", [0, 2, 4])
+@pytest.mark.parametrize("kind", ["RAS", "ORAS"])
+def test_elimination_order_is_rcm_of_the_oracle_pattern(case, kind):
+    """The factorisation's elimination order (Section 5, LU of the local
+    problems) is reverse Cuthill-McKee on the pattern of the oracle's A_j
+    (eq. localOP, with the Robin rows of eq. robfo for ORAS), and its
+    envelope is no wider than that of band order (about half for ORAS)."""
+    import scipy.sparse as sps
+    surf, h, p, method, n, no = CASES[case]
+    b = oracle.build_band(surf, h, p, [-2.0] * 3, [2.0] * 3)
+    ctx = P.Context(-1)
+    ctx.build_band(surf, h, p)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_RCB, n, None, no, getattr(P, kind), 3.0, 30.0)
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, n), no, kind, alpha=3.0, alpha_cross=30.0, only={0, n - 1})
+    for j in (0, n - 1):
+        A = sps.csr_matrix(schwarz.local_matrix(b, dec, j, 1.0))
+        S = ((abs(A) + abs(A).T) != 0).astype(np.int8).tolil()
+        S.setdiag(0)
+        S = S.tocsr()
+        S.eliminate_zeros()
+        S.sort_indices()
+        order = ctx.subdomain(j)["order"]
+        assert np.array_equal(np.sort(order), np.arange(S.shape[0]))
+        assert _cm_violations(S, order) == []
+        # ORAS puts the B_j unknowns after Sigma_j in band order, far from the
+        # Sigma_j rows that reference them: there the order halves the envelope
+        bound = 0.7 if kind == "ORAS" else 1.0
+        assert _envelope(S, order) <= bound * _envelope(S, np.arange(S.shape[0]))
+    ctx.close()
+
+
+def test_cm_check_catches_a_wrong_order():
+    """The Cuthill-McKee check fails for band order and for a swapped pair."""
+    import scipy.sparse as sps
+    surf, h, p, method, n, no = CASES[0]
+    b = oracle.build_band(surf, h, p, [-2.0] * 3, [2.0] * 3)
+    ctx = P.Context(-1)
+    ctx.build_band(surf, h, p)
+    ctx.build_operator(1.0)
+    ctx.partition(P.PART_RCB, n, None, no, P.ORAS, 3.0, 30.0)
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, n), no, "ORAS", alpha=3.0, alpha_cross=30.0, only={0})
+    A = sps.csr_matrix(schwarz.local_matrix(b, dec, 0, 1.0))
+    S = ((abs(A) + abs(A).T) != 0).astype(np.int8).tolil()
+    S.setdiag(0)
+    S = S.tocsr()
+    S.eliminate_zeros()
+    S.sort_indices()
+    order = ctx.subdomain(0)["order"].copy()
+    assert _cm_violations(S, np.arange(S.shape[0])) != []
+    order[[5, 400]] = order[[400, 5]]
+    assert _cm_violations(S, order) != []
+    ctx.close()
 
 
 def test_state_machine_and_argument_errors():

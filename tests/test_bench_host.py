@@ -59,8 +59,9 @@ def test_algorithmic_counts_from_their_definitions():
     want = int(8 * (t * m).sum() + 12 * m.sum() + 12 * t.sum())
     got, _ = bench.precond_bytes(ctx, 6, 8)
     assert got == want
-    # blocked LU update flops: left-looking catch-up of every 32-wide panel inside a
-    # 128-wide outer block, then one trailing update per outer block
+    # blocked LU update flops with no block skipped: left-looking catch-up of
+    # every 32-wide panel inside a 128-wide outer block, then one trailing
+    # update per outer block
     flops = 0
     for nj, tj, mj in zip(n, t, m):
         rows, cols = nj + tj, nj + mj

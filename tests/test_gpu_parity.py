@@ -384,11 +384,27 @@ def test_factor_tiles_are_identical_and_autotune_caches_the_faster(prec):
     b, dec, ctx = _setup("torus", 3, "rcb", 16, 3, "ORAS", 4.47, 20.0)
     js = (0, 7, 15)
     got = {}
+    # the bordered LU's update work with no tile skipped (outer blocks of 128,
+    # left-looking 32-wide panels inside)
+    dense = 0
+    for j in range(16):
+        s = ctx.subdomain(j)
+        m, t = len(s["sigma"]), len(s["tilde"])
+        nj = m + len(s["bnd"])
+        rows_j, cols_j = nj + t, nj + m
+        for k0 in range(0, nj, 128):
+            k1 = min(k0 + 128, nj)
+            for k in range(k0 + 32, k1, 32):
+                dense += 2 * (k - k0) * (rows_j - k) * min(32, nj - k)
+            dense += 2 * (k1 - k0) * (rows_j - k1) * (cols_j - k1)
     for rows in (64, 128):
         ctx.set_factor_tile(rows)
         ctx.factor(prec)
         assert ctx.factor_tile() == rows
         got[rows] = [ctx.factor_export(j) for j in js]
+        fl = ctx.factor_flops()
+        say("  tile", rows, "matrix-core flops", fl, "of dense", dense)
+        assert 0 < fl < 0.7 * dense  # exactly-zero tiles are skipped
     for a, c in zip(got[64], got[128]):
         np.testing.assert_array_equal(a, c)
     ctx.set_factor_tile(0)
