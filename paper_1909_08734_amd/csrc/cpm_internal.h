@@ -40,6 +40,11 @@ struct Sub {
   // Cuthill-McKee on the pattern of A_j, so that the LU factors stay inside a
   // narrow profile and most of the bordered update is exactly zero.
   std::vector<int32_t> order;
+  // reach[c]: one past the last position whose row of A_j has its first
+  // nonzero in a column <= c (in elimination order). Rows below reach[c] are
+  // zero in columns <= c and stay so under partial pivoting, so the
+  // elimination of column c only involves positions below reach[c].
+  std::vector<int32_t> reach;
 };
 
 struct Decomp {
@@ -72,6 +77,7 @@ struct SubDesc {
   int32_t cols;      // n + m
   int32_t blk_off;   // first apply block of this subdomain
   int32_t rpb;       // rows of W_j per apply block
+  int32_t pb_off;    // first entry of this subdomain in the panel row-bound table
 };
 
 // A group of extension rows for the LDS-staged operator apply: rows whose

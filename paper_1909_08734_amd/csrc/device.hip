@@ -541,6 +541,10 @@ struct FactorPlan {
   // (position of the unit entry); W maps: wrow (W row -> border row), wcol
   // (W column -> right-hand column, indexed like U).
   std::vector<int32_t> U, fU, rcol, wrow, wcol, usrt, upos, bx, tilde_pos, tilde_idx, blk_sub;
+  // per subdomain and panel (columns [k, k + LU_NB)): one past the last A_j
+  // row and one past the last border row that can hold a nonzero in the
+  // panel (absolute rows), from the structure of A_j
+  std::vector<int32_t> pbound;
   std::vector<double> bs, ba;
   int64_t a_elems = 0, w_elems = 0, u_total = 0;
   int max_m = 0, max_n = 0, max_rows = 0, n_blocks = 0;
@@ -654,6 +658,17 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) 
       wrow[brow[i].second] = (int32_t)i;
     }
     P.wrow.insert(P.wrow.end(), wrow.begin(), wrow.end());
+    // panel row bounds: A_j rows below reach[c], border rows whose unit entry
+    // lies in a column <= c, c the panel's last column
+    d.pb_off = (int32_t)(P.pbound.size() / 2);
+    const bool have = (int)s.reach.size() == d.n && (int)s.order.size() == d.n;
+    int32_t nb_rows = 0;
+    for (int k = 0; k < d.n; k += LU_NB) {
+      const int c = std::min(k + LU_NB, d.n) - 1;
+      while (nb_rows < d.t && brow[nb_rows].first <= c) ++nb_rows;
+      P.pbound.push_back(have ? std::max(s.reach[c], (int32_t)(c + 1)) : d.n);
+      P.pbound.push_back(d.n + (have ? nb_rows : d.t));
+    }
     u_off += d.n;
     t_off += d.t;
     P.max_m = std::max(P.max_m, (int)d.ldw);
@@ -667,10 +682,10 @@ void make_plan(const cpm_ctx* ctx, FactorPlan& P, int block_slots, int rpb_max) 
   P.n_blocks = blk;
 }
 
-// Factor workspace of one subdomain (bordered matrix, column-major panel scratch,
-// I - L11^{-1} of an outer block), elements.
+// Factor workspace of one subdomain (bordered matrix, panel scratch in 64-row
+// tiles, I - L11^{-1} of an outer block), elements.
 inline int64_t factor_ws_elems(const SubDesc& d) {
-  return (int64_t)d.rows * d.lda + (int64_t)LU_NB * d.rows + (int64_t)LU_KMAX * LU_KMAX;
+  return (int64_t)d.rows * d.lda + (int64_t)LU_NB * round_up(d.rows, 64) + (int64_t)LU_KMAX * LU_KMAX;
 }
 
 // Consecutive groups of subdomains whose factor workspaces fit in `limit` bytes
@@ -704,15 +719,15 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   SubDesc *ddesc = nullptr, *gdesc = nullptr;
   int32_t *dU = nullptr, *dsrt = nullptr, *dpos = nullptr, *dbx = nullptr, *dtpos = nullptr, *dtidx = nullptr,
           *dblk = nullptr, *dipiv = nullptr, *dinfo = nullptr, *dpre = nullptr, *dfu = nullptr, *drc = nullptr,
-          *dwrow = nullptr, *dwcol = nullptr, *drowhi = nullptr, *dntile = nullptr;
+          *dwrow = nullptr, *dwcol = nullptr, *drowhi = nullptr, *dntile = nullptr, *dpb = nullptr;
   int2* dlist = nullptr;
   unsigned long long* dflops = nullptr;
   double *dbs = nullptr, *dba = nullptr;
-  int64_t* dscr_off = nullptr;
   LuJob* jobs_buf = nullptr;
+  int64_t* dscr_off = nullptr;
+  T* dscr = nullptr;
   T* dA = nullptr;
   T* dW = nullptr;
-  T* dscr = nullptr;
   T* dlm = nullptr;  // per subdomain of a group: I - L11^{-1} of the current outer block
   int rc = CPM_OK;
   auto free_group = [&]() {
@@ -723,7 +738,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   auto cleanup = [&]() {
     free_group();
     dfree(dsrt); dfree(dpos); dfree(dbx); dfree(dtpos); dfree(dipiv); dfree(dinfo);
-    dfree(dbs); dfree(dba); dfree(dfu); dfree(drc); dfree(dwrow); dfree(dwcol); dfree(dntile); dfree(dflops);
+    dfree(dbs); dfree(dba); dfree(dfu); dfree(drc); dfree(dwrow); dfree(dwcol); dfree(dntile); dfree(dflops); dfree(dpb);
   };
   auto bail = [&](int code) {
     cleanup();
@@ -758,6 +773,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   FCHK(upload(ctx, &drc, P.rcol));
   FCHK(upload(ctx, &dwrow, P.wrow));
   FCHK(upload(ctx, &dwcol, P.wcol));
+  FCHK(upload(ctx, &dpb, P.pbound));
   FHIP(hipMalloc((void**)&dntile, sizeof(int32_t)));
   FHIP(hipMalloc((void**)&dflops, sizeof(unsigned long long)));
   FHIP(hipMemsetAsync(dflops, 0, sizeof(unsigned long long), ctx->stream));
@@ -781,19 +797,20 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
       FHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_gemm_list<T, GEMM_TILE_R, GEMM_TILE>, 256, 0));
     else
       FHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_gemm_list<T, GEMM_TILE, GEMM_TILE>, 256, 0));
-    trail_grid = std::max(1, n_cu * std::max(1, per_cu));
+    trail_grid = std::max(8, n_cu * std::max(1, per_cu) / 8 * 8);  // a multiple of 8 (one share per XCD)
   }
   for (const auto& gr : groups) {
     const int g0 = gr.first, gn = gr.second - gr.first;
     std::vector<SubDesc> gd(P.desc.begin() + g0, P.desc.begin() + gr.second);
     const int64_t a0 = gd[0].a_off;
-    const int32_t u0 = gd[0].u_off, t0 = gd[0].t_off;
+    const int32_t u0 = gd[0].u_off, t0 = gd[0].t_off, pb0 = gd[0].pb_off;
     int64_t a_elems = 0;
     int max_n = 0, max_rows = 0, tmax = 0;
     for (SubDesc& d : gd) {
       d.a_off -= a0;
       d.u_off -= u0;
       d.t_off -= t0;
+      d.pb_off -= pb0;
       a_elems = std::max(a_elems, d.a_off + (int64_t)d.rows * d.lda);
       max_n = std::max(max_n, (int)d.n);
       max_rows = std::max(max_rows, (int)d.rows);
@@ -834,7 +851,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
     // earlier L columns. After the outer block, the trailing matrix gets the
     // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
     // and one MFMA update with K = LU_KMAX.
-    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4, L_LINV = 5, L_GEMM_U = 6 };
+    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4, L_LINV = 5, L_GEMM_U = 6, L_BORDER = 7 };
     struct Launch {
       int kind, k, job_off, n_jobs, units;
     };
@@ -871,6 +888,16 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
           add(L_GEMM, k, gm);
         }
         lplan.push_back(Launch{L_PANEL, k, 0, 0, gn});
+        {  // border rows that may be nonzero in this panel: 256 per block
+          int nbl = 0;
+          for (int j = 0; j < gn; ++j) {
+            const SubDesc& d = gd[j];
+            if (k >= d.n) continue;
+            const int n_b = P.pbound[2 * ((size_t)d.pb_off + pb0 + k / LU_NB) + 1] - d.n;
+            nbl = std::max(nbl, cdiv(n_b, 256));
+          }
+          if (nbl > 0) lplan.push_back(Launch{L_BORDER, k, 0, 0, nbl});
+        }
         if (p > 0) {
           std::vector<std::pair<LuJob, int>> sw;
           for (int j = 0; j < gn; ++j) {
@@ -901,12 +928,12 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
     }
     FCHK(upload(ctx, &jobs_buf, jobs));
     FCHK(upload(ctx, &dpre, prefix));
-    // column-major panel scratch, LU_NB x rows_j per subdomain
+    // panel scratch, LU_NB x rows_j (rounded to 64-row tiles) per subdomain
     std::vector<int64_t> scr_off(gn);
     int64_t scr_total = 0;
     for (int j = 0; j < gn; ++j) {
       scr_off[j] = scr_total;
-      scr_total += (int64_t)LU_NB * gd[j].rows;
+      scr_total += (int64_t)LU_NB * round_up(gd[j].rows, 64);
     }
     FCHK(upload(ctx, &dscr_off, scr_off));
     FHIP(hipMalloc((void**)&dscr, scr_total * sizeof(T)));
@@ -922,7 +949,11 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
       const int32_t* pre = dpre + L.job_off;
       switch (L.kind) {
         case L_PANEL:
-          k_lu_panel<T><<<gn, PANEL_THREADS, 0, ctx->stream>>>(gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off, drowhi);
+          k_lu_panel<T><<<gn, PANEL_THREADS, 0, ctx->stream>>>(gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off,
+                                                               dpb + 2 * (int64_t)pb0, drowhi);
+          break;
+        case L_BORDER:
+          k_lu_border<T><<<dim3(L.units, gn), 256, 0, ctx->stream>>>(gdesc, dA, L.k, dpb + 2 * (int64_t)pb0);
           break;
         case L_SWAP_TRSM:
         case L_SWAP:
@@ -1852,8 +1883,8 @@ int dev_stationary(cpm_ctx* ctx, const double* f, double* u, double tol, int max
 
 // Device bytes of a factorisation before it is made: resident afterwards
 // (operator arrays, W arena and its index lists, Krylov space of `restart`)
-// and the peak while factoring (plus the bordered matrices, panel scratch and
-// assembly lists). Mirrors the allocations of dev_upload_operator, make_plan,
+// and the peak while factoring (plus the bordered matrices, the assembly and
+// elimination-order lists, the panel row bounds and the trailing-tile list). Mirrors the allocations of dev_upload_operator, make_plan,
 // run_factor and ensure_krylov; the apply-block table is bounded by one entry
 // per W row.
 void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, size_t* peak) {
@@ -1880,16 +1911,23 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
     u_total += d.n;
     t_total += d.t;
   }
-  int64_t ws = 0;  // largest group workspace
+  size_t ws = 0;  // largest group workspace: matrices, row bounds, tile list (64-row tiles at most)
   for (const auto& g : factor_groups(desc, esz, ctx->dev.ws_limit)) {
-    int64_t e = 0;
-    for (int j = g.first; j < g.second; ++j) e += factor_ws_elems(desc[j]);
+    size_t e = 0;
+    for (int j = g.first; j < g.second; ++j) {
+      const SubDesc& d = desc[j];
+      e += (size_t)factor_ws_elems(d) * esz + 2 * 4 +
+           (size_t)((d.rows + GEMM_TILE - 1) / GEMM_TILE) * ((d.n + d.m + GEMM_TILE - 1) / GEMM_TILE) * 8;
+    }
     ws = std::max(ws, e);
   }
   const size_t lists = (size_t)D.n_sub * sizeof(SubDesc) + (size_t)(u_total + 2 * t_total) * 4;
   const size_t res = op + (size_t)w_elems * esz + lists + (restart > 0 ? krylov_bytes(b.n_act, restart) : 0);
-  const size_t work = (size_t)ws * esz + (size_t)u_total * (5 * 4 + 2 * 8) + (size_t)t_total * 4 +
-                      (size_t)D.n_sub * (4 + 8);
+  // per unknown: factor-order node, sorted lookup (2), B data index, pivot,
+  // right-hand column, W column map, B data (2 doubles); per Sigma~ node: unit
+  // entry position, W row map; per panel: two row bounds
+  const size_t work = ws + (size_t)u_total * (7 * 4 + 2 * 8) + (size_t)t_total * 8 +
+                      (size_t)(u_total / LU_NB + D.n_sub) * 8 + (size_t)D.n_sub * (4 + 8) + 16;
   if (resident) *resident = res;
   if (peak) *peak = res + work;
 }

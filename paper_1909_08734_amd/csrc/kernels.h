@@ -741,12 +741,7 @@ constexpr int LU_NB = 32;  // panel width
 constexpr int LU_KMAX = 128;  // outer block width (panels caught up left-looking inside it)
 static_assert(LU_KMAX % LU_NB == 0, "whole panels per outer block");
 constexpr int PANEL_THREADS = 1024;
-// columns of a row updated together in the panel (fewer in FP64: registers)
-template <typename T>
-constexpr int PANEL_GROUP = sizeof(T) == 8 ? 4 : 8;
 constexpr int PANEL_TB = 4;     // 32-row tiles per round of the panel's gather and write-back
-static_assert(LU_NB % PANEL_GROUP<double> == 0 && LU_NB % PANEL_GROUP<float> == 0,
-              "panel groups cover the scratch columns exactly");
 
 // (value, row) pair reduction over the block: largest |value|, lowest row on ties.
 __device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri, int* out) {
@@ -771,20 +766,32 @@ __device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int
   return *out;
 }
 
-// Unblocked LU with partial pivoting of the panel A[k:rows, k:k+kb] of every
-// subdomain (one block each). The panel is moved to a column-major scratch so
-// that every pass is coalesced; the pass that eliminates column jj also finds
-// the pivot of column jj+1. Pivots are searched in the A_j rows only.
-// Only the rows up to the last one holding a nonzero panel entry, among the
-// A_j rows and among the border rows, take part: every row below is zero in
-// the panel, so its multipliers are zero and eliminating it changes nothing.
-// Those bounds (absolute rows) are kept in rowhi[2j], rowhi[2j+1], as maxima
-// over the panels of the current outer block of LU_KMAX columns.
+// Panel scratch layout: 64-row tiles, column-major inside a tile, so that a
+// wave's 64 consecutive rows read a column as 64 consecutive values and one
+// row's columns sit at fixed offsets (64 apart) from a single address.
+__device__ __forceinline__ int64_t panel_index(int r, int c) {
+  return (int64_t)(r >> 6) * (LU_NB * 64) + c * 64 + (r & 63);
+}
+
+// Unblocked LU with partial pivoting of the A_j rows of the panel
+// A[k:n, k:k+kb] of every subdomain (one block each); the border rows, which
+// never pivot, are eliminated afterwards by k_lu_border. Rows that are zero
+// throughout the panel have zero multipliers, so eliminating them changes
+// nothing: the panel reads only the rows the structure of A_j allows to be
+// nonzero (pbound[0]), finds among them the last row that is nonzero, and
+// eliminates only up to it. Those rows are moved to the scratch (transposed
+// through LDS, PANEL_TB 32-row tiles per round with their loads in flight
+// together), where a pass gives each thread one row with all its values
+// loaded at once; the pass that eliminates column jj also finds the pivot of
+// column jj+1. The last possibly nonzero rows (absolute; border rows: from
+// pbound[1]) are kept in rowhi[2j], rowhi[2j+1], as maxima over the panels of
+// the current outer block of LU_KMAX columns.
 template <typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                             int k, int32_t* __restrict__ ipiv,
                                                             int32_t* __restrict__ info, T* __restrict__ scratch,
                                                             const int64_t* __restrict__ scr_off,
+                                                            const int32_t* __restrict__ pbound,
                                                             int32_t* __restrict__ rowhi) {
   constexpr int NW = PANEL_THREADS / 64;
   __shared__ T tile[PANEL_TB * 32][33];
@@ -792,159 +799,123 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
   __shared__ double rv[NW];
   __shared__ int ri[NW];
   __shared__ int piv_s;
-  __shared__ int hi_s[2][NW];
+  __shared__ int hi_s[1][NW];
   const int j = blockIdx.x;
   const SubDesc d = desc[j];
   if (k >= d.n) return;
   const int kb = min(LU_NB, d.n - k);
-  const int rows = d.rows - k;  // panel height
   const int np = d.n - k;       // pivot-eligible rows
   T* a = A + d.a_off + (int64_t)k * d.lda + k;
   const int64_t lda = d.lda;
-  T* P = scratch + scr_off[j];  // column c at P + c * rows
+  T* P = scratch + scr_off[j];
   const int t = threadIdx.x;
-  // gather the panel (PANEL_TB 32-row tiles per round, transposed through LDS;
-  // a round's loads are in flight together), noting the last nonzero rows
-  int hia = 0, hib = np;
-  for (int r0 = 0; r0 < rows; r0 += PANEL_TB * 32) {
-    {
-      const int rl = t >> 5, c = t & 31;
-      T g[PANEL_TB];
+  const int32_t* pb = pbound + 2 * ((int64_t)d.pb_off + k / LU_NB);
+  const int ga = min(pb[0] - k, np);  // A_j rows [0, ga) may be nonzero
+  // gather those rows, noting the last nonzero row and the pivot of column 0
+  int hia = 0;
+  double best = -1.0;
+  int bi = INT32_MAX;
+  {
+    const int s1 = ga;
+    for (int r0 = 0; r0 < s1; r0 += PANEL_TB * 32) {
+      {
+        const int rl = t >> 5, c = t & 31;
+        T g[PANEL_TB];
 #pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) {
-        const int r = r0 + b * 32 + rl;
-        g[b] = (r < rows && c < kb) ? a[(int64_t)r * lda + c] : (T)0;
-      }
+        for (int b = 0; b < PANEL_TB; ++b) {
+          const int r = r0 + b * 32 + rl;
+          g[b] = (r < s1 && c < kb) ? a[(int64_t)r * lda + c] : (T)0;
+        }
 #pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) {
-        tile[b * 32 + rl][c] = g[b];
-        const int r = r0 + b * 32 + rl;
-        if (g[b] != (T)0) {
-          if (r < np) hia = r + 1;
-          else hib = r + 1;
+        for (int b = 0; b < PANEL_TB; ++b) {
+          tile[b * 32 + rl][c] = g[b];
+          const int r = r0 + b * 32 + rl;
+          if (g[b] != (T)0) {
+            hia = r + 1;
+            const double av = fabs((double)g[b]);
+            if (c == 0 && av > best) { best = av; bi = r; }
+          }
         }
       }
-    }
-    __syncthreads();
-    {
-      const int c = t >> 5, rl = t & 31;
+      __syncthreads();
+      {
+        const int c = t >> 5, rl = t & 31;
 #pragma unroll
-      for (int b = 0; b < PANEL_TB; ++b) {
-        const int r = r0 + b * 32 + rl;
-        if (r < rows && c < kb) P[(int64_t)c * rows + r] = tile[b * 32 + rl][c];
+        for (int b = 0; b < PANEL_TB; ++b) {
+          const int r = r0 + b * 32 + rl;
+          if (r < s1) P[panel_index(r, c)] = tile[b * 32 + rl][c];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // active rows: A_j rows [0, ea) and border rows [np, eb), numbered
-  // i = 0 .. na_ - 1 in that order
   {
     const int lane = t & 63, wave = t >> 6;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      hia = max(hia, __shfl_xor(hia, o, 64));
-      hib = max(hib, __shfl_xor(hib, o, 64));
-    }
-    if (lane == 0) {
-      hi_s[0][wave] = hia;
-      hi_s[1][wave] = hib;
-    }
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) hia = max(hia, __shfl_xor(hia, o, 64));
+    if (lane == 0) hi_s[0][wave] = hia;
   }
-  int ea = kb, eb = np;
-  for (int w = 0; w < NW; ++w) {
-    ea = max(ea, hi_s[0][w]);
-    eb = max(eb, hi_s[1][w]);
-  }
-  const int na_ = ea + (eb - np);
+  int piv = block_argmax(best, bi, rv, ri, &piv_s);  // its barriers also publish hi_s
+  // active rows [0, ea)
+  int ea = kb;
+  for (int w = 0; w < NW; ++w) ea = max(ea, hi_s[0][w]);
   if (t == 0) {
     int32_t* lv = rowhi + 2 * j;
     if (k % LU_KMAX == 0) {
       lv[0] = k + ea;
-      lv[1] = k + eb;
+      lv[1] = pb[1];
     } else {
       lv[0] = max(lv[0], k + ea);
-      lv[1] = max(lv[1], k + eb);
+      lv[1] = max(lv[1], pb[1]);
     }
   }
-  // pivot of column 0
-  double best = -1.0;
-  int bi = INT32_MAX;
-  for (int r = t; r < ea; r += PANEL_THREADS) {
-    const double v = fabs((double)P[r]);
-    if (v > best) { best = v; bi = r; }
-  }
-  int piv = block_argmax(best, bi, rv, ri, &piv_s);
   for (int jj = 0; jj < kb; ++jj) {
-    T* pj = P + (int64_t)jj * rows;
     if (t == 0) {
       ipiv[d.u_off + k + jj] = k + (piv < 0 ? jj : piv);
       if (piv < 0 && info[j] == 0) info[j] = k + jj + 1;
     }
     // interchange rows jj and piv (thread c: column c) and keep the new row jj
     if (t < kb) {
-      T* pc = P + (int64_t)t * rows;
-      const T rj = pc[jj];
-      const T rp = piv >= 0 ? pc[piv] : rj;
+      T* pj = P + panel_index(jj, t);
+      const T rj = *pj;
       if (piv >= 0 && piv != jj) {
-        pc[jj] = rp;
-        pc[piv] = rj;
+        T* pp = P + panel_index(piv, t);
+        const T rp = *pp;
+        *pj = rp;
+        *pp = rj;
+        prow[t] = rp;
+      } else {
+        prow[t] = rj;
       }
-      prow[t] = rp;
     }
     __syncthreads();
     const T pv = prow[jj];
     best = -1.0;
     bi = INT32_MAX;
     if (piv >= 0) {
-      // two rows per pass (r and r + PANEL_THREADS; a missing second row
-      // repeats the first, which rewrites the same values), PANEL_GROUP columns
-      // at a time: all loads of a group are issued before its stores, and none
-      // is conditional (a column outside jj < c < kb is written back
-      // unchanged; the scratch has LU_NB columns), so the loads of both rows
-      // are in flight together with no wait between them
-      for (int i = jj + 1 + t; i < na_; i += 2 * PANEL_THREADS) {
-        const bool two = i + PANEL_THREADS < na_;
-        const int r = i < ea ? i : np + (i - ea);
-        const int i2 = i + PANEL_THREADS;
-        const int r2 = two ? (i2 < ea ? i2 : np + (i2 - ea)) : r;
-        T* pa = P + r;
-        T* pb = P + r2;
-        const T la = pj[r] / pv, lb = pj[r2] / pv;
-        pj[r] = la;
-        pj[r2] = lb;
-        for (int c0 = (jj + 1) / PANEL_GROUP<T> * PANEL_GROUP<T>; c0 < kb; c0 += PANEL_GROUP<T>) {
-          T va[PANEL_GROUP<T>], vb[PANEL_GROUP<T>];
+      for (int r = jj + 1 + t; r < ea; r += PANEL_THREADS) {
+        // prow is read from LDS inside the loop (a compiler-only barrier keeps
+        // its values from being held in registers next to the row's)
+        asm volatile("" ::: "memory");
+        T* row = P + panel_index(r, 0);  // column c at row[64 c]
+        T v[LU_NB];
 #pragma unroll
-          for (int q = 0; q < PANEL_GROUP<T>; ++q) {
-            va[q] = pa[(int64_t)(c0 + q) * rows];
-            vb[q] = pb[(int64_t)(c0 + q) * rows];
-          }
+        for (int c = 0; c < LU_NB; ++c) v[c] = row[64 * c];  // columns past kb are zeros, not used
+        const T vj = row[64 * jj];
+        const T vn = jj + 1 < kb ? row[64 * (jj + 1)] : (T)0;
+        const T l = vj / pv;
 #pragma unroll
-          for (int q = 0; q < PANEL_GROUP<T>; ++q) {
-            const int c = c0 + q;
-            const bool live = c > jj && c < kb;
-            const T na = live ? va[q] - la * prow[c] : va[q];
-            const T nb = live ? vb[q] - lb * prow[c] : vb[q];
-            pa[(int64_t)c * rows] = na;
-            pb[(int64_t)c * rows] = nb;
-            if (live && c == jj + 1) {
-              if (i < ea) {
-                const double av = fabs((double)na);
-                if (av > best) { best = av; bi = r; }
-              }
-              if (two && i2 < ea) {
-                const double av = fabs((double)nb);
-                if (av > best) { best = av; bi = r2; }
-              }
-            }
-          }
+        for (int c = 0; c < LU_NB; ++c)
+          if (c > jj && c < kb) row[64 * c] = v[c] - l * prow[c];
+        row[64 * jj] = l;
+        if (jj + 1 < kb) {
+          const double av = fabs((double)(vn - l * prow[jj + 1]));
+          if (av > best) { best = av; bi = r; }
         }
       }
     } else if (jj + 1 < kb) {  // singular column: nothing eliminated, search the next one
-      const T* pn = P + (int64_t)(jj + 1) * rows;
       for (int r = jj + 1 + t; r < ea; r += PANEL_THREADS) {
-        const double av = fabs((double)pn[r]);
+        const double av = fabs((double)P[panel_index(r, jj + 1)]);
         if (av > best) { best = av; bi = r; }
       }
     }
@@ -952,16 +923,16 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
     else __syncthreads();
   }
   // write the active rows of the factored panel back (same rounds)
-  for (int seg = 0; seg < 2; ++seg) {
-    const int s0 = seg ? np : 0, s1 = seg ? eb : ea;
-    for (int r0 = s0; r0 < s1; r0 += PANEL_TB * 32) {
+  {
+    const int s1 = ea;
+    for (int r0 = 0; r0 < s1; r0 += PANEL_TB * 32) {
       {
         const int c = t >> 5, rl = t & 31;
         T g[PANEL_TB];
 #pragma unroll
         for (int b = 0; b < PANEL_TB; ++b) {
           const int r = r0 + b * 32 + rl;
-          g[b] = (r < s1 && c < kb) ? P[(int64_t)c * rows + r] : (T)0;
+          g[b] = (r < s1 && c < kb) ? P[panel_index(r, c)] : (T)0;
         }
 #pragma unroll
         for (int b = 0; b < PANEL_TB; ++b) tile[b * 32 + rl][c] = g[b];
@@ -978,6 +949,51 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
       __syncthreads();
     }
   }
+}
+
+// The border rows of a panel (Section 5: the rows R~_j appended to A_j) take
+// no part in pivoting, so their multipliers need not wait for the panel's
+// column-by-column pivot searches: after the panel, each border row that may
+// be nonzero in it (rows [n, pbound[1])) is eliminated against the panel's
+// final upper triangle U11 by the same steps the panel applies to its own
+// rows (column jj: l = a_jj / u_jj, then a_c -= l u_jc for c > jj; nothing
+// where u_jj = 0, a column the panel found singular). One row per thread,
+// U11 in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_border(const SubDesc* __restrict__ desc, T* __restrict__ A, int k,
+                                                   const int32_t* __restrict__ pbound) {
+  __shared__ T U[LU_NB][LU_NB + 1];
+  const int j = blockIdx.y;
+  const SubDesc d = desc[j];
+  if (k >= d.n) return;
+  const int kb = min(LU_NB, d.n - k);
+  const int n_b = pbound[2 * ((int64_t)d.pb_off + k / LU_NB) + 1] - d.n;
+  if ((int)blockIdx.x * 256 >= n_b) return;  // the whole block
+  const int64_t lda = d.lda;
+  const T* u = A + d.a_off + (int64_t)k * lda + k;
+  for (int e = threadIdx.x; e < LU_NB * LU_NB; e += 256) {
+    const int r = e / LU_NB, c = e - (e / LU_NB) * LU_NB;
+    U[r][c] = (r < kb && c < kb) ? u[(int64_t)r * lda + c] : (T)0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_b) return;
+  T* row = A + d.a_off + (int64_t)(d.n + i) * lda + k;
+  T v[LU_NB];
+#pragma unroll
+  for (int c = 0; c < LU_NB; ++c) v[c] = c < kb ? row[c] : (T)0;
+#pragma unroll
+  for (int jj = 0; jj < LU_NB; ++jj) {
+    if (jj < kb && U[jj][jj] != (T)0) {
+      const T l = v[jj] / U[jj][jj];
+      v[jj] = l;
+#pragma unroll
+      for (int c = jj + 1; c < LU_NB; ++c) v[c] = v[c] - l * U[jj][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < LU_NB; ++c)
+    if (c < kb) row[c] = v[c];
 }
 
 __device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int n_jobs, int blk) {
@@ -1270,15 +1286,22 @@ __global__ __launch_bounds__(256) void k_lu_gemm_u(const SubDesc* __restrict__ d
 }
 
 // Trailing update A22 -= L21 U12 of an outer block over the listed tiles
-// (k_lu_gemm_u), a persistent grid taking every gridDim.x-th entry; `jobs`
-// are the U12 jobs (rows of the trailing update start at K1 = c_lo).
+// (k_lu_gemm_u), a persistent grid (gridDim.x a multiple of 8); `jobs` are
+// the U12 jobs (rows of the trailing update start at K1 = c_lo). Workgroups go
+// to the 8 XCDs in turn, so XCD x = blockIdx.x % 8 takes the x-th contiguous
+// eighth of the list: the tiles of a U12 column tile (listed together) and of
+// neighbouring column tiles share their L2.
 template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void k_lu_gemm_list(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                       const LuJob* __restrict__ jobs,
                                                       const int2* __restrict__ list,
                                                       const int32_t* __restrict__ n_tiles) {
   const int nt = *n_tiles;
-  for (int e = blockIdx.x; e < nt; e += gridDim.x) {
+  const int x = blockIdx.x & 7, per = gridDim.x >> 3;
+  const int q = (nt + 7) >> 3;  // entries per XCD
+  for (int v = blockIdx.x >> 3; v < q; v += per) {
+    const int e = x * q + v;
+    if (e >= nt) break;
     const int2 it = list[e];
     const LuJob jb = jobs[it.x];
     const SubDesc d = desc[jb.j];

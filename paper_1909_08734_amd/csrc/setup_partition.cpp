@@ -213,7 +213,8 @@ void sort_unique(std::vector<int32_t>& v) {
 // whose interpolation weight is exactly zero (a closest point on a grid
 // plane) are not entries. `lpos` is an all -1 scratch of N_T entries and is
 // left that way.
-std::vector<int32_t> rcm_order(const Band& b, const Sub& sd, bool oras, std::vector<int32_t>& lpos) {
+std::vector<int32_t> rcm_order(const Band& b, const Sub& sd, bool oras, std::vector<int32_t>& lpos,
+                               std::vector<int32_t>& reach) {
   const int64_t na = b.n_act;
   const int P1 = b.p + 1, P2 = P1 * P1;
   const int m = (int)sd.sigma.size();
@@ -308,6 +309,18 @@ std::vector<int32_t> rcm_order(const Band& b, const Sub& sd, bool oras, std::vec
     }
   }
   std::reverse(order.begin(), order.end());
+  // first nonzero column of each row in elimination order (diagonal included),
+  // then reach[c] = 1 + the last position p with first[p] <= c
+  std::vector<int32_t> at(n), first(n);
+  for (int p = 0; p < n; ++p) at[order[p]] = p;
+  for (int r = 0; r < n; ++r) {
+    int32_t f = at[r];
+    for (int32_t e = off[r]; e < off[r + 1]; ++e) f = std::min(f, at[col[e]]);
+    first[at[r]] = f;
+  }
+  reach.assign(n, 0);
+  for (int p = 0; p < n; ++p) reach[first[p]] = std::max(reach[first[p]], p + 1);
+  for (int c = 1; c < n; ++c) reach[c] = std::max(reach[c], reach[c - 1]);
   return order;
 }
 
@@ -450,7 +463,7 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
     (void)NS;
     for (int32_t q : sd.sigma) mark[q] = 0;
     if (kind != CPM_ORAS) {
-      sd.order = rcm_order(b, sd, false, lpos);
+      sd.order = rcm_order(b, sd, false, lpos, sd.reach);
       return;
     }
     const size_t nbd = sd.bnd.size();
@@ -482,7 +495,7 @@ int build_decomposition(const Band& b, Decomp& d, int method, int n_sub, const d
         if (near_cross[(size_t)(((int64_t)x[0] * b.n[1] + x[1]) * b.n[2] + x[2])]) sd.alpha[q] = alpha_cross;
       }
     }
-    sd.order = rcm_order(b, sd, true, lpos);
+    sd.order = rcm_order(b, sd, true, lpos, sd.reach);
   };
 
   const int nth = std::max(1, std::min<int>(n_sub, (int)std::thread::hardware_concurrency()));
