@@ -1049,13 +1049,17 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
     }
   }
   if (!trsm || !live) return;
+  // forward substitution by rows: X_i -= l_iq X_q for q = 0, 1, ..., i-1 in
+  // turn (the order of the column-by-column form), reading row i of L11 (contiguous)
   const T* l = a + (int64_t)jb.kstart * lda + jb.kstart;
   for (int i = 0; i < jb.kdim; ++i) X[i][t] = a[(jb.kstart + i) * lda + c];
-  for (int qq = 0; qq < jb.kdim; ++qq) {
-    const T xq = X[qq][t];
-    for (int i = qq + 1; i < jb.kdim; ++i) X[i][t] -= l[(int64_t)i * lda + qq] * xq;
+  for (int i = 1; i < jb.kdim; ++i) {
+    const T* li = l + (int64_t)i * lda;
+    T x = X[i][t];
+    for (int q = 0; q < i; ++q) x -= li[q] * X[q][t];
+    X[i][t] = x;
+    a[(jb.kstart + i) * lda + c] = x;
   }
-  for (int i = 1; i < jb.kdim; ++i) a[(jb.kstart + i) * lda + c] = X[i][t];
 }
 
 // Trailing update on matrix cores: C -= Lsrc * Usrc for one 64x64 tile of C,
@@ -1230,11 +1234,14 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_linv(const SubDesc* __restrict
   const int col = (blockIdx.x - prefix[q]) * TRSM_COLS + t;  // < LU_KMAX
   const int kd = jb.kdim;
   const int64_t lda = d.lda;
+  // forward substitution by rows on the identity column (the column-by-column
+  // order of subtractions, reading row i of L11 contiguously)
   const T* l = A + d.a_off + (int64_t)jb.kstart * lda + jb.kstart;
-  for (int i = 0; i < kd; ++i) X[i][t] = i == col ? (T)1 : (T)0;
-  for (int qq = 0; qq < kd; ++qq) {
-    const T xq = X[qq][t];
-    for (int i = qq + 1; i < kd; ++i) X[i][t] -= l[(int64_t)i * lda + qq] * xq;
+  for (int i = 0; i < kd; ++i) {
+    const T* li = l + (int64_t)i * lda;
+    T x = i == col ? (T)1 : (T)0;
+    for (int q = 0; q < i; ++q) x -= li[q] * X[q][t];
+    X[i][t] = x;
   }
   T* out = lm + (int64_t)jb.j * LU_KMAX * LU_KMAX;
   for (int i = 0; i < LU_KMAX; ++i)
