@@ -149,6 +149,28 @@ def lu_flops(ctx, n_sub, kind_oras, nb=32, kmax=128):
     return tot
 
 
+def stream_read_reference(nbytes, reps=10):
+    """Read rate of a library reduction (torch.sum over float64) of the same
+    number of bytes, on the current stream, outside every timed region: how
+    fast a general-purpose kernel streams this much from HBM, for comparison."""
+    import torch
+    x = torch.ones(max(1, nbytes // 8), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        x.sum()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x
+    torch.cuda.empty_cache()
+    return {"kernel": "torch.sum, float64", "bytes": (nbytes // 8) * 8, "ms": ms,
+            "GBs": (nbytes // 8) * 8 / (ms * 1e-3) / 1e9}
+
+
 def pmc_traffic(kind, source_hash, tiling):
     """HBM bytes per apply launch of the given tiling from the committed
     counter summary, if it was taken on the current kernel source."""
@@ -641,6 +663,7 @@ def main():
             "algorithmic_bytes_per_launch": r64["precond_bytes"],
             "avg_launch_ms": r64["precond_ms_avg"],
             "kernel_source_hash": src,
+            "library_read_reference": stream_read_reference(r64["precond_bytes"]),
         },
     }
     if args.serve_requests > 0 and default:

@@ -1299,7 +1299,7 @@ __global__ __launch_bounds__(256) void k_lu_gemm_u(const SubDesc* __restrict__ d
 // eighth of the list: the tiles of a U12 column tile (listed together) and of
 // neighbouring column tiles share their L2.
 template <typename T, int TM, int TN>
-__global__ __launch_bounds__(256) void k_lu_gemm_list(const SubDesc* __restrict__ desc, T* __restrict__ A,
+__global__ __launch_bounds__(256, 2) void k_lu_gemm_list(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                       const LuJob* __restrict__ jobs,
                                                       const int2* __restrict__ list,
                                                       const int32_t* __restrict__ n_tiles) {
