@@ -140,6 +140,43 @@ def test_preconditioner_apply(case, prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("alpha,prec,tol", [(1e-3, P.FP64, 1e-8), (3.0, P.FP64, 1e-8), (3.0, P.FP32, 2e-2)],
+                         ids=["alpha1e-3-fp64", "alpha3-fp64", "alpha3-fp32"])
+def test_heavily_pivoting_local_solves_match_oracle(alpha, prec, tol):
+    """Torus h = 0.05 in 8 RCB parts (about 8,500 local unknowns), ORAS: the LU
+    interchanges hundreds of rows per subdomain (a weak Robin weight alpha
+    makes the transmission rows compete with the diagonal), so the rows the
+    elimination skips as structurally zero must stay zero under partial
+    pivoting (Section 5, LU of the local problems). W_j and M^{-1} v on two
+    sampled subdomains against the oracle's dense inverses; cond(A_j) is
+    4.5e4 (alpha = 3) and 1.1e6 (alpha = 1e-3), hence the bars."""
+    import scipy.linalg as sl
+    say("heavy pivoting", alpha, prec)
+    b, dec_all, ctx = _setup("torus", 3, "rcb", 8, 2, "ORAS", alpha, 0.0)
+    sample = [0, 5]
+    dec = schwarz.decompose(b, oracle.rcb_partition(b, 8), 2, "ORAS", alpha=alpha, only=set(sample))
+    ctx.factor(prec)
+    for j in sample:
+        sd = dec.subs[j]
+        Aj = schwarz.local_matrix(b, dec, j, 1.0)
+        Aj = Aj.toarray() if hasattr(Aj, "toarray") else np.asarray(Aj)
+        order = ctx.subdomain(j)["order"]
+        _, piv = sl.lu_factor(Aj[np.ix_(order, order)], check_finite=False)
+        assert np.count_nonzero(piv != np.arange(len(order))) > 200  # the case pivots heavily
+        inv = np.linalg.inv(Aj)
+        pos = np.searchsorted(sd.sigma, sd.tilde)
+        W_ref = inv[np.ix_(pos, np.arange(len(sd.sigma)))]
+        assert rel(ctx.factor_export(j), W_ref) < tol
+    M = schwarz.Preconditioner(b, dec, 1.0, subs=sample)
+    v = np.random.default_rng(5).standard_normal(b.n_act)
+    z_ref = M.apply(v)
+    z = torch.zeros(b.n_act, dtype=torch.float64, device="cuda")
+    ctx.apply_precond(dev(v), z)
+    rows = np.concatenate([dec.subs[j].tilde for j in sample])
+    assert rel(z.cpu().numpy()[rows], z_ref[rows]) < tol
+    ctx.close()
+
+
 @pytest.fixture(scope="module")
 def direct_cfg1():
     surf, h = SURF["sphere"]
