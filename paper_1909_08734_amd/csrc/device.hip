@@ -788,6 +788,11 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   // rebased descriptors (a_off, u_off, t_off relative to the group; w_off
   // global, into the resident W arena).
   const std::vector<std::pair<int, int>> groups = factor_groups(P.desc, sizeof(T), dv.ws_limit);
+  // the panel's dynamic LDS (register + LDS rows of its fast form) exceeds the default limit
+  FHIP(hipFuncSetAttribute((const void*)k_lu_panel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)panel_lds_bytes<T>()));
+  FHIP(hipFuncSetAttribute((const void*)k_lu_panel_fast<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)panel_lds_bytes<T>()));
   // resident blocks of the listed trailing update
   int trail_grid = 0;
   {
@@ -851,7 +856,8 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
     // earlier L columns. After the outer block, the trailing matrix gets the
     // block's interchanges, the unit-lower solve with the LU_KMAX x LU_KMAX L11
     // and one MFMA update with K = LU_KMAX.
-    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4, L_LINV = 5, L_GEMM_U = 6, L_BORDER = 7 };
+    enum { L_PANEL = 0, L_SWAP_TRSM = 1, L_SWAP = 2, L_GEMM = 3, L_GEMM_TRAIL = 4, L_LINV = 5, L_GEMM_U = 6, L_BORDER = 7,
+           L_PANEL_FAST = 8 };
     struct Launch {
       int kind, k, job_off, n_jobs, units;
     };
@@ -887,7 +893,16 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
           add(L_SWAP_TRSM, k, ts);
           add(L_GEMM, k, gm);
         }
-        lplan.push_back(Launch{L_PANEL, k, 0, 0, gn});
+        {  // the register + LDS form when every panel of the launch is full width and fits
+          bool fast = true;
+          for (int j = 0; j < gn && fast; ++j) {
+            const SubDesc& d = gd[j];
+            if (k >= d.n) continue;
+            const int ga = std::min(P.pbound[2 * ((size_t)d.pb_off + pb0 + k / LU_NB)] - k, d.n - k);
+            fast = d.n - k >= LU_NB && ga <= PANEL_FAST_THREADS + PanelLds<T>::ROWS;
+          }
+          lplan.push_back(Launch{fast ? L_PANEL_FAST : L_PANEL, k, 0, 0, gn});
+        }
         {  // border rows that may be nonzero in this panel: 256 per block
           int nbl = 0;
           for (int j = 0; j < gn; ++j) {
@@ -949,8 +964,12 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
       const int32_t* pre = dpre + L.job_off;
       switch (L.kind) {
         case L_PANEL:
-          k_lu_panel<T><<<gn, PANEL_THREADS, 0, ctx->stream>>>(gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off,
-                                                               dpb + 2 * (int64_t)pb0, drowhi);
+          k_lu_panel<T><<<gn, PANEL_THREADS, panel_lds_bytes<T>(), ctx->stream>>>(
+              gdesc, dA, L.k, gipiv, ginfo, dscr, dscr_off, dpb + 2 * (int64_t)pb0, drowhi);
+          break;
+        case L_PANEL_FAST:
+          k_lu_panel_fast<T><<<gn, PANEL_FAST_THREADS, panel_lds_bytes<T>(), ctx->stream>>>(
+              gdesc, dA, L.k, gipiv, ginfo, dpb + 2 * (int64_t)pb0, drowhi);
           break;
         case L_BORDER:
           k_lu_border<T><<<dim3(L.units, gn), 256, 0, ctx->stream>>>(gdesc, dA, L.k, dpb + 2 * (int64_t)pb0);

@@ -744,8 +744,9 @@ constexpr int PANEL_THREADS = 1024;
 constexpr int PANEL_TB = 4;     // 32-row tiles per round of the panel's gather and write-back
 
 // (value, row) pair reduction over the block: largest |value|, lowest row on ties.
+template <int NT = PANEL_THREADS>
 __device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri, int* out) {
-  constexpr int NW = PANEL_THREADS / 64;
+  constexpr int NW = NT / 64;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const double ob = __shfl_xor(best, o, 64);
@@ -773,6 +774,268 @@ __device__ __forceinline__ int64_t panel_index(int r, int c) {
   return (int64_t)(r >> 6) * (LU_NB * 64) + c * 64 + (r & 63);
 }
 
+// Fast form of the panel (k_lu_panel below) when its rows fit on the CU: rows
+// [0, PANEL_FAST_THREADS) in registers (thread t holds row t's LU_NB values),
+// rows [PANEL_FAST_THREADS, PANEL_FAST_THREADS + PanelLds<T>::ROWS) in LDS
+// (column c of LDS row q at lds[c * LRP + q]), so the column steps touch no
+// global memory.
+// Same arithmetic in the same order as the scratch form: column jj: the
+// interchange of rows jj and piv, l = a_jj / u_jj, a_c -= l u_c for c > jj,
+// the pivot of column jj+1 from the updated values.
+template <typename T>
+struct PanelLds;
+template <>
+struct PanelLds<double> {
+  static constexpr int LRP = 577;  // odd: a column's rows fall in consecutive banks
+  static constexpr int ROWS = LRP - 1;
+};
+template <>
+struct PanelLds<float> {
+  static constexpr int LRP = 1153;
+  static constexpr int ROWS = LRP - 1;
+};
+// dynamic LDS of the panel kernel: the LDS rows of the fast form, or the
+// staging tiles of either form (they are used one after the other)
+template <typename T>
+constexpr size_t panel_lds_bytes() {
+  return (size_t)PanelLds<T>::LRP * LU_NB * sizeof(T);
+}
+constexpr int PANEL_STAGE = 128;  // rows per staging round of the register rows
+
+constexpr int PANEL_FAST_THREADS = 512;  // register rows per block of the fast form
+
+// Used only when every panel of the launch is LU_NB wide and its rows that
+// may be nonzero fit (host-checked from pbound).
+template <typename T>
+__global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubDesc* __restrict__ desc,
+                                                                      T* __restrict__ A, int k,
+                                                                      int32_t* __restrict__ ipiv,
+                                                                      int32_t* __restrict__ info,
+                                                                      const int32_t* __restrict__ pbound,
+                                                                      int32_t* __restrict__ rowhi) {
+  constexpr int NT = PANEL_FAST_THREADS;
+  constexpr int NW = NT / 64;
+  constexpr int LRP = PanelLds<T>::LRP;
+  extern __shared__ __align__(16) unsigned char panel_dyn[];  // panel_lds_bytes<T>()
+  __shared__ T xa[LU_NB];
+  __shared__ T xb[LU_NB];
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
+  __shared__ int piv_s_;
+  __shared__ int hi_s[NW];
+  int* piv_s = &piv_s_;
+  const int j = blockIdx.x;
+  const SubDesc d = desc[j];
+  if (k >= d.n) return;
+  const int kb = LU_NB;
+  T* a = A + d.a_off + (int64_t)k * d.lda + k;
+  const int64_t lda = d.lda;
+  const int32_t* pb = pbound + 2 * ((int64_t)d.pb_off + k / LU_NB);
+  const int ga = min(pb[0] - k, d.n - k);
+  const int32_t pb1 = pb[1];
+  const int t = threadIdx.x;
+  T* stage = reinterpret_cast<T*>(panel_dyn);  // PANEL_STAGE x 33
+  T* L = reinterpret_cast<T*>(panel_dyn);      // LDS rows, after the register rows are in place
+  T v[LU_NB];
+#pragma unroll
+  for (int c = 0; c < LU_NB; ++c) v[c] = (T)0;
+  int hia = 0;
+  double best = -1.0;
+  int bi = INT32_MAX;
+  // lanes cover RPL rows x 32 columns at a time; a round of PANEL_STAGE rows
+  // is LAY such layers, their loads in flight together
+  constexpr int RPL = NT / 32, LAY = PANEL_STAGE / RPL;
+  const int rl = t >> 5, cl = t & 31;
+  // register rows [0, gr): staged through LDS, coalesced loads
+  const int gr = min(ga, NT);
+  for (int R0 = 0; R0 < gr; R0 += PANEL_STAGE) {
+    T g[LAY];
+#pragma unroll
+    for (int b = 0; b < LAY; ++b) {
+      const int r = R0 + b * RPL + rl;
+      g[b] = (r < gr && cl < kb) ? a[(int64_t)r * lda + cl] : (T)0;
+    }
+#pragma unroll
+    for (int b = 0; b < LAY; ++b) {
+      stage[(b * RPL + rl) * 33 + cl] = g[b];
+      const int r = R0 + b * RPL + rl;
+      if (g[b] != (T)0) {
+        hia = r + 1;
+        const double av = fabs((double)g[b]);
+        if (cl == 0 && av > best) { best = av; bi = r; }
+      }
+    }
+    __syncthreads();
+    if (t >= R0 && t < R0 + PANEL_STAGE) {
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) v[c] = stage[(t - R0) * 33 + c];
+    }
+    __syncthreads();
+  }
+  // LDS rows [NT, ga)
+  for (int r0 = NT; r0 < ga; r0 += PANEL_STAGE) {
+    T g[LAY];
+#pragma unroll
+    for (int b = 0; b < LAY; ++b) {
+      const int r = r0 + b * RPL + rl;
+      g[b] = (r < ga && cl < kb) ? a[(int64_t)r * lda + cl] : (T)0;
+    }
+#pragma unroll
+    for (int b = 0; b < LAY; ++b) {
+      const int r = r0 + b * RPL + rl;
+      if (r < ga) L[cl * LRP + (r - NT)] = g[b];
+      if (g[b] != (T)0) {
+        hia = r + 1;
+        const double av = fabs((double)g[b]);
+        if (cl == 0 && av > best) { best = av; bi = r; }
+      }
+    }
+  }
+  {
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) hia = max(hia, __shfl_xor(hia, o, 64));
+    if (lane == 0) hi_s[wave] = hia;
+  }
+  int piv = block_argmax<NT>(best, bi, rv, ri, piv_s);  // its barriers also publish hi_s and the LDS rows
+  int ea = kb;
+  for (int w = 0; w < NW; ++w) ea = max(ea, hi_s[w]);
+  if (t == 0) {
+    int32_t* lv = rowhi + 2 * j;
+    if (k % LU_KMAX == 0) {
+      lv[0] = k + ea;
+      lv[1] = pb1;
+    } else {
+      lv[0] = max(lv[0], k + ea);
+      lv[1] = max(lv[1], pb1);
+    }
+  }
+  constexpr int LM = (PanelLds<T>::ROWS + NT - 1) / NT;  // LDS rows per thread: q = t + m NT
+  // The register row is rotated one place per column, so that at step jj
+  // v[c] holds column jj + c (mod LU_NB): every access to v is at a fixed
+  // index (a runtime index would put v in private memory) and after LU_NB
+  // steps v is back in column order. The pivot row xa and the exchange
+  // buffer xb are kept in column order.
+  for (int jj = 0; jj < LU_NB; ++jj) {
+    if (t == 0) {
+      ipiv[d.u_off + k + jj] = k + (piv < 0 ? jj : piv);
+      if (piv < 0 && info[j] == 0) info[j] = k + jj + 1;
+    }
+    // interchange rows jj (a register row) and piv: the pivot row to xa,
+    // row jj to xb; each owner then takes the other
+    const bool swap = piv >= 0 && piv != jj;
+    if (swap) {
+      if (piv < NT) {
+        if (t == piv) {
+#pragma unroll
+          for (int c = 0; c < LU_NB; ++c) xa[(c + jj) & (LU_NB - 1)] = v[c];
+        }
+      } else if (t == (piv - NT) % NT) {
+        const int q = piv - NT;
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) xa[c] = L[c * LRP + q];
+      }
+      if (t == jj) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) xb[(c + jj) & (LU_NB - 1)] = v[c];
+      }
+    } else if (t == jj) {
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) xa[(c + jj) & (LU_NB - 1)] = v[c];
+    }
+    __syncthreads();
+    if (swap) {
+      if (t == jj) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) v[c] = xa[(c + jj) & (LU_NB - 1)];
+      }
+      if (piv < NT) {
+        if (t == piv) {
+#pragma unroll
+          for (int c = 0; c < LU_NB; ++c) v[c] = xb[(c + jj) & (LU_NB - 1)];
+        }
+      } else if (t == (piv - NT) % NT) {
+        const int q = piv - NT;
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) L[c * LRP + q] = xb[c];
+      }
+    }
+    const T pv = xa[jj];
+    best = -1.0;
+    bi = INT32_MAX;
+    if (piv >= 0) {
+      asm volatile("" ::: "memory");  // xa is read where it is used
+      if (t > jj && t < ea) {  // register row t: column jj at v[0]
+        const T l = v[0] / pv;
+        v[0] = l;
+#pragma unroll
+        for (int c = 1; c < LU_NB; ++c)
+          if (c < LU_NB - jj) v[c] = v[c] - l * xa[jj + c];
+      }
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int m = 0; m < LM; ++m) {
+        const int q = t + m * NT;
+        if (NT + q < ea) {  // LDS row NT + q (> jj)
+          T* lr = L + q;
+          const T l = lr[jj * LRP] / pv;
+          lr[jj * LRP] = l;
+          for (int c = jj + 1; c < LU_NB; ++c) lr[c * LRP] = lr[c * LRP] - l * xa[c];
+          if (jj + 1 < LU_NB) {
+            const double av = fabs((double)lr[(jj + 1) * LRP]);
+            if (av > best) { best = av; bi = NT + q; }
+          }
+        }
+      }
+    } else if (jj + 1 < LU_NB) {  // singular column: nothing eliminated, search the next one
+#pragma unroll
+      for (int m = 0; m < LM; ++m) {
+        const int q = t + m * NT;
+        if (NT + q < ea) {
+          const double av = fabs((double)L[(jj + 1) * LRP + q]);
+          if (av > best) { best = av; bi = NT + q; }
+        }
+      }
+    }
+    // rotate: column jj + 1 to v[0]
+    {
+      const T v0 = v[0];
+#pragma unroll
+      for (int c = 0; c < LU_NB - 1; ++c) v[c] = v[c + 1];
+      v[LU_NB - 1] = v0;
+    }
+    if (jj + 1 < LU_NB && t > jj && t < ea) {  // pivot candidates of column jj + 1 among the register rows
+      const double av = fabs((double)v[0]);
+      if (av > best) { best = av; bi = t; }
+    }
+    if (jj + 1 < LU_NB) piv = block_argmax<NT>(best, bi, rv, ri, piv_s);
+    else __syncthreads();
+  }
+  // write back: the LDS rows, then the register rows through the staging tile
+  for (int r0 = NT; r0 < ea; r0 += PANEL_STAGE) {
+#pragma unroll
+    for (int b = 0; b < LAY; ++b) {
+      const int r = r0 + b * RPL + rl;
+      if (r < ea && cl < kb) a[(int64_t)r * lda + cl] = L[cl * LRP + (r - NT)];
+    }
+  }
+  __syncthreads();
+  const int er = min(ea, NT);
+  for (int R0 = 0; R0 < er; R0 += PANEL_STAGE) {
+    if (t >= R0 && t < R0 + PANEL_STAGE) {
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) stage[(t - R0) * 33 + c] = v[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < LAY; ++b) {
+      const int r = R0 + b * RPL + rl;
+      if (r < er && cl < kb) a[(int64_t)r * lda + cl] = stage[(b * RPL + rl) * 33 + cl];
+    }
+    __syncthreads();
+  }
+}
+
 // Unblocked LU with partial pivoting of the A_j rows of the panel
 // A[k:n, k:k+kb] of every subdomain (one block each); the border rows, which
 // never pivot, are eliminated afterwards by k_lu_border. Rows that are zero
@@ -794,7 +1057,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
                                                             const int32_t* __restrict__ pbound,
                                                             int32_t* __restrict__ rowhi) {
   constexpr int NW = PANEL_THREADS / 64;
-  __shared__ T tile[PANEL_TB * 32][33];
+  extern __shared__ __align__(16) unsigned char panel_dyn[];  // panel_lds_bytes<T>()
+  T (*tile)[33] = reinterpret_cast<T (*)[33]>(panel_dyn);      // PANEL_TB * 32 rows
   __shared__ T prow[LU_NB];
   __shared__ double rv[NW];
   __shared__ int ri[NW];
