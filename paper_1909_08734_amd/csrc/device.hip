@@ -899,7 +899,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
             const SubDesc& d = gd[j];
             if (k >= d.n) continue;
             const int ga = std::min(P.pbound[2 * ((size_t)d.pb_off + pb0 + k / LU_NB)] - k, d.n - k);
-            fast = d.n - k >= LU_NB && ga <= PANEL_FAST_THREADS + PanelLds<T>::ROWS;
+            fast = d.n - k >= LU_NB && ga <= PANEL_FAST_RR * PANEL_FAST_THREADS + PanelLds<T>::ROWS;
           }
           lplan.push_back(Launch{fast ? L_PANEL_FAST : L_PANEL, k, 0, 0, gn});
         }

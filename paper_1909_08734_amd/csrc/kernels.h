@@ -802,7 +802,8 @@ constexpr size_t panel_lds_bytes() {
 }
 constexpr int PANEL_STAGE = 128;  // rows per staging round of the register rows
 
-constexpr int PANEL_FAST_THREADS = 512;  // register rows per block of the fast form
+constexpr int PANEL_FAST_THREADS = 512;  // threads per block of the fast form
+constexpr int PANEL_FAST_RR = 2;         // register rows per thread: rows t and t + PANEL_FAST_THREADS
 
 // Used only when every panel of the launch is LU_NB wide and its rows that
 // may be nonzero fit (host-checked from pbound).
@@ -814,6 +815,8 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
                                                                       const int32_t* __restrict__ pbound,
                                                                       int32_t* __restrict__ rowhi) {
   constexpr int NT = PANEL_FAST_THREADS;
+  constexpr int RR = PANEL_FAST_RR;
+  constexpr int NR = RR * NT;  // register rows; LDS rows follow
   constexpr int NW = NT / 64;
   constexpr int LRP = PanelLds<T>::LRP;
   extern __shared__ __align__(16) unsigned char panel_dyn[];  // panel_lds_bytes<T>()
@@ -836,9 +839,11 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
   const int t = threadIdx.x;
   T* stage = reinterpret_cast<T*>(panel_dyn);  // PANEL_STAGE x 33
   T* L = reinterpret_cast<T*>(panel_dyn);      // LDS rows, after the register rows are in place
-  T v[LU_NB];
+  T v[RR][LU_NB];  // register row t + s NT in v[s]
 #pragma unroll
-  for (int c = 0; c < LU_NB; ++c) v[c] = (T)0;
+  for (int s2 = 0; s2 < RR; ++s2)
+#pragma unroll
+    for (int c = 0; c < LU_NB; ++c) v[s2][c] = (T)0;
   int hia = 0;
   double best = -1.0;
   int bi = INT32_MAX;
@@ -847,7 +852,7 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
   constexpr int RPL = NT / 32, LAY = PANEL_STAGE / RPL;
   const int rl = t >> 5, cl = t & 31;
   // register rows [0, gr): staged through LDS, coalesced loads
-  const int gr = min(ga, NT);
+  const int gr = min(ga, NR);
   for (int R0 = 0; R0 < gr; R0 += PANEL_STAGE) {
     T g[LAY];
 #pragma unroll
@@ -866,14 +871,18 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
       }
     }
     __syncthreads();
-    if (t >= R0 && t < R0 + PANEL_STAGE) {
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) v[c] = stage[(t - R0) * 33 + c];
+    for (int s2 = 0; s2 < RR; ++s2) {
+      const int r = t + s2 * NT;
+      if (r >= R0 && r < R0 + PANEL_STAGE) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) v[s2][c] = stage[(r - R0) * 33 + c];
+      }
     }
     __syncthreads();
   }
-  // LDS rows [NT, ga)
-  for (int r0 = NT; r0 < ga; r0 += PANEL_STAGE) {
+  // LDS rows [NR, ga)
+  for (int r0 = NR; r0 < ga; r0 += PANEL_STAGE) {
     T g[LAY];
 #pragma unroll
     for (int b = 0; b < LAY; ++b) {
@@ -883,7 +892,7 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
 #pragma unroll
     for (int b = 0; b < LAY; ++b) {
       const int r = r0 + b * RPL + rl;
-      if (r < ga) L[cl * LRP + (r - NT)] = g[b];
+      if (r < ga) L[cl * LRP + (r - NR)] = g[b];
       if (g[b] != (T)0) {
         hia = r + 1;
         const double av = fabs((double)g[b]);
@@ -925,37 +934,45 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
     // row jj to xb; each owner then takes the other
     const bool swap = piv >= 0 && piv != jj;
     if (swap) {
-      if (piv < NT) {
-        if (t == piv) {
+      if (piv < NR) {
+        if (t == piv % NT) {
 #pragma unroll
-          for (int c = 0; c < LU_NB; ++c) xa[(c + jj) & (LU_NB - 1)] = v[c];
+          for (int s2 = 0; s2 < RR; ++s2)
+            if (s2 == piv / NT) {
+#pragma unroll
+              for (int c = 0; c < LU_NB; ++c) xa[(c + jj) & (LU_NB - 1)] = v[s2][c];
+            }
         }
-      } else if (t == (piv - NT) % NT) {
-        const int q = piv - NT;
+      } else if (t == (piv - NR) % NT) {
+        const int q = piv - NR;
 #pragma unroll
         for (int c = 0; c < LU_NB; ++c) xa[c] = L[c * LRP + q];
       }
       if (t == jj) {
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) xb[(c + jj) & (LU_NB - 1)] = v[c];
+        for (int c = 0; c < LU_NB; ++c) xb[(c + jj) & (LU_NB - 1)] = v[0][c];
       }
     } else if (t == jj) {
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) xa[(c + jj) & (LU_NB - 1)] = v[c];
+      for (int c = 0; c < LU_NB; ++c) xa[(c + jj) & (LU_NB - 1)] = v[0][c];
     }
     __syncthreads();
     if (swap) {
       if (t == jj) {
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) v[c] = xa[(c + jj) & (LU_NB - 1)];
+        for (int c = 0; c < LU_NB; ++c) v[0][c] = xa[(c + jj) & (LU_NB - 1)];
       }
-      if (piv < NT) {
-        if (t == piv) {
+      if (piv < NR) {
+        if (t == piv % NT) {
 #pragma unroll
-          for (int c = 0; c < LU_NB; ++c) v[c] = xb[(c + jj) & (LU_NB - 1)];
+          for (int s2 = 0; s2 < RR; ++s2)
+            if (s2 == piv / NT) {
+#pragma unroll
+              for (int c = 0; c < LU_NB; ++c) v[s2][c] = xb[(c + jj) & (LU_NB - 1)];
+            }
         }
-      } else if (t == (piv - NT) % NT) {
-        const int q = piv - NT;
+      } else if (t == (piv - NR) % NT) {
+        const int q = piv - NR;
 #pragma unroll
         for (int c = 0; c < LU_NB; ++c) L[c * LRP + q] = xb[c];
       }
@@ -964,26 +981,30 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
     best = -1.0;
     bi = INT32_MAX;
     if (piv >= 0) {
-      asm volatile("" ::: "memory");  // xa is read where it is used
-      if (t > jj && t < ea) {  // register row t: column jj at v[0]
-        const T l = v[0] / pv;
-        v[0] = l;
 #pragma unroll
-        for (int c = 1; c < LU_NB; ++c)
-          if (c < LU_NB - jj) v[c] = v[c] - l * xa[jj + c];
+      for (int s2 = 0; s2 < RR; ++s2) {
+        asm volatile("" ::: "memory");  // xa is read where it is used
+        const int r = t + s2 * NT;
+        if (r > jj && r < ea) {  // register row r: column jj at v[s2][0]
+          const T l = v[s2][0] / pv;
+          v[s2][0] = l;
+#pragma unroll
+          for (int c = 1; c < LU_NB; ++c)
+            if (c < LU_NB - jj) v[s2][c] = v[s2][c] - l * xa[jj + c];
+        }
       }
       asm volatile("" ::: "memory");
 #pragma unroll
       for (int m = 0; m < LM; ++m) {
         const int q = t + m * NT;
-        if (NT + q < ea) {  // LDS row NT + q (> jj)
+        if (NR + q < ea) {  // LDS row NR + q (> jj)
           T* lr = L + q;
           const T l = lr[jj * LRP] / pv;
           lr[jj * LRP] = l;
           for (int c = jj + 1; c < LU_NB; ++c) lr[c * LRP] = lr[c * LRP] - l * xa[c];
           if (jj + 1 < LU_NB) {
             const double av = fabs((double)lr[(jj + 1) * LRP]);
-            if (av > best) { best = av; bi = NT + q; }
+            if (av > best) { best = av; bi = NR + q; }
           }
         }
       }
@@ -991,40 +1012,48 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
 #pragma unroll
       for (int m = 0; m < LM; ++m) {
         const int q = t + m * NT;
-        if (NT + q < ea) {
+        if (NR + q < ea) {
           const double av = fabs((double)L[(jj + 1) * LRP + q]);
-          if (av > best) { best = av; bi = NT + q; }
+          if (av > best) { best = av; bi = NR + q; }
         }
       }
     }
-    // rotate: column jj + 1 to v[0]
-    {
-      const T v0 = v[0];
+    // rotate: column jj + 1 to v[s][0]; pivot candidates of column jj + 1
+    // among the register rows (in row order, after the LDS rows' candidates:
+    // ties keep the lower row in block_argmax)
 #pragma unroll
-      for (int c = 0; c < LU_NB - 1; ++c) v[c] = v[c + 1];
-      v[LU_NB - 1] = v0;
-    }
-    if (jj + 1 < LU_NB && t > jj && t < ea) {  // pivot candidates of column jj + 1 among the register rows
-      const double av = fabs((double)v[0]);
-      if (av > best) { best = av; bi = t; }
+    for (int s2 = 0; s2 < RR; ++s2) {
+      const T v0 = v[s2][0];
+#pragma unroll
+      for (int c = 0; c < LU_NB - 1; ++c) v[s2][c] = v[s2][c + 1];
+      v[s2][LU_NB - 1] = v0;
+      const int r = t + s2 * NT;
+      if (jj + 1 < LU_NB && r > jj && r < ea) {
+        const double av = fabs((double)v[s2][0]);
+        if (av > best || (av == best && r < bi)) { best = av; bi = r; }
+      }
     }
     if (jj + 1 < LU_NB) piv = block_argmax<NT>(best, bi, rv, ri, piv_s);
     else __syncthreads();
   }
   // write back: the LDS rows, then the register rows through the staging tile
-  for (int r0 = NT; r0 < ea; r0 += PANEL_STAGE) {
+  for (int r0 = NR; r0 < ea; r0 += PANEL_STAGE) {
 #pragma unroll
     for (int b = 0; b < LAY; ++b) {
       const int r = r0 + b * RPL + rl;
-      if (r < ea && cl < kb) a[(int64_t)r * lda + cl] = L[cl * LRP + (r - NT)];
+      if (r < ea && cl < kb) a[(int64_t)r * lda + cl] = L[cl * LRP + (r - NR)];
     }
   }
   __syncthreads();
-  const int er = min(ea, NT);
+  const int er = min(ea, NR);
   for (int R0 = 0; R0 < er; R0 += PANEL_STAGE) {
-    if (t >= R0 && t < R0 + PANEL_STAGE) {
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) stage[(t - R0) * 33 + c] = v[c];
+    for (int s2 = 0; s2 < RR; ++s2) {
+      const int r = t + s2 * NT;
+      if (r >= R0 && r < R0 + PANEL_STAGE) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) stage[(r - R0) * 33 + c] = v[s2][c];
+      }
     }
     __syncthreads();
 #pragma unroll
