@@ -975,9 +975,10 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
           k_lu_border<T><<<dim3(L.units, gn), 256, 0, ctx->stream>>>(gdesc, dA, L.k, dpb + 2 * (int64_t)pb0);
           break;
         case L_SWAP_TRSM:
+          k_lu_swap_trsm<T, true><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, gipiv, jb, pre, L.n_jobs);
+          break;
         case L_SWAP:
-          k_lu_swap_trsm<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, gipiv, jb, pre, L.n_jobs,
-                                                                     L.kind == L_SWAP_TRSM ? 1 : 0);
+          k_lu_swap_trsm<T, false><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, gipiv, jb, pre, L.n_jobs);
           break;
         case L_LINV:
           k_lu_linv<T><<<L.units, TRSM_COLS, 0, ctx->stream>>>(gdesc, dA, jb, pre, L.n_jobs, dlm, dntile);

@@ -1309,18 +1309,17 @@ struct LuJob {
 constexpr int TRSM_COLS = 64;
 
 // Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
-// [c_lo, c_hi); with `trsm`, then U = L11^{-1} A on rows [kstart, kstart+kdim)
-// (L11 unit lower triangular). One wave per 64 columns, column values in LDS.
-// The interchanges are loaded once, two per lane, and broadcast by shuffles
-// (most are the identity, so the loop then rarely touches memory).
-template <typename T>
+// [c_lo, c_hi); with TRSM, then U = L11^{-1} A on rows [kstart, kstart+kdim)
+// (L11 unit lower triangular), column values in LDS. One wave per 64 columns.
+// The interchanges are loaded once, two per lane, and broadcast by shuffles;
+// most are the identity, and a block whose interchanges all are skips them.
+template <typename T, bool TRSM>
 __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __restrict__ desc, T* __restrict__ A,
                                                             const int32_t* __restrict__ ipiv,
                                                             const LuJob* __restrict__ jobs,
-                                                            const int32_t* __restrict__ prefix, int n_jobs,
-                                                            int trsm) {
+                                                            const int32_t* __restrict__ prefix, int n_jobs) {
   static_assert(LU_KMAX <= 2 * TRSM_COLS, "two interchanges per lane");
-  __shared__ T X[LU_KMAX][TRSM_COLS];
+  __shared__ T X[TRSM ? LU_KMAX : 1][TRSM_COLS];  // the interchange-only form needs no LDS
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
@@ -1330,9 +1329,11 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
   const int32_t* pg = ipiv + d.u_off + jb.kstart;
-  const int pv0 = t < jb.kdim ? pg[t] : 0;
-  const int pv1 = t + TRSM_COLS < jb.kdim ? pg[t + TRSM_COLS] : 0;
-  for (int i = 0; i < jb.kdim; ++i) {
+  const int pv0 = t < jb.kdim ? pg[t] : jb.kstart + t;
+  const int pv1 = t + TRSM_COLS < jb.kdim ? pg[t + TRSM_COLS] : jb.kstart + t + TRSM_COLS;
+  // most interchanges are the identity: skip the loop when all of them are
+  const bool any_swap = __any(pv0 != jb.kstart + t || pv1 != jb.kstart + t + TRSM_COLS);
+  for (int i = 0; any_swap && i < jb.kdim; ++i) {
     const int p = __shfl(i < TRSM_COLS ? pv0 : pv1, i & (TRSM_COLS - 1), TRSM_COLS);
     const int r = jb.kstart + i;
     if (live && p != r) {
@@ -1341,7 +1342,7 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
       a[p * lda + c] = tmp;
     }
   }
-  if (!trsm || !live) return;
+  if (!TRSM || !live) return;
   // forward substitution by rows: X_i -= l_iq X_q for q = 0, 1, ..., i-1 in
   // turn (the order of the column-by-column form), reading row i of L11 (contiguous)
   const T* l = a + (int64_t)jb.kstart * lda + jb.kstart;
