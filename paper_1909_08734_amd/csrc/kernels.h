@@ -1308,6 +1308,25 @@ struct LuJob {
 
 constexpr int TRSM_COLS = 64;
 
+// sum_{q < i} li[q] X[q][t] in four interleaved partial sums (q mod 4),
+// combined as (s0 + s1) + (s2 + s3): a quarter of the dependent chain of one
+// running sum, in a fixed order.
+template <typename T>
+__device__ __forceinline__ T row_dot4(const T* __restrict__ li, const T (*X)[TRSM_COLS], int i, int t) {
+  T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+  int q = 0;
+  for (; q + 4 <= i; q += 4) {
+    s0 += li[q] * X[q][t];
+    s1 += li[q + 1] * X[q + 1][t];
+    s2 += li[q + 2] * X[q + 2][t];
+    s3 += li[q + 3] * X[q + 3][t];
+  }
+  if (q < i) s0 += li[q] * X[q][t];
+  if (q + 1 < i) s1 += li[q + 1] * X[q + 1][t];
+  if (q + 2 < i) s2 += li[q + 2] * X[q + 2][t];
+  return (s0 + s1) + (s2 + s3);
+}
+
 // Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
 // [c_lo, c_hi); with TRSM, then U = L11^{-1} A on rows [kstart, kstart+kdim)
 // (L11 unit lower triangular), column values in LDS. One wave per 64 columns.
@@ -1343,14 +1362,12 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
     }
   }
   if (!TRSM || !live) return;
-  // forward substitution by rows: X_i -= l_iq X_q for q = 0, 1, ..., i-1 in
-  // turn (the order of the column-by-column form), reading row i of L11 (contiguous)
+  // forward substitution by rows: X_i -= sum_{q<i} l_iq X_q, reading row i of
+  // L11 contiguously
   const T* l = a + (int64_t)jb.kstart * lda + jb.kstart;
   for (int i = 0; i < jb.kdim; ++i) X[i][t] = a[(jb.kstart + i) * lda + c];
   for (int i = 1; i < jb.kdim; ++i) {
-    const T* li = l + (int64_t)i * lda;
-    T x = X[i][t];
-    for (int q = 0; q < i; ++q) x -= li[q] * X[q][t];
+    const T x = X[i][t] - row_dot4<T>(l + (int64_t)i * lda, X, i, t);
     X[i][t] = x;
     a[(jb.kstart + i) * lda + c] = x;
   }
@@ -1528,13 +1545,11 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_linv(const SubDesc* __restrict
   const int col = (blockIdx.x - prefix[q]) * TRSM_COLS + t;  // < LU_KMAX
   const int kd = jb.kdim;
   const int64_t lda = d.lda;
-  // forward substitution by rows on the identity column (the column-by-column
-  // order of subtractions, reading row i of L11 contiguously)
+  // forward substitution by rows on the identity column, reading row i of L11
+  // contiguously
   const T* l = A + d.a_off + (int64_t)jb.kstart * lda + jb.kstart;
   for (int i = 0; i < kd; ++i) {
-    const T* li = l + (int64_t)i * lda;
-    T x = i == col ? (T)1 : (T)0;
-    for (int q = 0; q < i; ++q) x -= li[q] * X[q][t];
+    const T x = (i == col ? (T)1 : (T)0) - row_dot4<T>(l + (int64_t)i * lda, X, i, t);
     X[i][t] = x;
   }
   T* out = lm + (int64_t)jb.j * LU_KMAX * LU_KMAX;
