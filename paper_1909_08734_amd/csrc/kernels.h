@@ -1421,55 +1421,95 @@ __device__ __forceinline__ bool tile_update(T* a, int64_t lda, int rows, int col
   const int li = lane & 15, lk = lane >> 4;
   AT acc[NBR][NBC];
   bool nz = false;
+  // C element (bi, bj, i) of a lane: a row base that is the same for the whole
+  // wave plus one byte offset per lane, so that every load and store of the
+  // tile takes the scalar-base address form with the same offset register
+  // (no address register is rewritten between the stores). Tiles wholly
+  // inside the view skip the bounds tests.
+  const int wru = __builtin_amdgcn_readfirstlane(wr), wcu = __builtin_amdgcn_readfirstlane(wc);
+  const uint32_t loff = (uint32_t)(((int64_t)Acc4<T>::row(lk, 0) * lda + li) * (int64_t)sizeof(T));
+  auto cbase = [&](int bi, int bj, int i) {
+    return reinterpret_cast<char*>(a + (int64_t)(r0 + wru + bi * 16 + Acc4<T>::row(0, i)) * lda +
+                                   (c0 + wcu + bj * 16));
+  };
+  const bool full = r0 + TM <= rows && c0 + TN <= cols;
+  if (full) {
 #pragma unroll
-  for (int bi = 0; bi < NBR; ++bi)
+    for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < NBC; ++bj)
+      for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
-        acc[bi][bj][i] = (rr < rows && cc < cols) ? a[(int64_t)rr * lda + cc] : (T)0;
-      }
+        for (int i = 0; i < 4; ++i) acc[bi][bj][i] = *reinterpret_cast<const T*>(cbase(bi, bj, i) + loff);
+  } else {
+#pragma unroll
+    for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
+          acc[bi][bj][i] = (rr < rows && cc < cols) ? *reinterpret_cast<const T*>(cbase(bi, bj, i) + loff) : (T)0;
+        }
+  }
   // K in chunks of GEMM_KC, staged through LDS; the next chunk's loads are issued
   // into registers before the current chunk's matrix-core steps, so their
-  // latency overlaps the arithmetic.
-  constexpr int PL = TM * GEMM_KC / 256, PU = GEMM_KC * TN / 256;
-  T lreg[PL], ureg[PU];
+  // latency overlaps the arithmetic (nothing reads the loaded registers until
+  // they are staged). Each load brings V consecutive elements of a row (16
+  // bytes); a vector is loaded when its first element is in the tile, and its
+  // elements past the tile's edge are zeroed as it is staged. The row starts
+  // are V-aligned except for U sources that begin at an unaligned column (the
+  // last outer block's right-hand columns), hence the element-aligned vector
+  // type. Every vector read stays inside its matrix row or the next one: rows
+  // are padded to a multiple of 16 columns, the L columns start V-aligned,
+  // and U rows are never the matrix's last row.
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T VT __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+  constexpr int PL = TM * GEMM_KC / (256 * V), PU = GEMM_KC * TN / (256 * V);
+  VT lreg[PL], ureg[PU];
   auto fetch = [&](int kc) {
     const int kb = min(GEMM_KC, kdim - kc);
 #pragma unroll
     for (int t = 0; t < PL; ++t) {
-      const int idx = threadIdx.x + t * 256;
+      const int idx = (threadIdx.x + t * 256) * V;
       const int i = idx / GEMM_KC, qq = idx - (idx / GEMM_KC) * GEMM_KC;
-      lreg[t] = (r0 + i < rows && qq < kb) ? lsrc[(int64_t)(r0 + i) * lld + kc + qq] : (T)0;
+      lreg[t] = (r0 + i < rows && qq < kb) ? *reinterpret_cast<const VT*>(lsrc + (int64_t)(r0 + i) * lld + kc + qq)
+                                           : (VT)(T)0;
     }
 #pragma unroll
     for (int t = 0; t < PU; ++t) {
-      const int idx = threadIdx.x + t * 256;
+      const int idx = (threadIdx.x + t * 256) * V;
       const int qq = idx / TN, jx = idx - (idx / TN) * TN;
-      ureg[t] = (qq < kb && c0 + jx < cols) ? usrc[(int64_t)(kc + qq) * uld + c0 + jx] : (T)0;
+      ureg[t] = (qq < kb && c0 + jx < cols) ? *reinterpret_cast<const VT*>(usrc + (int64_t)(kc + qq) * uld + c0 + jx)
+                                             : (VT)(T)0;
     }
   };
   if (kdim > 0) fetch(0);
   for (int kc = 0; kc < kdim; kc += GEMM_KC) {
     const int kb = min(GEMM_KC, kdim - kc);
+    // L is staged negated, so that the steps below add products
 #pragma unroll
-    for (int t = 0; t < PL; ++t) {
-      const int idx = threadIdx.x + t * 256;
-      Ls[idx / GEMM_KC][idx - (idx / GEMM_KC) * GEMM_KC] = lreg[t];
-    }
+    for (int t = 0; t < PL; ++t)
 #pragma unroll
-    for (int t = 0; t < PU; ++t) {
-      const int idx = threadIdx.x + t * 256;
-      Us[idx / TN][idx - (idx / TN) * TN] = ureg[t];
-    }
+      for (int e = 0; e < V; ++e) {
+        const int idx = (threadIdx.x + t * 256) * V + e;
+        const int qq = idx - (idx / GEMM_KC) * GEMM_KC;
+        Ls[idx / GEMM_KC][qq] = qq < kb ? -lreg[t][e] : (T)0;
+      }
+#pragma unroll
+    for (int t = 0; t < PU; ++t)
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int idx = (threadIdx.x + t * 256) * V + e;
+        const int jx = idx - (idx / TN) * TN;
+        Us[idx / TN][jx] = c0 + jx < cols ? ureg[t][e] : (T)0;
+      }
     __syncthreads();
     if (kc + GEMM_KC < kdim) fetch(kc + GEMM_KC);
     const int ksteps = (kb + 3) >> 2;
     for (int kk = 0; kk < ksteps; ++kk) {
       T av[NBR], bv[NBC];
 #pragma unroll
-      for (int bi = 0; bi < NBR; ++bi) av[bi] = -Ls[wr + bi * 16 + li][kk * 4 + lk];
+      for (int bi = 0; bi < NBR; ++bi) av[bi] = Ls[wr + bi * 16 + li][kk * 4 + lk];
 #pragma unroll
       for (int bj = 0; bj < NBC; ++bj) bv[bj] = Us[kk * 4 + lk][wc + bj * 16 + li];
 #pragma unroll
@@ -1479,18 +1519,30 @@ __device__ __forceinline__ bool tile_update(T* a, int64_t lda, int rows, int col
     }
     __syncthreads();
   }
+  if (full) {
 #pragma unroll
-  for (int bi = 0; bi < NBR; ++bi)
+    for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < NBC; ++bj)
+      for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
-        if (rr < rows && cc < cols) {
-          a[(int64_t)rr * lda + cc] = acc[bi][bj][i];
+        for (int i = 0; i < 4; ++i) {
+          *reinterpret_cast<T*>(cbase(bi, bj, i) + loff) = acc[bi][bj][i];
           nz |= acc[bi][bj][i] != (T)0;
         }
-      }
+  } else {
+#pragma unroll
+    for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rr = r0 + wr + bi * 16 + Acc4<T>::row(lk, i), cc = c0 + wc + bj * 16 + li;
+          if (rr < rows && cc < cols) {
+            *reinterpret_cast<T*>(cbase(bi, bj, i) + loff) = acc[bi][bj][i];
+            nz |= acc[bi][bj][i] != (T)0;
+          }
+        }
+  }
   return nz;
 }
 
