@@ -410,6 +410,26 @@ size_t cpm_footprint_bytes(const cpm_ctx* ctx);
 int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident,
                            size_t* peak);
 
+/*
+ * Cache of large device work buffers (the bordered local matrices of a
+ * factorisation and the W arenas, buffers of 64 MiB or more), process-wide
+ * with one cache per device. Returning such a buffer to the driver becomes
+ * slow once the device memory that was never used has been handed out
+ * (tenths of a second per 10 GB), so released buffers are kept and reused by
+ * later factorisations on the same device, from any context. At most `bytes`
+ * idle bytes are kept per device (default 64 GiB; the longest idle buffer is
+ * freed first); 0 keeps none. Lowering the cap frees idle buffers at once.
+ * An allocation that fails empties its device's cache and is tried again.
+ * The idle bytes are not part of cpm_footprint_bytes or of the estimates
+ * above: callers that budget device memory should set a cap they can
+ * afford. Returns 0; *idle_before (may be NULL) gets the idle bytes held on
+ * all devices before the call.
+ */
+int cpm_set_workspace_cache(size_t bytes, size_t* idle_before);
+/* The cap, the idle bytes held and the cached buffers in use on `device`
+ * (any output may be NULL). EINVAL for a negative device. */
+int cpm_workspace_cache(int device, size_t* cap, size_t* idle, size_t* in_use);
+
 /* Per-kernel timing with HIP events on the context stream (off by default;
  * the events ride on the kernel dispatches, no extra packets). which:
  * 0 = preconditioner apply, 1 = extension apply, 2 = stencil apply (also in

@@ -113,6 +113,9 @@ _SIGS = {
     "cpm_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "cpm_kernel_time": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "cpm_selftest_tile": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "cpm_set_workspace_cache": (C.c_int, [C.c_size_t, C.POINTER(C.c_size_t)]),
+    "cpm_workspace_cache": (C.c_int, [C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                      C.POINTER(C.c_size_t)]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -168,6 +171,23 @@ def selftest_tile(a, b, c, prec=FP64, device=0):
     if rc != 0:
         raise CpmError(rc, "selftest_tile failed")
     return Cm
+
+
+def set_workspace_cache(nbytes):
+    """Most idle bytes of large work buffers kept for reuse per device (0: none);
+    returns the idle bytes held on all devices before the call."""
+    before = C.c_size_t()
+    lib().cpm_set_workspace_cache(int(nbytes), C.byref(before))
+    return before.value
+
+
+def workspace_cache(device=0):
+    """(cap, idle bytes, cached bytes in use) of the work-buffer cache on `device`."""
+    cap, idle, used = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    rc = lib().cpm_workspace_cache(int(device), C.byref(cap), C.byref(idle), C.byref(used))
+    if rc != 0:
+        raise CpmError(rc, "workspace_cache failed")
+    return cap.value, idle.value, used.value
 
 
 class Context:

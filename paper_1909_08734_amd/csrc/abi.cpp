@@ -426,6 +426,18 @@ int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* re
   return CPM_OK;
 }
 
+int cpm_set_workspace_cache(size_t bytes, size_t* idle_before) {
+  const size_t before = cpm::pool_set_cap(bytes);
+  if (idle_before) *idle_before = before;
+  return CPM_OK;
+}
+
+int cpm_workspace_cache(int device, size_t* cap, size_t* idle, size_t* in_use) {
+  if (device < 0) return CPM_EINVAL;
+  cpm::pool_stats(device, cap, idle, in_use);
+  return CPM_OK;
+}
+
 int cpm_set_factor_workspace(cpm_ctx* ctx, size_t bytes) {
   if (!ctx) return CPM_EINVAL;
   ctx->dev.ws_limit = bytes ? bytes : (size_t(64) << 30);

@@ -231,4 +231,8 @@ void dev_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* resident, s
 void dev_free_all(cpm_ctx* ctx);
 void dev_free_factor(cpm_ctx* ctx);
 void timer_harvest(cpm_ctx* ctx);
+// Per-device cache of large work buffers (device.hip): the cap on idle bytes
+// per device (returns the idle bytes held before), and a device's figures.
+size_t pool_set_cap(size_t bytes);
+void pool_stats(int dev, size_t* cap, size_t* idle, size_t* in_use);
 }  // namespace cpm

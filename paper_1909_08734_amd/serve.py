@@ -103,8 +103,13 @@ class Server:
         self.c_grid = np.exp(np.linspace(math.log(lo), math.log(hi), int(c_levels)))
         self.keep = bool(keep_solutions)
         if budget_bytes is None:
+            # the library keeps released factorisation work buffers for reuse
+            # outside this ledger: give that cache a tenth of the free memory
+            # (at most 64 GiB) and the ledger what is left of 85%
             free, _ = torch.cuda.mem_get_info(self.device)
-            budget_bytes = int(0.85 * free)
+            cache = min(64 << 30, int(0.10 * free))
+            B.set_workspace_cache(cache)
+            budget_bytes = int(0.85 * free) - cache
         self.budget = int(budget_bytes)
         self.used = 0
         self.peak_used = 0
