@@ -416,7 +416,9 @@ int cpm_footprint_estimate(const cpm_ctx* ctx, int prec, int restart, size_t* re
  * with one cache per device. Returning such a buffer to the driver becomes
  * slow once the device memory that was never used has been handed out
  * (tenths of a second per 10 GB), so released buffers are kept and reused by
- * later factorisations on the same device, from any context. At most `bytes`
+ * later factorisations on the same device, from any context, by requests of
+ * at least eight ninths of a buffer's size (a much larger buffer is not lent
+ * out, so a request holds about what its caller budgeted). At most `bytes`
  * idle bytes are kept per device (default 64 GiB; the longest idle buffer is
  * freed first); 0 keeps none. Lowering the cap frees idle buffers at once.
  * An allocation that fails empties its device's cache and is tried again.

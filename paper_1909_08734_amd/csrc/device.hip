@@ -43,7 +43,9 @@ void dfree(P*& p) {
 // against about 0.2 s for a whole factorisation at that size), and every
 // factorisation allocates its bordered matrices and a new W arena. Buffers of
 // at least kPoolMin bytes are therefore released into a per-device cache and
-// handed out again to requests they cover (smallest that fits). The cache
+// handed out again to requests of at least eight ninths of their size
+// (smallest that fits; a much larger buffer is not lent out, so the memory a
+// request holds stays close to what its caller budgeted for it). The cache
 // keeps at most g_pool_cap idle bytes per device, evicting the longest idle
 // first; an allocation that fails empties the device's cache and is tried
 // once more. A buffer is released only after the work using it has finished
@@ -94,7 +96,9 @@ hipError_t pool_malloc(void** p, size_t bytes) {
     std::lock_guard<std::mutex> lk(pl->mu);
     size_t best = pl->idle.size();
     for (size_t k = 0; k < pl->idle.size(); ++k)
-      if (pl->idle[k].bytes >= bytes && (best == pl->idle.size() || pl->idle[k].bytes < pl->idle[best].bytes)) best = k;
+      if (pl->idle[k].bytes >= bytes && pl->idle[k].bytes - bytes <= bytes / 8 &&
+          (best == pl->idle.size() || pl->idle[k].bytes < pl->idle[best].bytes))
+        best = k;
     if (best < pl->idle.size()) {
       *p = pl->idle[best].p;
       pl->live[*p] = pl->idle[best].bytes;
