@@ -78,7 +78,7 @@ void pool_shrink(DevPool& pl, size_t keep) {
     size_t q = 0;
     for (size_t k = 1; k < pl.idle.size(); ++k)
       if (pl.idle[k].stamp < pl.idle[q].stamp) q = k;
-    hipFree(pl.idle[q].p);
+    (void)hipFree(pl.idle[q].p);
     pl.idle_bytes -= pl.idle[q].bytes;
     pl.idle.erase(pl.idle.begin() + q);
   }
@@ -89,7 +89,7 @@ void pool_shrink(DevPool& pl, size_t keep) {
 hipError_t pool_malloc(void** p, size_t bytes) {
   *p = nullptr;
   int dev = -1;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   DevPool* pl = pool_of(dev);
   if (!pl || bytes < kPoolMin) return hipMalloc(p, bytes);
   {
@@ -130,7 +130,7 @@ template <class P>
 void pool_free(P*& p) {
   if (!p) return;
   int dev = -1;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   DevPool* pl = pool_of(dev);
   bool pooled = false;
   if (pl) {
@@ -144,7 +144,7 @@ void pool_free(P*& p) {
       pool_shrink(*pl, g_pool_cap.load());
     }
   }
-  if (!pooled) hipFree((void*)p);
+  if (!pooled) (void)hipFree((void*)p);
   p = nullptr;
 }
 
@@ -2319,17 +2319,17 @@ size_t pool_set_cap(size_t bytes) {
   g_pool_cap.store(bytes);
   size_t before = 0;
   int cur = -1;
-  hipGetDevice(&cur);
+  (void)hipGetDevice(&cur);
   for (int d = 0; d < kPoolDevices; ++d) {
     DevPool& pl = g_pool[d];
     std::lock_guard<std::mutex> lk(pl.mu);
     before += pl.idle_bytes;
     if (pl.idle_bytes > bytes) {
-      hipSetDevice(d);
+      (void)hipSetDevice(d);
       pool_shrink(pl, bytes);
     }
   }
-  if (cur >= 0) hipSetDevice(cur);
+  if (cur >= 0) (void)hipSetDevice(cur);
   return before;
 }
 

@@ -743,28 +743,83 @@ static_assert(LU_KMAX % LU_NB == 0, "whole panels per outer block");
 constexpr int PANEL_THREADS = 1024;
 constexpr int PANEL_TB = 4;     // 32-row tiles per round of the panel's gather and write-back
 
-// (value, row) pair reduction over the block: largest |value|, lowest row on ties.
-template <int NT = PANEL_THREADS>
-__device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri, int* out) {
-  constexpr int NW = NT / 64;
+// (value, row) pairs are ordered by value, then by lower row: the maximum of
+// that total order is the pivot, whatever order the pairs are combined in.
+__device__ __forceinline__ bool argmax_takes(double ob, int oi, double b, int i) {
+  return ob > b || (ob == b && oi < i);
+}
+
+// One exchange of the wave argmax by a data-parallel-primitives lane move
+// (CTRL: a fixed pairing of lanes within each 16-lane row), no LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& best, int& bi) {
+  const long long b = __double_as_longlong(best);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(0, bi, CTRL, 0xF, 0xF, false);
+  const double ob = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  if (argmax_takes(ob, oi, best, bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+
+// Wave argmax: within each 16-lane row by four lane moves (swap neighbours,
+// swap pairs, mirror each half-row, mirror the row: each joins two groups
+// that already agree), then the four rows' results read from lanes 0, 16, 32
+// and 48; every lane returns the wave's result.
+__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
+  argmax_dpp<0xB1>(best, bi);   // quad_perm [1,0,3,2]
+  argmax_dpp<0x4E>(best, bi);   // quad_perm [2,3,0,1]
+  argmax_dpp<0x141>(best, bi);  // row_half_mirror
+  argmax_dpp<0x140>(best, bi);  // row_mirror
+  const long long b = __double_as_longlong(best);
+  const int blo = (int)b, bhi = (int)(b >> 32);
+  auto at = [&](int lane, double& v, int& i) {
+    const int lo = __builtin_amdgcn_readlane(blo, lane), hi = __builtin_amdgcn_readlane(bhi, lane);
+    v = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    i = __builtin_amdgcn_readlane(bi, lane);
+  };
+  double rb;
+  int ri;
+  at(0, rb, ri);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ob = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  for (int r = 16; r < 64; r += 16) {
+    double v;
+    int i;
+    at(r, v, i);
+    if (argmax_takes(v, i, rb, ri)) {
+      rb = v;
+      ri = i;
+    }
   }
+  best = rb;
+  bi = ri;
+}
+
+// (value, row) pair reduction over the block: largest |value|, lowest row on
+// ties; -1 when every value is zero. One barrier: each wave posts its result,
+// then every thread reduces the posted results itself. rv / ri are written
+// again only by the next call, which callers reach through another barrier.
+template <int NT = PANEL_THREADS>
+__device__ __forceinline__ int block_argmax(double best, int bi, double* rv, int* ri) {
+  constexpr int NW = NT / 64;
+  wave_argmax(best, bi);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) { rv[wave] = best; ri[wave] = bi; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b0 = rv[0];
-    int i0 = ri[0];
-    for (int w = 1; w < NW; ++w)
-      if (rv[w] > b0 || (rv[w] == b0 && ri[w] < i0)) { b0 = rv[w]; i0 = ri[w]; }
-    *out = (i0 == INT32_MAX || b0 == 0.0) ? -1 : i0;
+  if (lane == 0) {
+    rv[wave] = best;
+    ri[wave] = bi;
   }
   __syncthreads();
-  return *out;
+  double b0 = rv[0];
+  int i0 = ri[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w)
+    if (argmax_takes(rv[w], ri[w], b0, i0)) {
+      b0 = rv[w];
+      i0 = ri[w];
+    }
+  return (i0 == INT32_MAX || b0 == 0.0) ? -1 : i0;
 }
 
 // Panel scratch layout: 64-row tiles, column-major inside a tile, so that a
@@ -824,9 +879,7 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
   __shared__ T xb[LU_NB];
   __shared__ double rv[NW];
   __shared__ int ri[NW];
-  __shared__ int piv_s_;
   __shared__ int hi_s[NW];
-  int* piv_s = &piv_s_;
   const int j = blockIdx.x;
   const SubDesc d = desc[j];
   if (k >= d.n) return;
@@ -906,7 +959,7 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
     for (int o = 32; o > 0; o >>= 1) hia = max(hia, __shfl_xor(hia, o, 64));
     if (lane == 0) hi_s[wave] = hia;
   }
-  int piv = block_argmax<NT>(best, bi, rv, ri, piv_s);  // its barriers also publish hi_s and the LDS rows
+  int piv = block_argmax<NT>(best, bi, rv, ri);  // its barrier also publishes hi_s and the LDS rows
   int ea = kb;
   for (int w = 0; w < NW; ++w) ea = max(ea, hi_s[w]);
   if (t == 0) {
@@ -1033,7 +1086,7 @@ __global__ __launch_bounds__(PANEL_FAST_THREADS) void k_lu_panel_fast(const SubD
         if (av > best || (av == best && r < bi)) { best = av; bi = r; }
       }
     }
-    if (jj + 1 < LU_NB) piv = block_argmax<NT>(best, bi, rv, ri, piv_s);
+    if (jj + 1 < LU_NB) piv = block_argmax<NT>(best, bi, rv, ri);
     else __syncthreads();
   }
   // write back: the LDS rows, then the register rows through the staging tile
@@ -1091,7 +1144,6 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
   __shared__ T prow[LU_NB];
   __shared__ double rv[NW];
   __shared__ int ri[NW];
-  __shared__ int piv_s;
   __shared__ int hi_s[1][NW];
   const int j = blockIdx.x;
   const SubDesc d = desc[j];
@@ -1148,7 +1200,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
     for (int o = 32; o > 0; o >>= 1) hia = max(hia, __shfl_xor(hia, o, 64));
     if (lane == 0) hi_s[0][wave] = hia;
   }
-  int piv = block_argmax(best, bi, rv, ri, &piv_s);  // its barriers also publish hi_s
+  int piv = block_argmax(best, bi, rv, ri);  // its barrier also publishes hi_s
   // active rows [0, ea)
   int ea = kb;
   for (int w = 0; w < NW; ++w) ea = max(ea, hi_s[0][w]);
@@ -1212,7 +1264,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(const SubDesc* __res
         if (av > best) { best = av; bi = r; }
       }
     }
-    if (jj + 1 < kb) piv = block_argmax(best, bi, rv, ri, &piv_s);
+    if (jj + 1 < kb) piv = block_argmax(best, bi, rv, ri);
     else __syncthreads();
   }
   // write the active rows of the factored panel back (same rounds)
