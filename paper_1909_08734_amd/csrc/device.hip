@@ -530,6 +530,14 @@ struct Tiling {
 };
 constexpr Tiling kTilings[N_TILINGS] = {{2, 2, 4}, {4, 1, 4}, {2, 2, 3}, {4, 1, 6},
                                         {4, 4, 2}, {4, 4, 4}, {8, 2, 4}, {4, 2, 4}};
+// a wave's RPW rows must lie in one tile of W (the multi-vector tilings take
+// 2, 4 or 8 rows per wave as well)
+constexpr bool tilings_fit_tile() {
+  for (const Tiling& t : kTilings)
+    if (W_TILE % t.rpw != 0) return false;
+  return W_TILE % 8 == 0;
+}
+static_assert(tilings_fit_tile(), "every tiling's rows per wave must divide W_TILE");
 
 template <typename T>
 static const void* tiled_fn(int t) {

@@ -287,7 +287,7 @@ struct VecOf<float> {
 };
 
 constexpr int PRECOND_THREADS = 512;  // 8 waves per block
-constexpr int W_TILE = 32;            // rows per tile of W_j
+constexpr int W_TILE = 8;             // rows per tile of W_j (a multiple of every tiling's rows per wave)
 template <typename T>
 constexpr int W_CW = 64 * VecOf<T>::n;  // columns per chunk
 
