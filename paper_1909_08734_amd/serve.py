@@ -100,7 +100,11 @@ class Server:
         self.prec, self.restart, self.tol, self.max_iter = prec, int(restart), float(tol), int(max_iter)
         self.degree, self.overlap, self.nodes_per_sub = int(degree), int(overlap), int(nodes_per_sub)
         lo, hi = c_range
-        self.c_grid = np.exp(np.linspace(math.log(lo), math.log(hi), int(c_levels)))
+        # log-spaced levels over the range (one level: its geometric middle)
+        if int(c_levels) == 1:
+            self.c_grid = np.array([math.sqrt(lo * hi)])
+        else:
+            self.c_grid = np.exp(np.linspace(math.log(lo), math.log(hi), int(c_levels)))
         self.keep = bool(keep_solutions)
         if budget_bytes is None:
             # the library keeps released factorisation work buffers for reuse

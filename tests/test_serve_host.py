@@ -201,3 +201,13 @@ def test_clone_and_footprint_estimate_host_only():
         empty.clone(-1)
     ctx.close()
     empty.close()
+
+
+def test_one_level_is_the_middle_of_the_range():
+    s = make_server(c_range=(0.1, 10.0), c_levels=1)
+    np.testing.assert_allclose(s.c_grid, [1.0])
+    assert s.quantise(0.1) == s.quantise(9.9) == s.c_grid[0]
+    s3 = make_server(c_range=(0.1, 10.0), c_levels=3)
+    np.testing.assert_allclose(s3.c_grid, [0.1, 1.0, 10.0])
+    g = s3.c_grid
+    assert s3.quantise(0.3) == g[0] and s3.quantise(0.4) == g[1] and s3.quantise(3.0) == g[1] and s3.quantise(4.0) == g[2]
