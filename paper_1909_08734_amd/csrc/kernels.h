@@ -1362,11 +1362,28 @@ constexpr int TRSM_COLS = 64;
 
 // sum_{q < i} li[q] X[q][t] in four interleaved partial sums (q mod 4),
 // combined as (s0 + s1) + (s2 + s3): a quarter of the dependent chain of one
-// running sum, in a fixed order.
+// running sum, in a fixed order. Terms are fetched sixteen at a time, all
+// loads before the products, so that their latencies overlap (each partial
+// sum still adds its terms in q order).
 template <typename T>
 __device__ __forceinline__ T row_dot4(const T* __restrict__ li, const T (*X)[TRSM_COLS], int i, int t) {
   T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
   int q = 0;
+  for (; q + 16 <= i; q += 16) {
+    T lv[16], xv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      lv[u] = li[q + u];
+      xv[u] = X[q + u][t];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; u += 4) {
+      s0 += lv[u] * xv[u];
+      s1 += lv[u + 1] * xv[u + 1];
+      s2 += lv[u + 2] * xv[u + 2];
+      s3 += lv[u + 3] * xv[u + 3];
+    }
+  }
   for (; q + 4 <= i; q += 4) {
     s0 += li[q] * X[q][t];
     s1 += li[q + 1] * X[q + 1][t];
@@ -1377,6 +1394,32 @@ __device__ __forceinline__ T row_dot4(const T* __restrict__ li, const T (*X)[TRS
   if (q + 1 < i) s1 += li[q + 1] * X[q + 1][t];
   if (q + 2 < i) s2 += li[q + 2] * X[q + 2][t];
   return (s0 + s1) + (s2 + s3);
+}
+
+// Forward substitution of one column held in registers (KD rows, fixed at
+// compile time): x_i -= sum_{q<i} l_iq x_q, each row's sum formed as in
+// row_dot4 (partial sum q mod 4, terms in q order, combined (s0 + s1) +
+// (s2 + s3)), so the results equal row_dot4's bit for bit; row i of L11 is
+// read from LDS (the same entry for every lane), with no dependence on x, so
+// its loads run ahead of the arithmetic.
+template <typename T, int KD, int LDL>
+__device__ __forceinline__ void solve_column_regs(const T (*Ls)[LDL], T* col, int64_t lda) {
+  T x[KD];
+#pragma unroll
+  for (int i = 0; i < KD; ++i) x[i] = col[(int64_t)i * lda];
+#pragma unroll
+  for (int i = 1; i < KD; ++i) {
+    T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+#pragma unroll
+    for (int q = 0; q < i; ++q) {
+      if ((q & 3) == 0) s0 += Ls[i][q] * x[q];
+      else if ((q & 3) == 1) s1 += Ls[i][q] * x[q];
+      else if ((q & 3) == 2) s2 += Ls[i][q] * x[q];
+      else s3 += Ls[i][q] * x[q];
+    }
+    x[i] = x[i] - ((s0 + s1) + (s2 + s3));
+    col[(int64_t)i * lda] = x[i];
+  }
 }
 
 // Row interchanges ipiv[kstart + q] (q < kdim, in order) applied to columns
@@ -1390,7 +1433,11 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
                                                             const LuJob* __restrict__ jobs,
                                                             const int32_t* __restrict__ prefix, int n_jobs) {
   static_assert(LU_KMAX <= 2 * TRSM_COLS, "two interchanges per lane");
-  __shared__ T X[TRSM ? LU_KMAX : 1][TRSM_COLS];  // the interchange-only form needs no LDS
+  // The solve form serves the catch-up of a panel inside its outer block, so
+  // kdim = k - K0 <= LU_KMAX - LU_NB (the host plan builds no other).
+  constexpr int KT = LU_KMAX - LU_NB;
+  __shared__ T X[TRSM ? KT : 1][TRSM_COLS];  // the interchange-only form needs no LDS
+  __shared__ T Ls[TRSM ? KT : 1][TRSM ? KT : 1];  // strictly lower L11, staged once
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
@@ -1399,6 +1446,32 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
   const bool live = c < jb.c_hi;  // every lane takes part in the shuffles
   T* a = A + d.a_off;
   const int64_t lda = d.lda;
+  if (TRSM) {
+    // L11 (columns [kstart, kstart + kdim), not touched by the interchanges
+    // below, which act on columns >= kstart + kdim) read row by row with
+    // coalesced loads, all issued before the interchanges' round trips, so
+    // that the solve reads its rows from LDS instead of one global round trip
+    // per row
+    const T* l11 = a + (int64_t)jb.kstart * lda + jb.kstart;
+    static_assert(KT <= 2 * TRSM_COLS, "two L11 columns per lane");
+    for (int i0 = 1; i0 < jb.kdim; i0 += 16) {  // sixteen rows' loads in flight together
+      T g[16][2];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = i0 + u, qq = t + h * TRSM_COLS;
+          g[u][h] = (i < jb.kdim && qq < i) ? l11[(int64_t)i * lda + qq] : (T)0;
+        }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = i0 + u, qq = t + h * TRSM_COLS;
+          if (i < jb.kdim && qq < i) Ls[i][qq] = g[u][h];
+        }
+    }
+  }
   const int32_t* pg = ipiv + d.u_off + jb.kstart;
   const int pv0 = t < jb.kdim ? pg[t] : jb.kstart + t;
   const int pv1 = t + TRSM_COLS < jb.kdim ? pg[t + TRSM_COLS] : jb.kstart + t + TRSM_COLS;
@@ -1413,15 +1486,28 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_swap_trsm(const SubDesc* __res
       a[p * lda + c] = tmp;
     }
   }
-  if (!TRSM || !live) return;
-  // forward substitution by rows: X_i -= sum_{q<i} l_iq X_q, reading row i of
-  // L11 contiguously
-  const T* l = a + (int64_t)jb.kstart * lda + jb.kstart;
-  for (int i = 0; i < jb.kdim; ++i) X[i][t] = a[(jb.kstart + i) * lda + c];
-  for (int i = 1; i < jb.kdim; ++i) {
-    const T x = X[i][t] - row_dot4<T>(l + (int64_t)i * lda, X, i, t);
-    X[i][t] = x;
-    a[(jb.kstart + i) * lda + c] = x;
+  if (!TRSM) return;
+  __syncthreads();  // the staged L11 (one wave: orders the LDS writes before the reads)
+  if (!live) return;
+  // forward substitution by rows: X_i -= sum_{q<i} l_iq X_q, row i of L11
+  // from LDS; the column in registers for the block sizes that occur (kdim
+  // is a multiple of LU_NB), else in LDS
+  if constexpr (TRSM) {
+    T* col = a + (int64_t)jb.kstart * lda + c;
+    if (jb.kdim == 32) {
+      solve_column_regs<T, 32, KT>(Ls, col, lda);
+    } else if (jb.kdim == 64) {
+      solve_column_regs<T, 64, KT>(Ls, col, lda);
+    } else if (jb.kdim == 96) {
+      solve_column_regs<T, 96, KT>(Ls, col, lda);
+    } else {
+      for (int i = 0; i < jb.kdim; ++i) X[i][t] = col[(int64_t)i * lda];
+      for (int i = 1; i < jb.kdim; ++i) {
+        const T x = X[i][t] - row_dot4<T>(&Ls[i][0], X, i, t);
+        X[i][t] = x;
+        col[(int64_t)i * lda] = x;
+      }
+    }
   }
 }
 
