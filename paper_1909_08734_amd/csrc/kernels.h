@@ -1721,30 +1721,85 @@ __global__ __launch_bounds__(256) void k_lu_gemm(const SubDesc* __restrict__ des
 // Lm = I - L11^{-1} (strictly lower; L11^{-1} by forward substitution on the
 // identity, 64 columns per block), written row-major, LU_KMAX x LU_KMAX per
 // subdomain; then U12 -= Lm U12 in place (k_lu_gemm_u), i.e. U12 = L11^{-1} U12.
+// Columns col = BASE + t (t < TRSM_COLS) of L11^{-1}, the column in
+// registers (rows [BASE, LU_KMAX); the rows above BASE are zero for these
+// columns), row i's sum formed as in row_dot4 (partial sum q mod 4, terms in
+// q order): the terms q < BASE it skips are zero, and adding a zero leaves a
+// partial sum's bits unchanged, so the results equal the full solve's. Rows
+// of L11 from LDS. Writes Lm = I - L11^{-1} (strictly lower) as k_lu_linv.
+template <typename T, int BASE>
+__device__ __forceinline__ void linv_columns(const T (*Ls)[LU_KMAX], int col, int kd, T* __restrict__ out) {
+  constexpr int KD = LU_KMAX - BASE;
+  T x[KD];
+#pragma unroll
+  for (int i = BASE; i < LU_KMAX; ++i) {
+    T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+#pragma unroll
+    for (int q = BASE; q < i; ++q) {
+      if ((q & 3) == 0) s0 += Ls[i][q] * x[q - BASE];
+      else if ((q & 3) == 1) s1 += Ls[i][q] * x[q - BASE];
+      else if ((q & 3) == 2) s2 += Ls[i][q] * x[q - BASE];
+      else s3 += Ls[i][q] * x[q - BASE];
+    }
+    x[i - BASE] = (i == col ? (T)1 : (T)0) - ((s0 + s1) + (s2 + s3));
+  }
+#pragma unroll
+  for (int i = 0; i < LU_KMAX; ++i)
+    out[(int64_t)i * LU_KMAX + col] = (i >= BASE && i < kd && col < kd && i > col) ? -x[i >= BASE ? i - BASE : 0] : (T)0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(TRSM_COLS) void k_lu_linv(const SubDesc* __restrict__ desc, const T* __restrict__ A,
                                                        const LuJob* __restrict__ jobs,
                                                        const int32_t* __restrict__ prefix, int n_jobs,
                                                        T* __restrict__ lm, int32_t* __restrict__ n_tiles) {
-  __shared__ T X[LU_KMAX][TRSM_COLS];
+  static_assert(LU_KMAX == 2 * TRSM_COLS, "two column blocks per L11");
   if (blockIdx.x == 0 && threadIdx.x == 0) *n_tiles = 0;  // the trailing-tile list of this outer block starts empty
   const int q = find_job(prefix, n_jobs, blockIdx.x);
   const LuJob jb = jobs[q];
   const SubDesc d = desc[jb.j];
   const int t = threadIdx.x;
-  const int col = (blockIdx.x - prefix[q]) * TRSM_COLS + t;  // < LU_KMAX
+  const int cb = blockIdx.x - prefix[q];  // column block: 0 or 1
+  const int col = cb * TRSM_COLS + t;     // < LU_KMAX
   const int kd = jb.kdim;
   const int64_t lda = d.lda;
-  // forward substitution by rows on the identity column, reading row i of L11
-  // contiguously
   const T* l = A + d.a_off + (int64_t)jb.kstart * lda + jb.kstart;
-  for (int i = 0; i < kd; ++i) {
-    const T x = (i == col ? (T)1 : (T)0) - row_dot4<T>(l + (int64_t)i * lda, X, i, t);
-    X[i][t] = x;
-  }
   T* out = lm + (int64_t)jb.j * LU_KMAX * LU_KMAX;
-  for (int i = 0; i < LU_KMAX; ++i)
-    out[(int64_t)i * LU_KMAX + col] = (i < kd && col < kd && i > col) ? -X[i][t] : (T)0;
+  if constexpr (sizeof(T) == 4) {
+    // FP32: L11 staged (sixteen rows' coalesced loads in flight together),
+    // the column in registers (2x faster; in FP64 the 128-value column needs
+    // more registers than a wave has and the form below is faster)
+    __shared__ T Ls[LU_KMAX][LU_KMAX];  // strictly lower L11 (rows past kdim zero)
+    for (int i0 = 0; i0 < LU_KMAX; i0 += 16) {
+      T g[16][2];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = i0 + u, qq = t + h * TRSM_COLS;
+          g[u][h] = (i < kd && qq < i) ? l[(int64_t)i * lda + qq] : (T)0;
+        }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) Ls[i0 + u][t + h * TRSM_COLS] = g[u][h];
+    }
+    __syncthreads();
+    if (cb == 0)
+      linv_columns<T, 0>(Ls, col, kd, out);
+    else
+      linv_columns<T, TRSM_COLS>(Ls, col, kd, out);
+  } else {
+    // forward substitution by rows on the identity column, reading row i of
+    // L11 contiguously, the column in LDS
+    __shared__ T X[LU_KMAX][TRSM_COLS];
+    for (int i = 0; i < kd; ++i) {
+      const T x = (i == col ? (T)1 : (T)0) - row_dot4<T>(l + (int64_t)i * lda, X, i, t);
+      X[i][t] = x;
+    }
+    for (int i = 0; i < LU_KMAX; ++i)
+      out[(int64_t)i * LU_KMAX + col] = (i < kd && col < kd && i > col) ? -X[i][t] : (T)0;
+  }
 }
 
 // U12 = L11^{-1} U12 for one GEMM_TILE-column tile. When the tile is not all
