@@ -106,8 +106,9 @@ PRECOND_CASES = [
     ("offsphere", 2, "rcb", 5, 1, "ORAS", 2.0, 0.0),
     ("trimesh", 3, "rcb", 8, 2, "ORAS", 3.16, 10.0),
     ("torus", 3, "graph+align", 12, 2, "ORAS", 4.47, 20.0),
-    # many small subdomains: |Sigma~_j| below one 32-row tile of W_j, |Sigma_j| about
-    # one 128-column chunk (FP64) or inside the ragged chunk only (FP32)
+    # many small subdomains: |Sigma~_j| of 94-95 rows (a ragged last 8-row tile of W_j),
+    # |Sigma_j| of 166-232, one 128-column chunk and a ragged one (FP64) or inside the
+    # ragged chunk only (FP32)
     ("sphere", 3, "rcb", 96, 1, "ORAS", 3.16, 0.0),
 ]
 
