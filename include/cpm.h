@@ -251,16 +251,23 @@ int cpm_factor_flops(const cpm_ctx* ctx, double* flops);
 
 /*
  * Tiling of the apply for several right-hand sides at once (the lockstep
- * batches of cpm_solve_device): rows of W_j per wave and 16-byte chunks in
- * flight per row, 0: 2, 2; 1: 4, 1; 2: 4, 2 (FP64 default after cpm_factor);
- * 3: 8, 1 (FP32 default). Every tiling
- * forms each right-hand side's sums as the single apply does, so results do
- * not depend on it. cpm_autotune_multi times every tiling `reps` times on the
- * resident factors with the widest batch that fits (ESTATE when none does),
- * keeps the fastest, returns it in *best and the CPM_MULTI_TILINGS average
- * apply times in ms (both may be NULL); kernel timers are left unchanged.
+ * batches of cpm_solve_device). A tiling names rows of W_j per wave, 16-byte
+ * chunks in flight per row, whether each wave alternates two such register
+ * sets (the loads of the next chunks issued before the products of the
+ * current ones), and the apply blocks planned per resident block slot:
+ *   0: 8, 1, -, 1   1: 8, 1, -, 2 (FP32 default after cpm_factor)   2: 8, 1, -, 4
+ *   3: 4, 2, two sets, 1   4: 4, 2, two sets, 2   5: 4, 2, two sets, 4 (FP64 default)
+ *   6: 4, 1, two sets, 2   7: 4, 2, -, 2
+ * Every tiling forms each right-hand side's sums as the single apply does, so
+ * results do not depend on it. cpm_set_multi_tiling needs resident factors
+ * (ESTATE before cpm_factor; a new factorisation restores the default) and
+ * re-plans the blocks. cpm_autotune_multi times every tiling `reps` times on
+ * the resident factors with the widest batch that fits (ESTATE when none
+ * does), keeps the fastest, returns it in *best and the CPM_MULTI_TILINGS
+ * average apply times in ms (both may be NULL); kernel timers are left
+ * unchanged.
  */
-#define CPM_MULTI_TILINGS 4
+#define CPM_MULTI_TILINGS 8
 int cpm_set_multi_tiling(cpm_ctx* ctx, int tiling);
 int cpm_multi_tiling(const cpm_ctx* ctx);
 int cpm_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms);

@@ -25,7 +25,7 @@ FP64, FP32 = 0, 1
 PART_OCTANT, PART_RCB, PART_GRAPH = 0, 1, 2
 PART_ALIGN = 16
 PRECOND_TILINGS = 8  # CPM_PRECOND_TILINGS
-MULTI_TILINGS = 4  # CPM_MULTI_TILINGS
+MULTI_TILINGS = 8  # CPM_MULTI_TILINGS
 TIMER_PRECOND, TIMER_EXTEND, TIMER_STENCIL, TIMER_LU_GEMM, TIMER_KRYLOV, TIMER_UPDATE = 0, 1, 2, 3, 4, 5
 PHASES = ("precond", "operator", "orthogonalisation", "update")  # cpm_solve_info.phase_ms
 

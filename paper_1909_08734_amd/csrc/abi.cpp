@@ -495,7 +495,8 @@ int cpm_autotune_factor(cpm_ctx* ctx, int prec, int* best, double* ms) {
 
 int cpm_set_multi_tiling(cpm_ctx* ctx, int tiling) {
   if (!ctx) return CPM_EINVAL;
-  return cpm::dev_set_multi_tiling(ctx, tiling);
+  if (ctx->state < 4) return fail(ctx, CPM_ESTATE, "set_multi_tiling: factor first");
+  return guarded(ctx, [&]() -> int { return cpm::dev_set_multi_tiling(ctx, tiling); });
 }
 
 int cpm_multi_tiling(const cpm_ctx* ctx) { return ctx ? ctx->dev.multi_tiling : 0; }

@@ -143,6 +143,9 @@ struct Dev {
   int chunk = 0;                // 0: v|Sigma_j staged whole; else columns per pass (chunked apply)
   int tiling = 0;               // tiling of the unchunked apply (see dev_set_tiling)
   int multi_tiling = 0;         // tiling of the several-right-hand-side apply
+  SubDesc* mdesc = nullptr;     // its plan: descriptors with their own block fields
+  int32_t* mblk_sub = nullptr;  // its block -> subdomain table
+  int m_n_blocks = 0;
   int factor_tile = 0;          // rows of the LU trailing-update tile: 0 = tuned (or 128), 64 or 128
   int factor_tile_used = 0;     // the tile of the resident factors
   double factor_flops = 0;      // matrix-core flops of the last factorisation's Schur-complement updates

@@ -236,6 +236,9 @@ void dev_free_factor(cpm_ctx* ctx) {
   drop_graphs(d);
   dfree(d.desc);
   dfree(d.blk_sub);
+  dfree(d.mdesc);
+  dfree(d.mblk_sub);
+  d.m_n_blocks = 0;
   dfree(d.sig_idx);
   dfree(d.tilde_idx);
   pool_free(d.W);
@@ -1148,7 +1151,7 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
   dv.hdesc = P.desc;
   dv.factor_tile_used = tile_r;
   dv.tiling = 0;
-  dv.multi_tiling = prec == CPM_FP64 ? 2 : 3;  // the measured best at the benchmark size
+  dv.multi_tiling = prec == CPM_FP64 ? 5 : 1;  // the measured best at the benchmark size (planned by dev_factor)
   dv.sig_idx = dU;
   dv.tilde_idx = dtidx;
   dv.blk_sub = dblk;
@@ -1165,6 +1168,8 @@ int run_factor(cpm_ctx* ctx, const FactorPlan& P, int prec, int tile_r) {
 }
 
 }  // namespace
+
+int plan_multi(cpm_ctx* ctx);
 
 int dev_factor(cpm_ctx* ctx, int prec) {
   HIPCHK(hipSetDevice(ctx->device));
@@ -1204,7 +1209,9 @@ int dev_factor(cpm_ctx* ctx, int prec) {
   make_plan(ctx, P, dv.chunk > 0 ? n_cu * per_cu : n_cu * per_cu * kTilings[0].over2 / 2,
             dv.chunk > 0 ? PRECOND_RPB_MAX : 0);
   const int tile_r = dv.factor_tile ? dv.factor_tile : tuned_factor_tile(ctx, prec);
-  return prec == CPM_FP64 ? run_factor<double>(ctx, P, prec, tile_r) : run_factor<float>(ctx, P, prec, tile_r);
+  int rc = prec == CPM_FP64 ? run_factor<double>(ctx, P, prec, tile_r) : run_factor<float>(ctx, P, prec, tile_r);
+  if (rc == CPM_OK) rc = plan_multi(ctx);
+  return rc;
 }
 
 // Rows of the trailing-update tile chosen by cpm_autotune_factor, per device
@@ -1699,43 +1706,117 @@ int dev_batch_width(cpm_ctx* ctx, int nrhs) {
   return 0;
 }
 
-// Tilings of the several-right-hand-side apply (rows per wave, chunks in
-// flight per row); every one gives the single apply's sums bit for bit.
-// Tiling t = (rows per wave, chunks in flight): 0 = (2, 2), 1 = (4, 1),
-// 2 = (4, 2), 3 = (8, 1).
+// Tilings of the several-right-hand-side apply; every one gives the single
+// apply's sums bit for bit. Each names rows per wave, chunks in flight per
+// row, whether two register sets alternate (the next group's loads issued
+// before the current group's products), and the blocks planned per resident
+// block slot. One block holds every vector of the batch in LDS, so few fit on
+// a CU and each block's gather of v|Sigma_j runs with little else beside it:
+// fewer, larger blocks than the single apply's plan pay it less often.
+struct MultiTiling {
+  int rpw, unr;
+  bool pipe;
+  int over;
+};
 constexpr int N_MULTI_TILINGS = CPM_MULTI_TILINGS;
+constexpr MultiTiling kMultiTilings[N_MULTI_TILINGS] = {{8, 1, false, 1}, {8, 1, false, 2}, {8, 1, false, 4},
+                                                        {4, 2, true, 1},  {4, 2, true, 2},  {4, 2, true, 4},
+                                                        {4, 1, true, 2},  {4, 2, false, 2}};
 
-template <typename T, int NB, int RPW, int UNR>
-static void launch_multi_t(cpm_ctx* ctx, size_t lds, const double* v, int64_t v_stride, const double* scale,
-                           int64_t scale_stride, double* z, int64_t z_stride) {
-  Dev& d = ctx->dev;
-  auto fn = k_precond_multi<T, NB, RPW, UNR>;
-  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  launch(ctx, TIMER_PRECOND, fn, dim3(d.n_blocks), dim3(PRECOND_THREADS), lds, (const SubDesc*)d.desc,
-         (const int32_t*)d.blk_sub, (const int32_t*)d.sig_idx, (const int32_t*)d.tilde_idx, (const T*)d.W, v, v_stride,
-         scale, scale_stride, z, z_stride);
+// Calls f with the kernel of tiling t.
+template <typename T, int NB, int I, class F>
+static void multi_fn_at(F&& f) {
+  constexpr MultiTiling m = kMultiTilings[I];
+  f(k_precond_multi<T, NB, m.rpw, m.unr, m.pipe>);
+}
+template <typename T, int NB, class F>
+static void with_multi_fn(int t, F&& f) {
+  static_assert(N_MULTI_TILINGS == 8, "one case per multi tiling");
+  switch (t) {
+    case 0: multi_fn_at<T, NB, 0>(f); break;
+    case 1: multi_fn_at<T, NB, 1>(f); break;
+    case 2: multi_fn_at<T, NB, 2>(f); break;
+    case 3: multi_fn_at<T, NB, 3>(f); break;
+    case 4: multi_fn_at<T, NB, 4>(f); break;
+    case 5: multi_fn_at<T, NB, 5>(f); break;
+    case 6: multi_fn_at<T, NB, 6>(f); break;
+    default: multi_fn_at<T, NB, 7>(f); break;
+  }
 }
 
 template <typename T, int NB>
-static void launch_multi_nb(cpm_ctx* ctx, size_t lds, const double* v, int64_t v_stride, const double* scale,
-                            int64_t scale_stride, double* z, int64_t z_stride) {
-  switch (ctx->dev.multi_tiling) {
-    case 1: launch_multi_t<T, NB, 4, 1>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
-    case 2: launch_multi_t<T, NB, 4, 2>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
-    case 3: launch_multi_t<T, NB, 8, 1>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
-    default: launch_multi_t<T, NB, 2, 2>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride); break;
-  }
+static void launch_multi_typed(cpm_ctx* ctx, const double* v, int64_t v_stride, const double* scale,
+                               int64_t scale_stride, double* z, int64_t z_stride) {
+  Dev& d = ctx->dev;
+  const size_t lds = (size_t)NB * d.max_m * sizeof(double);
+  with_multi_fn<T, NB>(d.multi_tiling, [&](auto fn) {
+    if (lds > 64 * 1024) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    launch(ctx, TIMER_PRECOND, fn, dim3(d.m_n_blocks), dim3(PRECOND_THREADS), lds, (const SubDesc*)d.mdesc,
+           (const int32_t*)d.mblk_sub, (const int32_t*)d.sig_idx, (const int32_t*)d.tilde_idx, (const T*)d.W, v,
+           v_stride, scale, scale_stride, z, z_stride);
+  });
 }
 
 template <int NB>
 static void launch_precond_multi(cpm_ctx* ctx, const double* v, int64_t v_stride, const double* scale,
                                  int64_t scale_stride, double* z, int64_t z_stride) {
-  Dev& d = ctx->dev;
-  const size_t lds = (size_t)NB * d.max_m * sizeof(double);
-  if (d.prec == CPM_FP64)
-    launch_multi_nb<double, NB>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride);
+  if (ctx->dev.prec == CPM_FP64)
+    launch_multi_typed<double, NB>(ctx, v, v_stride, scale, scale_stride, z, z_stride);
   else
-    launch_multi_nb<float, NB>(ctx, lds, v, v_stride, scale, scale_stride, z, z_stride);
+    launch_multi_typed<float, NB>(ctx, v, v_stride, scale, scale_stride, z, z_stride);
+}
+
+// Plan of the several-right-hand-side apply for the current multi tiling:
+// n_cu x (blocks of the widest batch that fit on a CU) x over blocks,
+// apportioned to subdomains by W bytes and cut into whole tiles as the single
+// apply's. (Rounding rows per block up to whole passes of the eight waves
+// measured slower: it leaves fewer blocks than slots x over, so the CUs run
+// uneven numbers of them.) No plan (and no batched apply) when no batch of
+// two fits.
+int plan_multi(cpm_ctx* ctx) {
+  Dev& dv = ctx->dev;
+  dfree(dv.mdesc);
+  dfree(dv.mblk_sub);
+  dv.m_n_blocks = 0;
+  const int nb = dev_batch_width(ctx, 4);
+  if (nb < 2) return CPM_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  const MultiTiling& mt = kMultiTilings[dv.multi_tiling];
+  const size_t lds = (size_t)nb * dv.max_m * sizeof(double);
+  int n_cu = 0, per_cu = 0;
+  HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  hipError_t e = hipSuccess;
+  auto occ = [&](auto fn) {
+    if (lds > 64 * 1024) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PRECOND_THREADS, lds);
+  };
+  if (dv.prec == CPM_FP64)
+    nb == 4 ? with_multi_fn<double, 4>(dv.multi_tiling, occ) : with_multi_fn<double, 2>(dv.multi_tiling, occ);
+  else
+    nb == 4 ? with_multi_fn<float, 4>(dv.multi_tiling, occ) : with_multi_fn<float, 2>(dv.multi_tiling, occ);
+  HIPCHK(e);
+  per_cu = std::max(1, per_cu);
+  const std::vector<int> want = apportion_blocks(ctx->dec, n_cu * per_cu * mt.over);
+  std::vector<SubDesc> hd = dv.hdesc;
+  std::vector<int32_t> blk_sub;
+  int32_t blk = 0;
+  for (int j = 0; j < ctx->dec.n_sub; ++j) {
+    SubDesc& d = hd[j];
+    d.rpb = rows_per_block(d.t, want[j]);
+    const int n = (d.t + d.rpb - 1) / d.rpb;
+    d.blk_off = blk;
+    for (int q = 0; q < n; ++q) blk_sub.push_back(j);
+    blk += n;
+  }
+  int rc = upload(ctx, &dv.mdesc, hd);
+  if (rc == CPM_OK) rc = upload(ctx, &dv.mblk_sub, blk_sub);
+  if (rc != CPM_OK) {
+    dfree(dv.mdesc);
+    dfree(dv.mblk_sub);
+    return rc;
+  }
+  dv.m_n_blocks = blk;
+  return CPM_OK;
 }
 
 int dev_solve_batch(cpm_ctx* ctx, const double* f, double* u, int nb, double tol, int max_iter, int m,
@@ -2202,8 +2283,14 @@ int dev_set_multi_tiling(cpm_ctx* ctx, int t) {
     ctx->err = "multi tiling out of range";
     return CPM_EINVAL;
   }
+  if (ctx->dev.prec < 0) {
+    ctx->err = "multi tiling: factor first";
+    return CPM_ESTATE;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->dev.multi_tiling = t;
-  return CPM_OK;
+  return plan_multi(ctx);
 }
 
 int dev_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms) {
@@ -2241,8 +2328,12 @@ int dev_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms) {
   };
   int arg = 0;
   double tbest = 0.0;
-  for (int t = 0; t < N_MULTI_TILINGS; ++t) {
+  int rc = CPM_OK;
+  for (int t = 0; t < N_MULTI_TILINGS && rc == CPM_OK; ++t) {
+    hipStreamSynchronize(ctx->stream);  // the previous plan's launches are done
     dv.multi_tiling = t;
+    rc = plan_multi(ctx);
+    if (rc != CPM_OK) break;
     tm.on = false;
     pass();
     timer_harvest(ctx);
@@ -2268,6 +2359,8 @@ int dev_autotune_multi(cpm_ctx* ctx, int reps, int* best, double* ms) {
   dfree(v);
   dfree(z);
   dv.multi_tiling = arg;
+  if (rc == CPM_OK) rc = plan_multi(ctx);
+  if (rc != CPM_OK) return rc;
   if (best) *best = arg;
   return CPM_OK;
 }

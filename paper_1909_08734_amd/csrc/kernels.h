@@ -508,18 +508,23 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
 // right-hand side the sums are formed in the order of k_precond, so a batched
 // apply equals NB single applies bit for bit.
 // RPW rows per wave and UNR 16-byte chunks in flight per row are tunable as
-// in k_precond (the sums do not depend on them).
+// in k_precond (the sums do not depend on them). With PIPE the full chunks go
+// through two register sets of UNR chunks instead: the loads of the next
+// group are issued before the products of the current one, so a wave's
+// arithmetic (NB products per element) overlaps its next loads even when few
+// waves fit beside the staged vectors.
 // Register budget (waves per SIMD) without spills: accumulators, loads in
 // flight and the v values of a chunk for every right-hand side.
 // (Values from the compiler's register counts for each instance.)
-constexpr int multi_waves(int nb, int vn, int rpw, int unr) {
-  return (rpw == 2 && unr == 2) ? (nb >= 4 ? (vn >= 4 ? 4 : 6) : (vn >= 4 ? 7 : 8))
+constexpr int multi_waves(int nb, int vn, int rpw, int unr, bool pipe) {
+  return pipe ? (nb >= 4 || unr >= 2 ? 2 : 3)
+         : (rpw == 2 && unr == 2) ? (nb >= 4 ? (vn >= 4 ? 4 : 6) : (vn >= 4 ? 7 : 8))
          : vn >= 4 ? (rpw * unr <= 4 ? 4 : rpw == 8 ? 2 : 3)
                    : (rpw * unr <= 4 ? (nb >= 4 ? 4 : 5) : (nb >= 4 && rpw == 8) ? 3 : 4);
 }
 
-template <typename T, int NB, int MULTI_RPW, int UNR>
-__global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n, MULTI_RPW, UNR)) void k_precond_multi(const SubDesc* __restrict__ desc,
+template <typename T, int NB, int MULTI_RPW, int UNR, bool PIPE = false>
+__global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n, MULTI_RPW, UNR, PIPE)) void k_precond_multi(const SubDesc* __restrict__ desc,
                                                                    const int32_t* __restrict__ blk_sub,
                                                                    const int32_t* __restrict__ sig_idx,
                                                                    const int32_t* __restrict__ tilde_idx,
@@ -581,8 +586,43 @@ __global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n, MULTI
       for (int q = 0; q < NB; ++q) acc[i][q] = 0.0;
     }
     int k = 0;
+    if constexpr (PIPE) {  // groups of UNR chunks, two groups held
+      VT wa[UNR][MULTI_RPW], wb[UNR][MULTI_RPW];
+      auto fetch = [&](VT(&w)[UNR][MULTI_RPW], int kk) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int i = 0; i < MULTI_RPW; ++i)
+            w[u][i] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(wf + (kk + u) * KS + ro[i] * CW));
+      };
+      auto madd = [&](const VT(&w)[UNR][MULTI_RPW], int kk) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int e = 0; e < VN; ++e)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              const double xv = vl[q * d.ldw + (kk + u) * CW + e];
+#pragma unroll
+              for (int i = 0; i < MULTI_RPW; ++i) acc[i][q] += (double)w[u][i][e] * xv;
+            }
+      };
+      const int kg = nfull / UNR * UNR;  // chunks in whole groups; the rest below
+      if (kg > 0) fetch(wa, 0);
 #pragma unroll 1
-    for (; k + UNR <= nfull; k += UNR) {
+      for (; k + 2 * UNR <= kg; k += 2 * UNR) {  // wa holds the group at k
+        fetch(wb, k + UNR);
+        madd(wa, k);
+        if (k + 2 * UNR < kg) fetch(wa, k + 2 * UNR);
+        madd(wb, k + UNR);
+      }
+      if (k < kg) {  // odd number of groups: the last is in wa
+        madd(wa, k);
+        k += UNR;
+      }
+    }
+#pragma unroll 1
+    for (; !PIPE && k + UNR <= nfull; k += UNR) {
       VT wv[UNR][MULTI_RPW];
 #pragma unroll
       for (int u = 0; u < UNR; ++u)

@@ -86,6 +86,9 @@ def test_failed_band_build_keeps_state_and_operator_constant_host_only():
     np.testing.assert_array_equal(ctx.band_arrays(3)["lin"], lin)
     assert ctx.partition_info()[0] == 8
     ctx.footprint_estimate(P.FP32, 30)  # still partitioned
+    with pytest.raises(P.CpmError) as e:  # the batched apply's plan needs factors
+        ctx.set_multi_tiling(1)
+    assert e.value.code == P.ESTATE
     ctx.set_operator_c(2.0)
     assert ctx.partition_info()[0] == 8 and ctx.factor_c() == 0.0
     for bad in (0.0, -1.0, float("nan")):

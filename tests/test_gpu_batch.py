@@ -103,3 +103,37 @@ def test_batched_solve_at_benchmark_size_meets_tolerance():
         assert np.linalg.norm(F[q] - A @ U1[q]) / np.linalg.norm(F[q]) <= 1.05e-8
     assert t_batch < 0.7 * t_single
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
+def test_every_multi_tiling_equals_separate_solves(prec):
+    """Each tiling of the batched apply (rows per wave, chunks in flight, and
+    the double-buffered forms) gives the separate solves' bits. At h = 0.05
+    with 5 parts every W_j has many full 16-byte-per-lane chunks, and both the
+    chunk counts and the counts of pairs of chunks are odd for some subdomains
+    and even for others, so the double-buffered loops (groups of one and of
+    two chunks) run every ending."""
+    ctx = _ctx(0.05, 5, prec)
+    cw = 128 if prec == P.FP64 else 256
+    nfull = [((len(ctx.subdomain(j)["sigma"]) + 7) // 8 * 8) // cw for j in range(5)]
+    say("multi tilings", prec, "full chunks per subdomain", nfull)
+    assert min(nfull) >= 4
+    assert {n % 2 for n in nfull} == {0, 1} and {n // 2 % 2 for n in nfull} == {0, 1}
+    na = ctx.band_sizes()[0]
+    cp = ctx.band_arrays(3)["cp"][:na]
+    F = _rhs(cp, 7)
+    kw = dict(tol=1e-10, max_iter=500, restart=30)
+    U1, info1 = _single(ctx, F, **kw)
+    Fd = torch.from_numpy(F).cuda()
+    for t in range(P.MULTI_TILINGS):
+        ctx.set_multi_tiling(t)
+        Ud = torch.zeros_like(Fd)
+        info, rc = ctx.solve_device(Fd, Ud, **kw)
+        say("  tiling", t, "rc", rc)
+        np.testing.assert_array_equal(Ud.cpu().numpy(), U1)
+        assert [(i["iters"], i["status"], i["cycles"]) for i in info] == info1
+    best, ms = ctx.autotune_multi(reps=2)
+    say("  autotune", best, ["%.3f" % m for m in ms])
+    assert 0 <= best < P.MULTI_TILINGS and ctx.multi_tiling() == best
+    assert len(ms) == P.MULTI_TILINGS and all(m > 0 for m in ms)
+    ctx.close()
