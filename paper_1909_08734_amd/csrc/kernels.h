@@ -19,6 +19,44 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave sums of K values per lane (K a power of two up to 64) with wave_sum's
+// pairing: at each step o = 32, 16, ..., 1 the partial sums of lanes l and
+// l ^ o are added, so every result equals wave_sum of that value bit for bit
+// (addition is commutative). Instead of reducing each value whole, a step
+// while more than one value is left splits them between the two lanes of a
+// pair (the lane with bit o set keeps the upper half), so the K sums take
+// K - 1 + (6 - log2 K) exchanges instead of 6 K. On return lane l holds the
+// sum of value l >> (6 - log2 K), as do the other lanes of its group of
+// 2^(6 - log2 K).
+// One step (lane offset O, N values left), then the rest.
+template <int N, int O, int K>
+__device__ __forceinline__ void wave_sum_step(double (&v)[K], int lane) {
+  if constexpr (O > 0) {
+    if constexpr (N > 1) {
+      const bool hi = (lane & O) != 0;
+#pragma unroll
+      for (int k = 0; k < N / 2; ++k) {
+        const double send = hi ? v[k] : v[k + N / 2];
+        const double keep = hi ? v[k + N / 2] : v[k];
+        v[k] = keep + __shfl_xor(send, O, 64);
+      }
+      wave_sum_step<N / 2, O / 2, K>(v, lane);
+    } else {
+      v[0] += __shfl_xor(v[0], O, 64);
+      wave_sum_step<1, O / 2, K>(v, lane);
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ double wave_sum_many(double (&v)[K], int lane) {
+  static_assert(K >= 1 && K <= 64 && (K & (K - 1)) == 0, "K: a power of two up to 64");
+  wave_sum_step<K, 32, K>(v, lane);
+  return v[0];
+}
+
+constexpr int ilog2(int k) { return k <= 1 ? 0 : 1 + ilog2(k / 2); }
+
 // Sum of one value per thread over a 256-thread block (fixed order).
 __device__ __forceinline__ double block_sum256(double v, double* red) {
   v = wave_sum(v);
@@ -520,7 +558,7 @@ constexpr int multi_waves(int nb, int vn, int rpw, int unr, bool pipe) {
   return pipe ? (nb >= 4 || unr >= 2 ? 2 : 3)
          : (rpw == 2 && unr == 2) ? (nb >= 4 ? (vn >= 4 ? 4 : 6) : (vn >= 4 ? 7 : 8))
          : vn >= 4 ? (rpw * unr <= 4 ? 4 : rpw == 8 ? 2 : 3)
-                   : (rpw * unr <= 4 ? (nb >= 4 ? 4 : 5) : (nb >= 4 && rpw == 8) ? 3 : 4);
+                   : (rpw * unr <= 4 ? (nb >= 4 ? 4 : 5) : rpw == 8 ? (nb >= 4 ? 2 : 3) : 4);
 }
 
 template <typename T, int NB, int MULTI_RPW, int UNR, bool PIPE = false>
@@ -669,13 +707,19 @@ __global__ __launch_bounds__(PRECOND_THREADS, multi_waves(NB, VecOf<T>::n, MULTI
           for (int i = 0; i < MULTI_RPW; ++i) acc[i][q] += (double)wv[i][e] * xv;
         }
     }
+    // the RPW x NB row sums, each as wave_sum forms it, in groups of up to 8
+    // (beside the second register set 4, or one at a time for 4-byte W, so
+    // that no exchange temporary spills); one lane writes each
+    constexpr int K = MULTI_RPW * NB, G = K < 8 ? K : !PIPE ? 8 : VN >= 4 ? 1 : 4, LG = ilog2(G);
 #pragma unroll
-    for (int i = 0; i < MULTI_RPW; ++i)
+    for (int g = 0; g < K; g += G) {
+      double red[G];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const double s = wave_sum(acc[i][q]);
-        if (lane == 0 && r0 + i < r_end) z[q * z_stride + tilde_idx[d.t_off + r0 + i]] = s;
-      }
+      for (int k = 0; k < G; ++k) red[k] = acc[(g + k) / NB][(g + k) % NB];
+      const double s = wave_sum_many<G>(red, lane);
+      const int kv = g + (lane >> (6 - LG)), i = kv / NB, q = kv % NB;
+      if ((lane & ((1 << (6 - LG)) - 1)) == 0 && r0 + i < r_end) z[q * z_stride + tilde_idx[d.t_off + r0 + i]] = s;
+    }
   }
 }
 
