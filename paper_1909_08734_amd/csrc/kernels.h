@@ -2069,36 +2069,6 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NC], int j0, 
   __syncthreads();
 }
 
-// Wave sums of 32 per-lane values by recursive halving: at each of five steps
-// a lane keeps half of its live values and adds the partner lane's copy of
-// that half (lane bit 5 picks column bit 4, ..., lane bit 1 picks column bit
-// 0), then the pair (lane, lane ^ 1) is added. Lanes with bit 0 clear end up
-// holding the wave sum of column transpose_col(lane): 32 shuffles instead of
-// 6 per column.
-__device__ __forceinline__ double transpose_sum32(double (&a)[32], int lane) {
-#pragma unroll
-  for (int s = 0; s < 5; ++s) {
-    const int half = 16 >> s;
-    const int off = 32 >> s;
-    const bool hi = (lane & off) != 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (i < half) {
-        const double lo_v = a[i], hi_v = a[i + half];
-        const double send = hi ? lo_v : hi_v;
-        const double keep = hi ? hi_v : lo_v;
-        a[i] = keep + __shfl_xor(send, off, 64);
-      }
-    }
-  }
-  return a[0] + __shfl_xor(a[0], 1, 64);
-}
-
-__device__ __forceinline__ int transpose_col(int lane) {
-  return (((lane >> 5) & 1) << 4) | (((lane >> 4) & 1) << 3) | (((lane >> 3) & 1) << 2) |
-         (((lane >> 2) & 1) << 1) | ((lane >> 1) & 1);
-}
-
 // block_partials for 32 accumulators per thread (acc is consumed).
 __device__ __forceinline__ void block_partials32(double (&acc)[32], int j0, int nc, double* __restrict__ part) {
   if (nc <= 2) {
@@ -2107,8 +2077,8 @@ __device__ __forceinline__ void block_partials32(double (&acc)[32], int j0, int 
   }
   __shared__ double red[RED_THREADS / 64][32];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double t = transpose_sum32(acc, lane);
-  if ((lane & 1) == 0) red[wave][transpose_col(lane)] = t;
+  const double t = wave_sum_many<32>(acc, lane);  // lanes 2c and 2c + 1: column c
+  if ((lane & 1) == 0) red[wave][lane >> 1] = t;
   __syncthreads();
   if (threadIdx.x < nc) {
     const int u = threadIdx.x;
