@@ -368,6 +368,12 @@ def _run_gpu(args, wl, torch, P):
                 # the same K right-hand sides solved in lockstep batches that share
                 # each pass over the factors (results equal the separate solves)
                 nb = 4 if args.steps >= 4 else 2
+                # the batched apply's tiling and block plan, timed on these factors
+                # (none when no batch of two vectors fits in LDS)
+                try:
+                    multi_tiling, multi_ms = ctx.autotune_multi(reps=5)
+                except P.CpmError:
+                    multi_tiling, multi_ms = None, None
                 ctx.solve_device(f_dev[args.warmup:args.warmup + nb], u_dev[args.warmup:args.warmup + nb],
                                  tol=tol, max_iter=3000, restart=RESTART)  # warm-up (workspace)
                 torch.cuda.synchronize()
@@ -380,6 +386,7 @@ def _run_gpu(args, wl, torch, P):
                     raise RuntimeError(f"batched solve did not converge: {binfo}")
                 r["batched"] = {"rhs_per_call": args.steps, "solves_per_s": args.steps / wb,
                                 "ms_per_solve": 1e3 * wb / args.steps,
+                                "multi_tiling": multi_tiling, "multi_tiling_ms": multi_ms,
                                 "iters_mean": float(np.mean([i["iters"] for i in binfo]))}
             if a_name == wl["alphas"][0][0] and args.restart60 and RESTART != 60:
                 # longer restart cycles: fewer iterations, same factors
