@@ -19,16 +19,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Wave sums of K values per lane (K a power of two up to 64) with wave_sum's
-// pairing: at each step o = 32, 16, ..., 1 the partial sums of lanes l and
-// l ^ o are added, so every result equals wave_sum of that value bit for bit
-// (addition is commutative). Instead of reducing each value whole, a step
-// while more than one value is left splits them between the two lanes of a
-// pair (the lane with bit o set keeps the upper half), so the K sums take
-// K - 1 + (6 - log2 K) exchanges instead of 6 K. On return lane l holds the
-// sum of value l >> (6 - log2 K), as do the other lanes of its group of
-// 2^(6 - log2 K).
-// One step (lane offset O, N values left), then the rest.
+// One step of wave_sum_many (lane offset O, N values left), then the rest.
 template <int N, int O, int K>
 __device__ __forceinline__ void wave_sum_step(double (&v)[K], int lane) {
   if constexpr (O > 0) {
@@ -48,6 +39,15 @@ __device__ __forceinline__ void wave_sum_step(double (&v)[K], int lane) {
   }
 }
 
+// Wave sums of K values per lane (K a power of two up to 64) with wave_sum's
+// pairing: at each step o = 32, 16, ..., 1 the partial sums of lanes l and
+// l ^ o are added, so every result equals wave_sum of that value bit for bit
+// (addition is commutative). Instead of reducing each value whole, a step
+// while more than one value is left splits them between the two lanes of a
+// pair (the lane with bit o set keeps the upper half), so the K sums take
+// K - 1 + (6 - log2 K) exchanges instead of 6 K. On return lane l holds the
+// sum of value l >> (6 - log2 K), as do the other lanes of its group of
+// 2^(6 - log2 K). v is consumed.
 template <int K>
 __device__ __forceinline__ double wave_sum_many(double (&v)[K], int lane) {
   static_assert(K >= 1 && K <= 64 && (K & (K - 1)) == 0, "K: a power of two up to 64");
@@ -543,14 +543,16 @@ __global__ __launch_bounds__(PRECOND_THREADS, 8) void k_precond_chunked(const Su
 // Several right-hand sides per pass over W: v_q|Sigma_j (q < NB) staged in LDS
 // one after the other (each read like the single apply's, without extra bank
 // conflicts), each W element multiplied by all of them. For every
-// right-hand side the sums are formed in the order of k_precond, so a batched
-// apply equals NB single applies bit for bit.
+// right-hand side the sums are formed in the order of k_precond (the row sums
+// by wave_sum_many, which pairs lanes as wave_sum does), so a batched apply
+// equals NB single applies bit for bit. desc and blk_sub are the batched
+// apply's own block plan (fewer, larger blocks than the single apply's).
 // RPW rows per wave and UNR 16-byte chunks in flight per row are tunable as
 // in k_precond (the sums do not depend on them). With PIPE the full chunks go
 // through two register sets of UNR chunks instead: the loads of the next
-// group are issued before the products of the current one, so a wave's
-// arithmetic (NB products per element) overlaps its next loads even when few
-// waves fit beside the staged vectors.
+// group are issued before the products of the current one (one more form
+// for the autotuner; with few waves beside the staged vectors it measured
+// about as fast as one register set).
 // Register budget (waves per SIMD) without spills: accumulators, loads in
 // flight and the v values of a chunk for every right-hand side.
 // (Values from the compiler's register counts for each instance.)
